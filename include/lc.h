@@ -1,0 +1,196 @@
+/*
+ * lc.h -- C ABI of the MI355X loop-cluster library.
+ *
+ * One continuous-time loop-cluster Monte Carlo update of the world lines of
+ * the antiferromagnetic Heisenberg chain H = J sum_j S_j . S_{j+1} (J = 1,
+ * periodic boundaries), after Todo, Matsuo and Shitara, "Parallel loop
+ * cluster quantum Monte Carlo simulation of quantum magnets based on global
+ * union-find graph algorithm" (arXiv:1810.07485): Sec. 2 (labeling, cluster
+ * flip, the continuous-time steps 1-8, union-find), Sec. 3.2 (lock-free
+ * union-find on a shared forest) and Sec. 5 (spin S by 2S subspins per spin
+ * and (2S)^2 sub-bonds per bond).  Every step runs in HIP kernels on one
+ * gfx950 GPU; the host only launches them and reads back a few counters.
+ *
+ * Conventions
+ *  - Every function returns LC_OK (0) or a negative LC_E* code and never
+ *    throws.  A failed call leaves the chain unchanged: a sweep is
+ *    transactional (the world lines are double-buffered and only the last
+ *    kernel of a successful sweep makes the new buffer current).
+ *  - Spin S is passed as a double: 0.5, 1.0, 1.5, ... 4.0 (2S integer in 1..8).
+ *    L must be even and >= 4; beta must be finite, > 0 and <= 8 * 2^32.
+ *  - Imaginary time is a 64-bit fixed-point fraction of beta:
+ *    tau = beta * t / 2^64.
+ *  - Subspin (j, a) of spin j has index 2S j + a; sub-bond
+ *    ((2S j) + a) 2S + c joins (j, a) with (j+1 mod L, c).  For S = 1/2
+ *    this is bond j joining spins j and j+1.
+ *  - Device memory comes from the caller's allocator when one is given (the
+ *    Python binding passes PyTorch's caching allocator), otherwise from
+ *    hipMalloc.  The library owns what it allocates and frees it in
+ *    lc_free / lc_batch_free.  Host buffers are the caller's.
+ *  - Work is queued on the caller's HIP stream (NULL = the null stream) and
+ *    every call returns after that stream has finished it.
+ *  - Calls on one chain or batch must not overlap; different chains may be
+ *    driven from different threads when they use different streams.
+ */
+#ifndef LC_H
+#define LC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LC_OK 0
+#define LC_EINVAL -1     /* bad argument (NULL pointer, L odd or < 4, 2S not in 1..8, bad beta) */
+#define LC_ENOMEM -2     /* an allocation failed; the object is unchanged */
+#define LC_ETOOLARGE -3  /* footprint exceeds the device memory */
+#define LC_ECAPACITY -4  /* a caller buffer is too small; the needed size is written back */
+#define LC_EDEVICE -5    /* a HIP runtime error */
+#define LC_ESTATE -6     /* call not valid in this state (e.g. chain owned by a batch) */
+
+typedef struct lc_chain lc_chain;
+typedef struct lc_batch lc_batch;
+
+/* Device allocator supplied by the caller.  alloc returns device memory of at
+ * least `bytes` bytes usable on `stream`, or NULL; free releases it. */
+typedef struct {
+  void *(*alloc)(size_t bytes, void *stream, void *ctx);
+  void (*free)(void *ptr, size_t bytes, void *stream, void *ctx);
+  void *ctx;
+} lc_alloc;
+
+/* Exact integers of the most recent sweep (Sec. 2, step 8).  A loop c has
+ * size_c nodes, n0_c nodes at tau = 0+, magnetization
+ * m_c = sum over those of (2 s - 1) before the flip, and length len_c
+ * (sum of its vertical segments, in ticks of beta / 2^64). */
+typedef struct {
+  int64_t sweep;         /* index of the sweep described */
+  int64_t n_ops;         /* operators (horizontal graphs) */
+  int64_t n_cand;        /* insertion candidates drawn */
+  int64_t n_acc;         /* candidates accepted (antiparallel) */
+  int64_t n_kept_in;     /* off-diagonal operators before the sweep */
+  int64_t n_kept_out;    /* off-diagonal operators after the flip */
+  int64_t n_nodes;       /* loop-graph nodes */
+  int64_t n_clusters;    /* loops */
+  uint64_t sum_m2;       /* sum_c m_c^2 */
+  uint64_t sum_n0sq;     /* sum_c n0_c^2 */
+  uint64_t sum_size2_lo; /* sum_c size_c^2, 128-bit */
+  uint64_t sum_size2_hi;
+  uint64_t sum_len2_lo;  /* sum_c (len_c >> 32)^2, 128-bit */
+  uint64_t sum_len2_hi;
+  int64_t m_after;       /* sum_j (2 s_j - 1) at tau = 0+ after the flip */
+  int64_t max_size;      /* largest loop in nodes */
+} lc_sweep_stats;
+
+/* Observables averaged over the sweeps accumulated since the last reset
+ * (FP64, from exact integer sums); N_b = (2S)^2 L sub-bonds:
+ *   e           = N_b/(4L) - <n_ops>/(beta L)        energy per spin
+ *   chi_u       = beta/(4L) <sum_c m_c^2>             uniform susceptibility
+ *   chi_u_plain = beta/(4L) <m_after^2>
+ *   s_pi        = <sum_c n0_c^2>/(4L)                 staggered structure factor
+ *   chi_s       = beta/(4L) <sum_c ((len_c >> 32)/2^32)^2>  staggered susceptibility */
+typedef struct {
+  int64_t n_sweeps;
+  double e, chi_u, chi_u_plain, s_pi, chi_s;
+  double mean_ops, mean_clusters;
+} lc_measurement;
+
+/* Device bytes one chain needs when run alone (state plus per-sweep scratch).
+ * Used for admission; LC_EINVAL on bad parameters. */
+int lc_footprint(int64_t L, double S, double beta, size_t *bytes);
+
+/* init_lattice: a chain of L spins S at inverse temperature beta with Philox
+ * key `seed`, in the Neel state with a random phase and no operators.
+ * alloc may be NULL (hipMalloc); hip_stream may be NULL.  *out receives the
+ * handle, owned by the caller until lc_free. */
+int lc_init_lattice(int64_t L, double S, double beta, uint64_t seed, const lc_alloc *alloc,
+                    void *hip_stream, lc_chain **out);
+
+/* update: n_sweeps loop-cluster updates (Sec. 2 steps 1-8).  With
+ * accumulate != 0 each sweep's integers are added to the measurement sums.
+ * LC_ESTATE when the chain belongs to a batch. */
+int lc_update(lc_chain *c, int64_t n_sweeps, int accumulate);
+
+/* measure: FP64 observables from the accumulated sums into *out. */
+int lc_measure(const lc_chain *c, lc_measurement *out);
+
+/* Integers of the most recent sweep; LC_ESTATE before the first sweep. */
+int lc_last_sweep(const lc_chain *c, lc_sweep_stats *out);
+
+/* Forget the accumulated sums. */
+int lc_reset_measurements(lc_chain *c);
+
+/* World lines (checkpoint and parity).  s0[n_sites] spins at tau = 0+
+ * (1 = up), bond_off[n_bonds + 1] CSR offsets and times[*n_kept] the
+ * off-diagonal operators in (bond, time) order, *sweep the next sweep index.
+ * *n_kept is the capacity of times on input and the count on output
+ * (LC_ECAPACITY if too small; times may be NULL to query sizes).
+ * n_sites = 2S L, n_bonds = (2S)^2 L. */
+int lc_export_state(const lc_chain *c, uint8_t *s0, int64_t *bond_off, uint64_t *times,
+                    int64_t *n_kept, int64_t *sweep);
+
+/* Replace the world lines (same layout as lc_export_state).  Times must be
+ * sorted within each bond; the configuration must be a valid world-line
+ * configuration (antiparallel spins at every operator, periodic) -- the next
+ * sweep reports LC_ESTATE for split spins whose ends cannot be matched.
+ * Accumulated measurements are kept. */
+int lc_import_state(lc_chain *c, const uint8_t *s0, const int64_t *bond_off, const uint64_t *times,
+                    int64_t sweep);
+
+/* Operators of the most recent sweep in canonical (bond, time) order:
+ * op_bond, op_time, and their type before (op_type0) and after (op_type1)
+ * the flip, 1 = off-diagonal.  *n_ops: capacity in, count out; all arrays
+ * NULL queries the count.  Valid until the next sweep of the chain or of
+ * its batch. */
+int lc_export_ops(const lc_chain *c, int64_t *op_bond, uint64_t *op_time, uint8_t *op_type0,
+                  uint8_t *op_type1, int64_t *n_ops);
+
+/* Loop labels of the most recent sweep: labels[v] = smallest node id of the
+ * loop through node v.  Nodes: boundary nodes first (S = 1/2: one per spin;
+ * split spins: bottom(x) = x and top(x) = n_sites + x), then operator q has
+ * lower node nbn + 2q and upper node nbn + 2q + 1.  *n_nodes: capacity in,
+ * count out. */
+int lc_export_labels(const lc_chain *c, int64_t *labels, int64_t *n_nodes);
+
+/* Symmetrization permutation of the most recent sweep (split spins): top
+ * node of subspin x is joined to bottom node perm[x].  *n: capacity in,
+ * count out. */
+int lc_export_perm(const lc_chain *c, int64_t *perm, int64_t *n);
+
+void lc_free(lc_chain *c);
+const char *lc_strerror(int code);
+
+/* ---- batching: many chains, one launch sequence per sweep ----------------
+ * A batch runs every member chain through the same kernels, each kernel
+ * walking a flat index space over all members (Sec. 3: independent Markov
+ * chains are the preferred parallelism when memory allows).  Member chains
+ * keep their own world lines; their results equal their alone-runs bit for
+ * bit.  The sweep is captured once as a HIP graph and replayed. */
+int lc_batch_create(const lc_alloc *alloc, void *hip_stream, lc_batch **out);
+int lc_batch_add(lc_batch *b, lc_chain *c);    /* LC_ESTATE if c is in a batch */
+int lc_batch_remove(lc_batch *b, lc_chain *c); /* LC_EINVAL if c is not a member */
+int lc_batch_size(const lc_batch *b, int *n);
+/* n_sweeps sweeps of every member; accumulate as in lc_update. */
+int lc_batch_update(lc_batch *b, int64_t n_sweeps, int accumulate);
+/* Launch configuration: persistent grid size (workgroups of 256) used by the
+ * node and window loops, and graph capture on/off.  Schedule only: results
+ * do not depend on it. */
+int lc_batch_set_schedule(lc_batch *b, int grid_blocks, int use_graph);
+void lc_batch_free(lc_batch *b);
+
+/* Same launch configuration for a chain run alone. */
+int lc_set_schedule(lc_chain *c, int grid_blocks, int use_graph);
+
+/* ---- testing hooks (host code of the library, no GPU needed) ------------
+ * The library's host twin of its Philox4x32-10 and its Poisson window rule:
+ * w (2^w windows per bond), mu = beta / 2^(w+1) and thresholds
+ * T[i] = floor(P(n <= i) 2^64) with T[*K - 1] = 2^64 - 1 (T holds 64). */
+int lc_debug_philox(uint64_t seed, const uint32_t ctr[4], uint32_t out[4]);
+int lc_debug_window_table(double beta, int *w, double *mu, uint64_t *T, int *K);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,321 @@
+"""MI355X-native continuous-time loop-cluster QMC (arXiv:1810.07485).
+
+Thin ctypes binding of ``liblc.so`` (C ABI in ``include/lc.h``): argument
+marshalling only; every step of a sweep runs in the library's HIP kernels.
+PyTorch supplies device memory (its caching allocator) and the HIP stream.
+
+There is no CPU fallback: importing works without a GPU (so the build can be
+checked), but creating a chain needs the compiled library and a device.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+__all__ = ["load", "Chain", "Batch", "lc_footprint", "lc_strerror", "LcError",
+           "lc_debug_philox", "lc_debug_window_table", "SweepStats", "Measurement"]
+
+SO = _build.SO
+
+LC_OK, LC_EINVAL, LC_ENOMEM, LC_ETOOLARGE, LC_ECAPACITY, LC_EDEVICE, LC_ESTATE = 0, -1, -2, -3, -4, -5, -6
+
+
+class LcError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {lc_strerror(code)} ({code})")
+        self.code = code
+
+
+class SweepStats(C.Structure):
+    _fields_ = [
+        ("sweep", C.c_int64), ("n_ops", C.c_int64), ("n_cand", C.c_int64),
+        ("n_acc", C.c_int64), ("n_kept_in", C.c_int64), ("n_kept_out", C.c_int64),
+        ("n_nodes", C.c_int64), ("n_clusters", C.c_int64),
+        ("sum_m2", C.c_uint64), ("sum_n0sq", C.c_uint64),
+        ("sum_size2_lo", C.c_uint64), ("sum_size2_hi", C.c_uint64),
+        ("sum_len2_lo", C.c_uint64), ("sum_len2_hi", C.c_uint64),
+        ("m_after", C.c_int64), ("max_size", C.c_int64),
+    ]
+
+    def as_dict(self) -> dict:
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["sum_size2"] = d.pop("sum_size2_lo") | (d.pop("sum_size2_hi") << 64)
+        d["sum_len2"] = d.pop("sum_len2_lo") | (d.pop("sum_len2_hi") << 64)
+        return d
+
+
+class Measurement(C.Structure):
+    _fields_ = [("n_sweeps", C.c_int64), ("e", C.c_double), ("chi_u", C.c_double),
+                ("chi_u_plain", C.c_double), ("s_pi", C.c_double), ("chi_s", C.c_double),
+                ("mean_ops", C.c_double), ("mean_clusters", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+
+
+class Alloc(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
+
+
+_lib = None
+
+
+def load():
+    """Load the compiled library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(SO):
+        raise RuntimeError(f"{SO} is missing: run paper_1810_07485_amd/build.py (or "
+                           "__graft_entry__.build()) first; there is no fallback path")
+    L = C.CDLL(SO)
+    p64, pu64, pu8, pi = (C.POINTER(C.c_int64), C.POINTER(C.c_uint64), C.POINTER(C.c_uint8),
+                          C.POINTER(C.c_int))
+    vp = C.c_void_p
+    sig = {
+        "lc_footprint": ([C.c_int64, C.c_double, C.c_double, C.POINTER(C.c_size_t)], C.c_int),
+        "lc_init_lattice": ([C.c_int64, C.c_double, C.c_double, C.c_uint64, C.POINTER(Alloc), vp,
+                             C.POINTER(vp)], C.c_int),
+        "lc_update": ([vp, C.c_int64, C.c_int], C.c_int),
+        "lc_measure": ([vp, C.POINTER(Measurement)], C.c_int),
+        "lc_last_sweep": ([vp, C.POINTER(SweepStats)], C.c_int),
+        "lc_reset_measurements": ([vp], C.c_int),
+        "lc_export_state": ([vp, pu8, p64, pu64, p64, p64], C.c_int),
+        "lc_import_state": ([vp, pu8, p64, pu64, C.c_int64], C.c_int),
+        "lc_export_ops": ([vp, p64, pu64, pu8, pu8, p64], C.c_int),
+        "lc_export_labels": ([vp, p64, p64], C.c_int),
+        "lc_export_perm": ([vp, p64, p64], C.c_int),
+        "lc_free": ([vp], None),
+        "lc_strerror": ([C.c_int], C.c_char_p),
+        "lc_batch_create": ([C.POINTER(Alloc), vp, C.POINTER(vp)], C.c_int),
+        "lc_batch_add": ([vp, vp], C.c_int),
+        "lc_batch_remove": ([vp, vp], C.c_int),
+        "lc_batch_size": ([vp, pi], C.c_int),
+        "lc_batch_update": ([vp, C.c_int64, C.c_int], C.c_int),
+        "lc_batch_set_schedule": ([vp, C.c_int, C.c_int], C.c_int),
+        "lc_batch_free": ([vp], None),
+        "lc_set_schedule": ([vp, C.c_int, C.c_int], C.c_int),
+        "lc_debug_philox": ([C.c_uint64, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)], C.c_int),
+        "lc_debug_window_table": ([C.c_double, pi, C.POINTER(C.c_double), pu64, pi], C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def lc_strerror(code: int) -> str:
+    try:
+        return load().lc_strerror(code).decode()
+    except RuntimeError:
+        return str(code)
+
+
+def _check(rc: int, what: str):
+    if rc != LC_OK:
+        raise LcError(rc, what)
+
+
+def _p(a: np.ndarray, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+def lc_footprint(L: int, S: float, beta: float) -> int:
+    n = C.c_size_t()
+    _check(load().lc_footprint(int(L), float(S), float(beta), C.byref(n)), "lc_footprint")
+    return n.value
+
+
+def lc_debug_philox(seed: int, ctr) -> tuple:
+    c = (C.c_uint32 * 4)(*[int(x) & 0xFFFFFFFF for x in ctr])
+    o = (C.c_uint32 * 4)()
+    _check(load().lc_debug_philox(C.c_uint64(seed), c, o), "lc_debug_philox")
+    return tuple(o)
+
+
+def lc_debug_window_table(beta: float):
+    w, mu, K = C.c_int(), C.c_double(), C.c_int()
+    T = (C.c_uint64 * 64)()
+    _check(load().lc_debug_window_table(float(beta), C.byref(w), C.byref(mu), T, C.byref(K)),
+           "lc_debug_window_table")
+    return w.value, mu.value, [T[i] for i in range(K.value)]
+
+
+class _TorchMemory:
+    """Device memory and stream from PyTorch (its caching allocator)."""
+
+    def __init__(self, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the loop-cluster library runs only on the device")
+        self.torch = torch
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        dev = self.stream.device
+
+        def _alloc(nbytes, _stream, _ctx):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), dev, self.stream)
+            except Exception:  # out of memory -> NULL, reported as LC_ENOMEM
+                return None
+
+        def _free(ptr, _nbytes, _stream, _ctx):
+            torch.cuda.caching_allocator_delete(ptr)
+
+        self._fa, self._ff = ALLOC_FN(_alloc), FREE_FN(_free)
+        self.alloc = Alloc(self._fa, self._ff, None)
+
+    @property
+    def handle(self):
+        return C.c_void_p(self.stream.cuda_stream)
+
+
+class Chain:
+    """One Markov chain: ``lc_init_lattice`` / ``lc_update`` / ``lc_measure``."""
+
+    def __init__(self, L: int, S: float, beta: float, seed: int, stream=None,
+                 torch_memory: bool = True):
+        lib = load()
+        self.L, self.S, self.beta, self.seed = int(L), float(S), float(beta), int(seed)
+        self.two_s = int(round(2 * S))
+        self._mem = _TorchMemory(stream) if torch_memory else None
+        h = C.c_void_p()
+        alloc = C.byref(self._mem.alloc) if self._mem else None
+        strm = self._mem.handle if self._mem else None
+        _check(lib.lc_init_lattice(self.L, self.S, self.beta, C.c_uint64(self.seed), alloc, strm,
+                                   C.byref(h)), "lc_init_lattice")
+        self._h = h
+        self.n_sites = self.two_s * self.L
+        self.n_bonds = self.two_s * self.two_s * self.L
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            load().lc_free(h)
+        self._h = None
+
+    __del__ = close
+
+    def update(self, n_sweeps: int = 1, accumulate: bool = True):
+        _check(load().lc_update(self._h, int(n_sweeps), int(bool(accumulate))), "lc_update")
+
+    def measure(self) -> dict:
+        m = Measurement()
+        _check(load().lc_measure(self._h, C.byref(m)), "lc_measure")
+        return m.as_dict()
+
+    def last_sweep(self) -> dict:
+        s = SweepStats()
+        _check(load().lc_last_sweep(self._h, C.byref(s)), "lc_last_sweep")
+        return s.as_dict()
+
+    def reset_measurements(self):
+        _check(load().lc_reset_measurements(self._h), "lc_reset_measurements")
+
+    def set_schedule(self, grid_blocks: int = 0, use_graph: bool = True):
+        _check(load().lc_set_schedule(self._h, int(grid_blocks), int(bool(use_graph))),
+               "lc_set_schedule")
+
+    def export_state(self):
+        lib = load()
+        n, sw = C.c_int64(0), C.c_int64()
+        _check(lib.lc_export_state(self._h, None, None, None, C.byref(n), C.byref(sw)),
+               "lc_export_state")
+        s0 = np.zeros(self.n_sites, np.uint8)
+        off = np.zeros(self.n_bonds + 1, np.int64)
+        t = np.zeros(max(n.value, 1), np.uint64)
+        n = C.c_int64(t.size)
+        _check(lib.lc_export_state(self._h, _p(s0, C.c_uint8), _p(off, C.c_int64),
+                                   _p(t, C.c_uint64), C.byref(n), C.byref(sw)), "lc_export_state")
+        return s0, off, t[: n.value].copy(), sw.value
+
+    def import_state(self, s0, bond_off, times, sweep: int):
+        s0 = np.ascontiguousarray(s0, np.uint8)
+        off = np.ascontiguousarray(bond_off, np.int64)
+        t = np.ascontiguousarray(times, np.uint64)
+        if t.size == 0:
+            t = np.zeros(1, np.uint64)
+        _check(load().lc_import_state(self._h, _p(s0, C.c_uint8), _p(off, C.c_int64),
+                                      _p(t, C.c_uint64), int(sweep)), "lc_import_state")
+
+    def export_ops(self):
+        lib = load()
+        n = C.c_int64(0)
+        _check(lib.lc_export_ops(self._h, None, None, None, None, C.byref(n)), "lc_export_ops")
+        k = n.value
+        b = np.zeros(max(k, 1), np.int64)
+        t = np.zeros(max(k, 1), np.uint64)
+        t0 = np.zeros(max(k, 1), np.uint8)
+        t1 = np.zeros(max(k, 1), np.uint8)
+        n = C.c_int64(b.size)
+        _check(lib.lc_export_ops(self._h, _p(b, C.c_int64), _p(t, C.c_uint64), _p(t0, C.c_uint8),
+                                 _p(t1, C.c_uint8), C.byref(n)), "lc_export_ops")
+        return b[:k].copy(), t[:k].copy(), t0[:k].copy(), t1[:k].copy()
+
+    def export_labels(self):
+        lib = load()
+        n = C.c_int64(0)
+        _check(lib.lc_export_labels(self._h, None, C.byref(n)), "lc_export_labels")
+        k = n.value
+        lab = np.zeros(max(k, 1), np.int64)
+        n = C.c_int64(lab.size)
+        _check(lib.lc_export_labels(self._h, _p(lab, C.c_int64), C.byref(n)), "lc_export_labels")
+        return lab[:k].copy()
+
+    def export_perm(self):
+        lib = load()
+        n = C.c_int64(0)
+        _check(lib.lc_export_perm(self._h, None, C.byref(n)), "lc_export_perm")
+        k = n.value
+        p = np.zeros(max(k, 1), np.int64)
+        n = C.c_int64(p.size)
+        _check(lib.lc_export_perm(self._h, _p(p, C.c_int64), C.byref(n)), "lc_export_perm")
+        return p[:k].copy()
+
+
+class Batch:
+    """Many chains advanced by one launch sequence per sweep (``lc_batch_*``)."""
+
+    def __init__(self, stream=None, torch_memory: bool = True):
+        lib = load()
+        self._mem = _TorchMemory(stream) if torch_memory else None
+        h = C.c_void_p()
+        alloc = C.byref(self._mem.alloc) if self._mem else None
+        strm = self._mem.handle if self._mem else None
+        _check(lib.lc_batch_create(alloc, strm, C.byref(h)), "lc_batch_create")
+        self._h = h
+        self.members = []
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            load().lc_batch_free(h)
+        self._h = None
+        self.members = []
+
+    __del__ = close
+
+    def add(self, chain: Chain):
+        _check(load().lc_batch_add(self._h, chain._h), "lc_batch_add")
+        self.members.append(chain)
+
+    def remove(self, chain: Chain):
+        _check(load().lc_batch_remove(self._h, chain._h), "lc_batch_remove")
+        self.members.remove(chain)
+
+    def update(self, n_sweeps: int = 1, accumulate: bool = True):
+        _check(load().lc_batch_update(self._h, int(n_sweeps), int(bool(accumulate))),
+               "lc_batch_update")
+
+    def set_schedule(self, grid_blocks: int = 0, use_graph: bool = True):
+        _check(load().lc_batch_set_schedule(self._h, int(grid_blocks), int(bool(use_graph))),
+               "lc_batch_set_schedule")

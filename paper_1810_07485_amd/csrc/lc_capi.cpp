@@ -1,0 +1,935 @@
+// lc_capi.cpp -- engine and C ABI of the loop-cluster library (host side).
+//
+// A chain owns its world lines (double-buffered spins and kept-operator
+// lists on the device).  An engine owns the per-sweep scratch of a set of
+// chains and queues one sweep as a fixed sequence of kernel launches over
+// flat index spaces (lc_kernels.hip), optionally captured once as a HIP
+// graph.  The host reads back one small record per sweep: the exact integer
+// statistics and an overflow flag.  On overflow the scratch or the chain
+// buffers grow and the same sweep is run again; its random numbers are
+// addressed by (seed, sweep, entity), so the replay is bit-identical.
+#include "lc.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "lc_kernels.h"
+
+using lc::ChainDesc;
+using lc::ChainDyn;
+
+typedef unsigned __int128 u128;
+
+namespace {
+
+constexpr int kDefaultGrid = 2048;  // 256 CUs x 8 workgroups
+constexpr int kRing = 64;           // sweeps per host synchronisation
+
+struct Mem {
+  lc_alloc a{};
+  bool user = false;
+  hipStream_t s = nullptr;
+  void* get(size_t bytes) const {
+    if (bytes < 8) bytes = 8;
+    if (user) return a.alloc(bytes, s, a.ctx);
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    return p;
+  }
+  void put(void* p, size_t bytes) const {
+    if (!p) return;
+    if (bytes < 8) bytes = 8;
+    if (user)
+      a.free(p, bytes, s, a.ctx);
+    else
+      (void)hipFree(p);
+  }
+};
+
+template <class T>
+struct DBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  bool ensure(const Mem& m, size_t want, bool keep = false, hipStream_t s = nullptr) {
+    if (want <= n && p) return true;
+    T* q = static_cast<T*>(m.get(want * sizeof(T)));
+    if (!q) return false;
+    if (keep && p && n) {
+      if (hipMemcpyAsync(q, p, n * sizeof(T), hipMemcpyDeviceToDevice, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess) {
+        m.put(q, want * sizeof(T));
+        return false;
+      }
+    }
+    release(m);
+    p = q;
+    n = want;
+    return true;
+  }
+  void release(const Mem& m) {
+    m.put(p, n * sizeof(T));
+    p = nullptr;
+    n = 0;
+  }
+};
+
+// Poisson window rule (library host code): 2^w windows per bond with
+// w the smallest w >= 0 such that beta / 2^w <= 8; per window the count of
+// candidates of a rate-1/2 process is Poisson with mean mu = beta / 2^(w+1);
+// T[i] = floor(P(n <= i) 2^64), last entry 2^64 - 1.
+int window_rule(double beta, int* w_out, double* mu_out, uint64_t* T, int* K) {
+  if (!(beta > 0.0) || !std::isfinite(beta) || beta > 8.0 * 4294967296.0) return LC_EINVAL;
+  int w = 0;
+  while (beta > std::ldexp(8.0, w)) ++w;
+  const double mu = std::ldexp(beta, -w - 1);
+  double term = std::exp(-mu);
+  double cdf = term;
+  double before = -1.0;
+  int k = 0;
+  for (; k < lc::kMaxTable; ++k) {
+    if (k > 0) {
+      const double num = term * mu;
+      term = num / static_cast<double>(k);
+      const double next = cdf + term;
+      cdf = next;
+    }
+    if (cdf >= 1.0 || k == lc::kMaxTable - 1 || cdf == before) {
+      T[k] = ~uint64_t(0);
+      break;
+    }
+    T[k] = static_cast<uint64_t>(cdf * 18446744073709551616.0);
+    before = cdf;
+  }
+  *w_out = w;
+  *mu_out = mu;
+  *K = k + 1;
+  return LC_OK;
+}
+
+struct Accum {
+  int64_t n = 0;
+  u128 ops = 0, m2 = 0, ma2 = 0, n02 = 0, len2 = 0, clusters = 0;
+};
+
+}  // namespace
+
+struct Engine;
+
+struct lc_chain {
+  int64_t L = 0;
+  int two_s = 1;
+  double beta = 0;
+  uint64_t seed = 0;
+  int w = 0;
+  double mu = 0;
+  uint64_t T[lc::kMaxTable] = {};
+  int K = 0;
+  int64_t n_sites = 0, n_bonds = 0, nwin = 0, nbn = 0;
+  Mem mem;
+  hipStream_t stream = nullptr;
+  DBuf<uint8_t> s0[2];
+  DBuf<int64_t> kstart[2];
+  DBuf<uint64_t> ktime[2];
+  DBuf<int64_t> perm;
+  int64_t kept_cap = 0;
+  int64_t n_kept = 0;  // host mirror of the current kept count
+  int cur = 0;
+  uint32_t sweep = 0;
+  Accum acc;
+  lc_sweep_stats last{};
+  bool has_last = false;
+  Engine* own = nullptr;     // engine used when run alone
+  lc_batch* batch = nullptr; // batch membership
+  Engine* last_engine = nullptr;
+  int last_index = 0;
+};
+
+struct Engine {
+  Mem mem;
+  hipStream_t stream = nullptr;
+  std::vector<lc_chain*> chains;
+  bool dirty = true;
+  int grid = kDefaultGrid;
+  bool use_graph = true;
+  // per-chain small arrays
+  DBuf<ChainDesc> descs;
+  DBuf<int64_t> win_bases, site_bases, spin_bases, op_bases, node_bases;
+  DBuf<ChainDyn> dyn;
+  DBuf<int64_t> totals, scan_tmp;
+  DBuf<uint64_t> stats;
+  DBuf<uint32_t> flags, ring_ctr;
+  DBuf<unsigned long long> ring;
+  // flat scratch
+  DBuf<int64_t> opstart, kflat, parent;
+  DBuf<uint64_t> optime;
+  DBuf<uint8_t> optype, flipb;
+  DBuf<unsigned long long> acc;
+  int64_t nwin = 0, nsites = 0, nspins = 0, sum_nbn = 0, op_cap = 0, node_cap = 0;
+  bool any_split = false;
+  hipGraphExec_t gexec = nullptr;
+  bool graph_ok = false;
+  std::vector<unsigned long long> hring;
+
+  void drop_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    gexec = nullptr;
+    graph_ok = false;
+  }
+  void release_all() {
+    drop_graph();
+    descs.release(mem);
+    win_bases.release(mem);
+    site_bases.release(mem);
+    spin_bases.release(mem);
+    op_bases.release(mem);
+    node_bases.release(mem);
+    dyn.release(mem);
+    totals.release(mem);
+    scan_tmp.release(mem);
+    stats.release(mem);
+    flags.release(mem);
+    ring_ctr.release(mem);
+    ring.release(mem);
+    opstart.release(mem);
+    kflat.release(mem);
+    parent.release(mem);
+    optime.release(mem);
+    optype.release(mem);
+    flipb.release(mem);
+    acc.release(mem);
+  }
+};
+
+struct lc_batch {
+  Engine eng;
+  bool owns_stream = false;
+};
+
+namespace {
+
+int hip_err(hipError_t e) { return e == hipSuccess ? LC_OK : LC_EDEVICE; }
+
+ChainDesc make_desc(const lc_chain* c, int64_t win_base, int64_t site_base, int64_t spin_base,
+                    int64_t bnode_base) {
+  ChainDesc d;
+  std::memset(&d, 0, sizeof(d));
+  d.seed = c->seed;
+  d.L = c->L;
+  d.n_sites = c->n_sites;
+  d.n_bonds = c->n_bonds;
+  d.nbn = c->nbn;
+  d.win_base = win_base;
+  d.site_base = site_base;
+  d.spin_base = spin_base;
+  d.bnode_base = bnode_base;
+  d.kept_cap = c->kept_cap;
+  for (int q = 0; q < 2; ++q) {
+    d.s0[q] = c->s0[q].p;
+    d.kstart[q] = c->kstart[q].p;
+    d.ktime[q] = c->ktime[q].p;
+  }
+  d.perm = c->perm.p;
+  d.two_s = c->two_s;
+  d.w = c->w;
+  d.K = c->K;
+  d.sweep = c->sweep;
+  d.cur = c->cur;
+  std::memcpy(d.T, c->T, sizeof(d.T));
+  return d;
+}
+
+int64_t ops_estimate(const lc_chain* c) {
+  // operators = kept + accepted <= kept + candidates; candidates ~ Poisson
+  const double cand = 0.5 * static_cast<double>(c->n_bonds) * c->beta;
+  return c->n_kept + static_cast<int64_t>(cand + 6.0 * std::sqrt(cand + 1.0)) + 1024;
+}
+
+// (Re)build the flat layout of an engine's chains and upload descriptors.
+int layout(Engine& E) {
+  const int n = static_cast<int>(E.chains.size());
+  std::vector<ChainDesc> h(n);
+  std::vector<int64_t> wb(n), sb(n), pb(n);
+  int64_t nwin = 0, nsites = 0, nspins = 0, nbn = 0, ops = 0;
+  bool split = false;
+  for (int i = 0; i < n; ++i) {
+    lc_chain* c = E.chains[i];
+    h[i] = make_desc(c, nwin, nsites, nspins, nbn);
+    wb[i] = nwin;
+    sb[i] = nsites;
+    pb[i] = nspins;
+    nwin += c->nwin;
+    nsites += c->n_sites;
+    nspins += c->L;
+    nbn += c->nbn;
+    ops += ops_estimate(c);
+    split = split || c->two_s > 1;
+  }
+  const Mem& m = E.mem;
+  const size_t nc = static_cast<size_t>(std::max(n, 1));
+  bool ok = E.descs.ensure(m, nc) && E.win_bases.ensure(m, nc) && E.site_bases.ensure(m, nc) &&
+            E.spin_bases.ensure(m, nc) && E.op_bases.ensure(m, nc) && E.node_bases.ensure(m, nc) &&
+            E.dyn.ensure(m, nc) && E.totals.ensure(m, 2) && E.scan_tmp.ensure(m, LC_SCAN_BLOCKS + 1) &&
+            E.stats.ensure(m, nc * lc::ST_WORDS) && E.flags.ensure(m, 2) && E.ring_ctr.ensure(m, 2) &&
+            E.ring.ensure(m, static_cast<size_t>(kRing) * (nc * lc::ST_WORDS + 1)) &&
+            E.opstart.ensure(m, static_cast<size_t>(nwin) + 1) &&
+            E.kflat.ensure(m, static_cast<size_t>(nwin) + 1);
+  if (!ok) return LC_ENOMEM;
+  if (E.op_cap < ops) {
+    const int64_t nc2 = nbn + 2 * ops;
+    E.optime.release(m);
+    E.optype.release(m);
+    E.parent.release(m);
+    E.flipb.release(m);
+    E.acc.release(m);
+    ok = E.optime.ensure(m, ops) && E.optype.ensure(m, ops) && E.parent.ensure(m, nc2) &&
+         E.flipb.ensure(m, nc2) && E.acc.ensure(m, 5 * static_cast<size_t>(nc2));
+    if (!ok) {
+      E.op_cap = E.node_cap = 0;
+      return LC_ENOMEM;
+    }
+    E.op_cap = ops;
+    E.node_cap = nc2;
+  }
+  E.nwin = nwin;
+  E.nsites = nsites;
+  E.nspins = nspins;
+  E.sum_nbn = nbn;
+  E.any_split = split;
+  if (n > 0) {
+    hipStream_t s = E.stream;
+    if (hipMemcpyAsync(E.descs.p, h.data(), n * sizeof(ChainDesc), hipMemcpyHostToDevice, s) ||
+        hipMemcpyAsync(E.win_bases.p, wb.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, s) ||
+        hipMemcpyAsync(E.site_bases.p, sb.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, s) ||
+        hipMemcpyAsync(E.spin_bases.p, pb.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, s) ||
+        hipStreamSynchronize(s))
+      return LC_EDEVICE;
+  }
+  for (int i = 0; i < n; ++i) {
+    E.chains[i]->last_engine = nullptr;
+  }
+  E.hring.assign(static_cast<size_t>(kRing) * (nc * lc::ST_WORDS + 1), 0);
+  E.drop_graph();
+  E.dirty = false;
+  return LC_OK;
+}
+
+LcSweepArgs sweep_args(Engine& E) {
+  LcSweepArgs A;
+  A.descs = E.descs.p;
+  A.win_bases = E.win_bases.p;
+  A.site_bases = E.site_bases.p;
+  A.spin_bases = E.spin_bases.p;
+  A.nchain = static_cast<int>(E.chains.size());
+  A.any_split = E.any_split ? 1 : 0;
+  A.nwin = E.nwin;
+  A.nsites = E.nsites;
+  A.nspins = E.nspins;
+  A.grid_blocks = E.grid;
+  A.opstart = E.opstart.p;
+  A.kflat = E.kflat.p;
+  A.optime = E.optime.p;
+  A.optype = E.optype.p;
+  A.parent = E.parent.p;
+  A.flipb = E.flipb.p;
+  A.acc = E.acc.p;
+  A.op_cap = E.op_cap;
+  A.node_cap = E.node_cap;
+  A.dyn = E.dyn.p;
+  A.op_bases = E.op_bases.p;
+  A.node_bases = E.node_bases.p;
+  A.totals = E.totals.p;
+  A.scan_tmp = E.scan_tmp.p;
+  A.stats = E.stats.p;
+  A.flags = E.flags.p;
+  A.ring = E.ring.p;
+  A.ring_ctr = E.ring_ctr.p;
+  A.ring_cap = kRing;
+  return A;
+}
+
+int launch_one(Engine& E) {
+  if (E.use_graph) {
+    if (!E.graph_ok) {
+      hipGraph_t g = nullptr;
+      if (hipStreamBeginCapture(E.stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return LC_EDEVICE;
+      const hipError_t le = lc_launch_sweep(sweep_args(E), E.stream);
+      const hipError_t ce = hipStreamEndCapture(E.stream, &g);
+      if (le != hipSuccess || ce != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return LC_EDEVICE;
+      }
+      const hipError_t ie = hipGraphInstantiate(&E.gexec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ie != hipSuccess) return LC_EDEVICE;
+      E.graph_ok = true;
+    }
+    return hip_err(hipGraphLaunch(E.gexec, E.stream));
+  }
+  return hip_err(lc_launch_sweep(sweep_args(E), E.stream));
+}
+
+void apply_record(lc_chain* c, const unsigned long long* st, bool accumulate) {
+  lc_sweep_stats& s = c->last;
+  s.sweep = c->sweep;
+  s.n_cand = static_cast<int64_t>(st[lc::ST_CAND]);
+  s.n_acc = static_cast<int64_t>(st[lc::ST_ACC]);
+  s.n_ops = static_cast<int64_t>(st[lc::ST_OPS]);
+  s.n_kept_in = static_cast<int64_t>(st[lc::ST_KEPT_IN]);
+  s.n_kept_out = static_cast<int64_t>(st[lc::ST_KEPT_OUT]);
+  s.n_nodes = static_cast<int64_t>(st[lc::ST_NODES]);
+  s.n_clusters = static_cast<int64_t>(st[lc::ST_CLUSTERS]);
+  s.sum_m2 = st[lc::ST_M2];
+  s.sum_n0sq = st[lc::ST_N0SQ];
+  s.sum_size2_lo = st[lc::ST_SIZE2_LO];
+  s.sum_size2_hi = st[lc::ST_SIZE2_HI];
+  s.sum_len2_lo = st[lc::ST_LEN2_LO];
+  s.sum_len2_hi = st[lc::ST_LEN2_HI];
+  s.m_after = static_cast<int64_t>(st[lc::ST_MAFTER]);
+  s.max_size = static_cast<int64_t>(st[lc::ST_MAXSIZE]);
+  c->has_last = true;
+  c->n_kept = s.n_kept_out;
+  c->cur ^= 1;
+  c->sweep += 1;
+  if (accumulate) {
+    Accum& a = c->acc;
+    a.n += 1;
+    a.ops += static_cast<u128>(s.n_ops);
+    a.m2 += static_cast<u128>(s.sum_m2);
+    a.ma2 += static_cast<u128>(static_cast<uint64_t>(s.m_after * s.m_after));
+    a.n02 += static_cast<u128>(s.sum_n0sq);
+    a.len2 += (static_cast<u128>(s.sum_len2_hi) << 64) | s.sum_len2_lo;
+    a.clusters += static_cast<u128>(s.n_clusters);
+  }
+}
+
+// Grow chain kept buffers (both halves, keeping the current content).
+int grow_kept(lc_chain* c, int64_t need) {
+  const int64_t cap = std::max<int64_t>(need + need / 4 + 1024, c->kept_cap);
+  for (int q = 0; q < 2; ++q)
+    if (!c->ktime[q].ensure(c->mem, static_cast<size_t>(cap), q == c->cur, c->stream)) return LC_ENOMEM;
+  c->kept_cap = cap;
+  if (c->own) c->own->dirty = true;
+  if (c->batch) c->batch->eng.dirty = true;
+  return LC_OK;
+}
+
+int run_engine(Engine& E, int64_t n_sweeps, int accumulate) {
+  if (n_sweeps < 0) return LC_EINVAL;
+  if (E.chains.empty() || n_sweeps == 0) return LC_OK;
+  int rc;
+  if (E.dirty && (rc = layout(E)) != LC_OK) return rc;
+  const int nch = static_cast<int>(E.chains.size());
+  const int64_t rec = static_cast<int64_t>(nch) * lc::ST_WORDS + 1;
+  int64_t done = 0;
+  int stuck = 0;
+  while (done < n_sweeps) {
+    const int chunk = static_cast<int>(std::min<int64_t>(n_sweeps - done, kRing));
+    if (hip_err(lc_launch_fill_u64(E.ring_ctr.p, 1, 0, E.stream)) != LC_OK) return LC_EDEVICE;
+    for (int q = 0; q < chunk; ++q)
+      if ((rc = launch_one(E)) != LC_OK) return rc;
+    if (hipMemcpyAsync(E.hring.data(), E.ring.p, chunk * rec * sizeof(unsigned long long),
+                       hipMemcpyDeviceToHost, E.stream) != hipSuccess ||
+        hipStreamSynchronize(E.stream) != hipSuccess)
+      return LC_EDEVICE;
+    int ok = 0;
+    uint32_t bad = 0;
+    for (; ok < chunk; ++ok) {
+      const unsigned long long* r = E.hring.data() + ok * rec;
+      bad = static_cast<uint32_t>(r[rec - 1]);
+      if (bad) break;
+      for (int i = 0; i < nch; ++i) apply_record(E.chains[i], r + i * lc::ST_WORDS, accumulate != 0);
+    }
+    done += ok;
+    for (int i = 0; i < nch; ++i) {
+      lc_chain* c = E.chains[i];
+      c->last_engine = &E;
+      c->last_index = i;
+      // descriptors held by the chain's other engine are now stale
+      if (ok && c->own && c->own != &E) c->own->dirty = true;
+    }
+    if (!bad) {
+      stuck = 0;
+      continue;
+    }
+    // a sweep did not fit: grow and run it again
+    if (bad & LC_FLAG_SYM) return LC_ESTATE;
+    if (++stuck > 8) return LC_ENOMEM;
+    for (int i = 0; i < nch; ++i) E.chains[i]->last_engine = nullptr;
+    const unsigned long long* r = E.hring.data() + ok * rec;
+    if (bad & (LC_FLAG_OPS | LC_FLAG_NODES)) {
+      int64_t tot[2] = {0, 0};
+      if (hipMemcpy(tot, E.totals.p, sizeof(tot), hipMemcpyDeviceToHost) != hipSuccess)
+        return LC_EDEVICE;
+      const int64_t ops = std::max<int64_t>(tot[0] + tot[0] / 8 + 4096, E.op_cap + E.op_cap / 4);
+      const int64_t nodes = E.sum_nbn + 2 * ops;
+      E.optime.release(E.mem);
+      E.optype.release(E.mem);
+      E.parent.release(E.mem);
+      E.flipb.release(E.mem);
+      E.acc.release(E.mem);
+      if (!(E.optime.ensure(E.mem, ops) && E.optype.ensure(E.mem, ops) &&
+            E.parent.ensure(E.mem, nodes) && E.flipb.ensure(E.mem, nodes) &&
+            E.acc.ensure(E.mem, 5 * static_cast<size_t>(nodes)))) {
+        E.op_cap = E.node_cap = 0;
+        E.dirty = true;
+        return LC_ENOMEM;
+      }
+      E.op_cap = ops;
+      E.node_cap = nodes;
+    }
+    if (bad & LC_FLAG_KEPT) {
+      for (int i = 0; i < nch; ++i) {
+        const int64_t need = static_cast<int64_t>(r[i * lc::ST_WORDS + lc::ST_KEPT_OUT]);
+        if (need > E.chains[i]->kept_cap && (rc = grow_kept(E.chains[i], need)) != LC_OK) return rc;
+      }
+    }
+    E.dirty = true;
+    if ((rc = layout(E)) != LC_OK) return rc;
+  }
+  return LC_OK;
+}
+
+int validate(int64_t L, double S, double beta, int* two_s) {
+  if (L < 4 || (L & 1) || L > (int64_t(1) << 40)) return LC_EINVAL;
+  if (!std::isfinite(S)) return LC_EINVAL;
+  const double ts = 2.0 * S;
+  const int t = static_cast<int>(std::lround(ts));
+  if (std::fabs(ts - t) > 1e-12 || t < 1 || t > 8) return LC_EINVAL;
+  if (!(beta > 0.0) || !std::isfinite(beta) || beta > 8.0 * 4294967296.0) return LC_EINVAL;
+  *two_s = t;
+  return LC_OK;
+}
+
+// Bytes of one chain alone: state + its engine's scratch.
+size_t footprint_bytes(int64_t L, int two_s, double beta) {
+  int w, K;
+  double mu;
+  uint64_t T[lc::kMaxTable];
+  (void)window_rule(beta, &w, &mu, T, &K);
+  const double n_sites = static_cast<double>(two_s) * L;
+  const double n_bonds = static_cast<double>(two_s) * two_s * L;
+  const double nwin = n_bonds * std::ldexp(1.0, w);
+  const double nbn = two_s == 1 ? n_sites : 2 * n_sites;
+  const double kept = 0.5 * n_bonds * beta + 1024;  // initial kept capacity
+  const double ops = kept + 0.5 * n_bonds * beta + 6 * std::sqrt(0.5 * n_bonds * beta + 1) + 1024;
+  const double nodes = nbn + 2 * ops;
+  const double state = 2 * n_sites + 2 * 8 * (nwin + 1) + 2 * 8 * kept + 8 * n_sites;
+  const double scratch = 2 * 8 * (nwin + 1) + 9 * ops + nodes * (8 + 1 + 40);
+  return static_cast<size_t>(state + scratch + (1 << 20));
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------
+extern "C" {
+
+const char* lc_strerror(int code) {
+  switch (code) {
+    case LC_OK: return "ok";
+    case LC_EINVAL: return "invalid argument";
+    case LC_ENOMEM: return "out of device memory";
+    case LC_ETOOLARGE: return "footprint exceeds device memory";
+    case LC_ECAPACITY: return "caller buffer too small";
+    case LC_EDEVICE: return "HIP runtime error";
+    case LC_ESTATE: return "invalid state for this call";
+    default: return "unknown error";
+  }
+}
+
+int lc_debug_philox(uint64_t seed, const uint32_t ctr[4], uint32_t out[4]) {
+  if (!ctr || !out) return LC_EINVAL;
+  const lc::u32x4 r = lc::philox10(seed, ctr[0], ctr[1], ctr[2], ctr[3]);
+  out[0] = r.x;
+  out[1] = r.y;
+  out[2] = r.z;
+  out[3] = r.w;
+  return LC_OK;
+}
+
+int lc_debug_window_table(double beta, int* w, double* mu, uint64_t* T, int* K) {
+  if (!w || !mu || !T || !K) return LC_EINVAL;
+  return window_rule(beta, w, mu, T, K);
+}
+
+int lc_footprint(int64_t L, double S, double beta, size_t* bytes) {
+  int two_s;
+  if (!bytes) return LC_EINVAL;
+  const int rc = validate(L, S, beta, &two_s);
+  if (rc != LC_OK) return rc;
+  *bytes = footprint_bytes(L, two_s, beta);
+  return LC_OK;
+}
+
+int lc_init_lattice(int64_t L, double S, double beta, uint64_t seed, const lc_alloc* alloc,
+                    void* hip_stream, lc_chain** out) {
+  if (!out) return LC_EINVAL;
+  *out = nullptr;
+  int two_s, rc;
+  if ((rc = validate(L, S, beta, &two_s)) != LC_OK) return rc;
+  if (alloc && (!alloc->alloc || !alloc->free)) return LC_EINVAL;
+  size_t fb = footprint_bytes(L, two_s, beta), freeb = 0, totalb = 0;
+  if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) return LC_EDEVICE;
+  if (fb > totalb) return LC_ETOOLARGE;
+  lc_chain* c = new (std::nothrow) lc_chain();
+  if (!c) return LC_ENOMEM;
+  c->L = L;
+  c->two_s = two_s;
+  c->beta = beta;
+  c->seed = seed;
+  (void)window_rule(beta, &c->w, &c->mu, c->T, &c->K);
+  c->n_sites = static_cast<int64_t>(two_s) * L;
+  c->n_bonds = static_cast<int64_t>(two_s) * two_s * L;
+  c->nwin = c->n_bonds << c->w;
+  c->nbn = two_s == 1 ? c->n_sites : 2 * c->n_sites;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->mem.s = c->stream;
+  if (alloc) {
+    c->mem.a = *alloc;
+    c->mem.user = true;
+  }
+  const int64_t kcap = static_cast<int64_t>(0.5 * static_cast<double>(c->n_bonds) * beta) + 1024;
+  bool ok = true;
+  for (int q = 0; q < 2; ++q)
+    ok = ok && c->s0[q].ensure(c->mem, c->n_sites) &&
+         c->kstart[q].ensure(c->mem, static_cast<size_t>(c->nwin) + 1) &&
+         c->ktime[q].ensure(c->mem, static_cast<size_t>(kcap));
+  ok = ok && c->perm.ensure(c->mem, c->n_sites);
+  if (!ok) {
+    lc_free(c);
+    return LC_ENOMEM;
+  }
+  c->kept_cap = kcap;
+  // initial configuration on the device
+  ChainDesc d = make_desc(c, 0, 0, 0, 0);
+  ChainDesc* dd = static_cast<ChainDesc*>(c->mem.get(sizeof(ChainDesc)));
+  if (!dd) {
+    lc_free(c);
+    return LC_ENOMEM;
+  }
+  rc = LC_OK;
+  if (hipMemcpyAsync(dd, &d, sizeof(d), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+      lc_launch_init_chain(dd, std::max(c->n_sites, c->nwin + 1), c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    rc = LC_EDEVICE;
+  c->mem.put(dd, sizeof(ChainDesc));
+  if (rc != LC_OK) {
+    lc_free(c);
+    return rc;
+  }
+  *out = c;
+  return LC_OK;
+}
+
+static Engine* own_engine(lc_chain* c) {
+  if (!c->own) {
+    c->own = new (std::nothrow) Engine();
+    if (!c->own) return nullptr;
+    c->own->mem = c->mem;
+    c->own->stream = c->stream;
+    c->own->chains.push_back(c);
+    // graph capture needs a stream other than the legacy null stream
+    c->own->use_graph = c->stream != nullptr;
+  }
+  return c->own;
+}
+
+int lc_set_schedule(lc_chain* c, int grid_blocks, int use_graph) {
+  if (!c || grid_blocks < 0) return LC_EINVAL;
+  Engine* E = own_engine(c);
+  if (!E) return LC_ENOMEM;
+  E->grid = grid_blocks > 0 ? grid_blocks : kDefaultGrid;
+  E->use_graph = use_graph && c->stream != nullptr;
+  E->drop_graph();
+  return LC_OK;
+}
+
+int lc_update(lc_chain* c, int64_t n_sweeps, int accumulate) {
+  if (!c || n_sweeps < 0) return LC_EINVAL;
+  if (c->batch) return LC_ESTATE;
+  Engine* E = own_engine(c);
+  if (!E) return LC_ENOMEM;
+  return run_engine(*E, n_sweeps, accumulate);
+}
+
+int lc_measure(const lc_chain* c, lc_measurement* out) {
+  if (!c || !out) return LC_EINVAL;
+  std::memset(out, 0, sizeof(*out));
+  const Accum& a = c->acc;
+  out->n_sweeps = a.n;
+  if (a.n == 0) return LC_OK;
+  const double n = static_cast<double>(a.n), L = static_cast<double>(c->L), b = c->beta;
+  const double nb = static_cast<double>(c->n_bonds);
+  out->mean_ops = static_cast<double>(a.ops) / n;
+  out->mean_clusters = static_cast<double>(a.clusters) / n;
+  out->e = nb / (4.0 * L) - out->mean_ops / (b * L);
+  out->chi_u = b / (4.0 * L) * (static_cast<double>(a.m2) / n);
+  out->chi_u_plain = b / (4.0 * L) * (static_cast<double>(a.ma2) / n);
+  out->s_pi = (static_cast<double>(a.n02) / n) / (4.0 * L);
+  out->chi_s = b / (4.0 * L) * (static_cast<double>(a.len2) / 18446744073709551616.0 / n);
+  return LC_OK;
+}
+
+int lc_last_sweep(const lc_chain* c, lc_sweep_stats* out) {
+  if (!c || !out) return LC_EINVAL;
+  if (!c->has_last) return LC_ESTATE;
+  *out = c->last;
+  return LC_OK;
+}
+
+int lc_reset_measurements(lc_chain* c) {
+  if (!c) return LC_EINVAL;
+  c->acc = Accum();
+  return LC_OK;
+}
+
+int lc_export_state(const lc_chain* c, uint8_t* s0, int64_t* bond_off, uint64_t* times,
+                    int64_t* n_kept, int64_t* sweep) {
+  if (!c || !n_kept) return LC_EINVAL;
+  const int64_t have = *n_kept;
+  *n_kept = c->n_kept;
+  if (sweep) *sweep = c->sweep;
+  hipStream_t s = c->stream;
+  if (s0 && hipMemcpyAsync(s0, c->s0[c->cur].p, c->n_sites, hipMemcpyDeviceToHost, s) != hipSuccess)
+    return LC_EDEVICE;
+  if (bond_off) {
+    std::vector<int64_t> ks(static_cast<size_t>(c->nwin) + 1);
+    if (hipMemcpyAsync(ks.data(), c->kstart[c->cur].p, ks.size() * sizeof(int64_t),
+                       hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return LC_EDEVICE;
+    for (int64_t b = 0; b <= c->n_bonds; ++b) bond_off[b] = ks[b << c->w];
+  }
+  if (times) {
+    if (have < c->n_kept) return LC_ECAPACITY;
+    if (c->n_kept && hipMemcpyAsync(times, c->ktime[c->cur].p, c->n_kept * sizeof(uint64_t),
+                                    hipMemcpyDeviceToHost, s) != hipSuccess)
+      return LC_EDEVICE;
+  }
+  return hip_err(hipStreamSynchronize(s));
+}
+
+int lc_import_state(lc_chain* c, const uint8_t* s0, const int64_t* bond_off, const uint64_t* times,
+                    int64_t sweep) {
+  if (!c || !s0 || !bond_off || sweep < 0 || sweep > 0xFFFFFFFFll) return LC_EINVAL;
+  if (bond_off[0] != 0) return LC_EINVAL;
+  for (int64_t b = 0; b < c->n_bonds; ++b) {
+    if (bond_off[b + 1] < bond_off[b]) return LC_EINVAL;
+    for (int64_t i = bond_off[b] + 1; i < bond_off[b + 1]; ++i)
+      if (times[i] < times[i - 1]) return LC_EINVAL;
+  }
+  for (int64_t x = 0; x < c->n_sites; ++x)
+    if (s0[x] > 1) return LC_EINVAL;
+  const int64_t n = bond_off[c->n_bonds];
+  if (n > 0 && !times) return LC_EINVAL;
+  int rc;
+  if (n > c->kept_cap && (rc = grow_kept(c, n)) != LC_OK) return rc;
+  // kept operators per window, exclusive scan
+  std::vector<int64_t> ks(static_cast<size_t>(c->nwin) + 1, 0);
+  const int64_t W = int64_t(1) << c->w;
+  for (int64_t b = 0; b < c->n_bonds; ++b)
+    for (int64_t i = bond_off[b]; i < bond_off[b + 1]; ++i) {
+      const int64_t k = c->w == 0 ? 0 : static_cast<int64_t>(times[i] >> (64 - c->w));
+      ks[b * W + k + 1] += 1;
+    }
+  for (size_t i = 1; i < ks.size(); ++i) ks[i] += ks[i - 1];
+  hipStream_t s = c->stream;
+  if (hipMemcpyAsync(c->s0[c->cur].p, s0, c->n_sites, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(c->kstart[c->cur].p, ks.data(), ks.size() * sizeof(int64_t),
+                     hipMemcpyHostToDevice, s) != hipSuccess ||
+      (n > 0 && hipMemcpyAsync(c->ktime[c->cur].p, times, n * sizeof(uint64_t),
+                               hipMemcpyHostToDevice, s) != hipSuccess) ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return LC_EDEVICE;
+  c->n_kept = n;
+  c->sweep = static_cast<uint32_t>(sweep);
+  c->has_last = false;
+  c->last_engine = nullptr;
+  if (c->own) c->own->dirty = true;
+  if (c->batch) c->batch->eng.dirty = true;
+  return LC_OK;
+}
+
+// Operator and node ranges of a chain's most recent sweep.
+static int last_ranges(const lc_chain* c, ChainDyn* d, int64_t* win_base) {
+  const Engine* E = c->last_engine;
+  if (!E || !c->has_last) return LC_ESTATE;
+  if (hipMemcpy(d, E->dyn.p + c->last_index, sizeof(ChainDyn), hipMemcpyDeviceToHost) != hipSuccess)
+    return LC_EDEVICE;
+  int64_t wb = 0;
+  for (int i = 0; i < c->last_index; ++i) wb += E->chains[i]->nwin;
+  *win_base = wb;
+  return LC_OK;
+}
+
+int lc_export_ops(const lc_chain* c, int64_t* op_bond, uint64_t* op_time, uint8_t* op_type0,
+                  uint8_t* op_type1, int64_t* n_ops) {
+  if (!c || !n_ops) return LC_EINVAL;
+  ChainDyn d;
+  int64_t wb;
+  int rc = last_ranges(c, &d, &wb);
+  if (rc != LC_OK) return rc;
+  const int64_t have = *n_ops;
+  *n_ops = d.n_ops;
+  if (!op_bond && !op_time && !op_type0 && !op_type1) return LC_OK;
+  if (have < d.n_ops) return LC_ECAPACITY;
+  const Engine* E = c->last_engine;
+  std::vector<uint8_t> ty(static_cast<size_t>(std::max<int64_t>(d.n_ops, 1)));
+  if (op_time && d.n_ops &&
+      hipMemcpy(op_time, E->optime.p + d.op_base, d.n_ops * sizeof(uint64_t), hipMemcpyDeviceToHost) !=
+          hipSuccess)
+    return LC_EDEVICE;
+  if (d.n_ops &&
+      hipMemcpy(ty.data(), E->optype.p + d.op_base, d.n_ops, hipMemcpyDeviceToHost) != hipSuccess)
+    return LC_EDEVICE;
+  for (int64_t q = 0; q < d.n_ops; ++q) {
+    if (op_type0) op_type0[q] = (ty[q] >> 1) & 1;
+    if (op_type1) op_type1[q] = ty[q] & 1;
+  }
+  if (op_bond) {
+    const int64_t W = int64_t(1) << c->w;
+    std::vector<int64_t> os(static_cast<size_t>(c->n_bonds) + 1);
+    for (int64_t b = 0; b <= c->n_bonds; ++b)
+      if (hipMemcpy(&os[b], E->opstart.p + wb + b * W, sizeof(int64_t), hipMemcpyDeviceToHost) !=
+          hipSuccess)
+        return LC_EDEVICE;
+    for (int64_t b = 0; b < c->n_bonds; ++b)
+      for (int64_t q = os[b]; q < os[b + 1]; ++q) op_bond[q - d.op_base] = b;
+  }
+  return LC_OK;
+}
+
+int lc_export_labels(const lc_chain* c, int64_t* labels, int64_t* n_nodes) {
+  if (!c || !n_nodes) return LC_EINVAL;
+  ChainDyn d;
+  int64_t wb;
+  int rc = last_ranges(c, &d, &wb);
+  if (rc != LC_OK) return rc;
+  const int64_t have = *n_nodes;
+  *n_nodes = d.n_nodes;
+  if (!labels) return LC_OK;
+  if (have < d.n_nodes) return LC_ECAPACITY;
+  if (hipMemcpy(labels, c->last_engine->parent.p + d.node_base, d.n_nodes * sizeof(int64_t),
+                hipMemcpyDeviceToHost) != hipSuccess)
+    return LC_EDEVICE;
+  for (int64_t v = 0; v < d.n_nodes; ++v) labels[v] -= d.node_base;
+  return LC_OK;
+}
+
+int lc_export_perm(const lc_chain* c, int64_t* perm, int64_t* n) {
+  if (!c || !n) return LC_EINVAL;
+  const int64_t have = *n;
+  *n = c->two_s > 1 ? c->n_sites : 0;
+  if (!perm || c->two_s == 1) return LC_OK;
+  if (!c->has_last) return LC_ESTATE;
+  if (have < c->n_sites) return LC_ECAPACITY;
+  return hip_err(hipMemcpy(perm, c->perm.p, c->n_sites * sizeof(int64_t), hipMemcpyDeviceToHost));
+}
+
+void lc_free(lc_chain* c) {
+  if (!c) return;
+  if (c->batch) (void)lc_batch_remove(c->batch, c);
+  if (c->own) {
+    c->own->release_all();
+    delete c->own;
+  }
+  for (int q = 0; q < 2; ++q) {
+    c->s0[q].release(c->mem);
+    c->kstart[q].release(c->mem);
+    c->ktime[q].release(c->mem);
+  }
+  c->perm.release(c->mem);
+  delete c;
+}
+
+int lc_batch_create(const lc_alloc* alloc, void* hip_stream, lc_batch** out) {
+  if (!out) return LC_EINVAL;
+  *out = nullptr;
+  if (alloc && (!alloc->alloc || !alloc->free)) return LC_EINVAL;
+  lc_batch* b = new (std::nothrow) lc_batch();
+  if (!b) return LC_ENOMEM;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (!s) {
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+      delete b;
+      return LC_EDEVICE;
+    }
+    b->owns_stream = true;
+  }
+  b->eng.stream = s;
+  b->eng.mem.s = s;
+  if (alloc) {
+    b->eng.mem.a = *alloc;
+    b->eng.mem.user = true;
+  }
+  *out = b;
+  return LC_OK;
+}
+
+int lc_batch_add(lc_batch* b, lc_chain* c) {
+  if (!b || !c) return LC_EINVAL;
+  if (c->batch) return LC_ESTATE;
+  b->eng.chains.push_back(c);
+  c->batch = b;
+  b->eng.dirty = true;
+  return LC_OK;
+}
+
+int lc_batch_remove(lc_batch* b, lc_chain* c) {
+  if (!b || !c) return LC_EINVAL;
+  auto& v = b->eng.chains;
+  auto it = std::find(v.begin(), v.end(), c);
+  if (it == v.end()) return LC_EINVAL;
+  // wait for queued work before the chain leaves
+  (void)hipStreamSynchronize(b->eng.stream);
+  v.erase(it);
+  c->batch = nullptr;
+  if (c->own) c->own->dirty = true;
+  if (c->last_engine == &b->eng) c->last_engine = nullptr;
+  for (lc_chain* o : v)
+    if (o->last_engine == &b->eng) o->last_engine = nullptr;
+  b->eng.dirty = true;
+  return LC_OK;
+}
+
+int lc_batch_size(const lc_batch* b, int* n) {
+  if (!b || !n) return LC_EINVAL;
+  *n = static_cast<int>(b->eng.chains.size());
+  return LC_OK;
+}
+
+int lc_batch_update(lc_batch* b, int64_t n_sweeps, int accumulate) {
+  if (!b || n_sweeps < 0) return LC_EINVAL;
+  // member chains may have been driven alone or on other streams before
+  for (lc_chain* c : b->eng.chains)
+    if (c->stream != b->eng.stream && hipStreamSynchronize(c->stream) != hipSuccess) return LC_EDEVICE;
+  return run_engine(b->eng, n_sweeps, accumulate);
+}
+
+int lc_batch_set_schedule(lc_batch* b, int grid_blocks, int use_graph) {
+  if (!b || grid_blocks < 0) return LC_EINVAL;
+  b->eng.grid = grid_blocks > 0 ? grid_blocks : kDefaultGrid;
+  b->eng.use_graph = use_graph != 0;
+  b->eng.drop_graph();
+  return LC_OK;
+}
+
+void lc_batch_free(lc_batch* b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->eng.stream);
+  for (lc_chain* c : b->eng.chains) {
+    c->batch = nullptr;
+    if (c->last_engine == &b->eng) c->last_engine = nullptr;
+  }
+  b->eng.chains.clear();
+  b->eng.release_all();
+  if (b->owns_stream) (void)hipStreamDestroy(b->eng.stream);
+  delete b;
+}
+
+}  // extern "C"

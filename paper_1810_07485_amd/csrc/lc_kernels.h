@@ -1,0 +1,51 @@
+// lc_kernels.h -- launch interface between the engine (host C++) and the
+// HIP kernels of one loop-cluster sweep.  Internal to the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lc_device.h"
+
+#define LC_SCAN_BLOCKS 1024
+
+struct LcSweepArgs {
+  lc::ChainDesc* descs;       // nchain descriptors
+  const int64_t* win_bases;   // first flat window per chain
+  const int64_t* site_bases;  // first flat subspin per chain
+  const int64_t* spin_bases;  // first flat spin per chain
+  int nchain;
+  int any_split;              // some chain has S > 1/2
+  int64_t nwin, nsites, nspins;
+  int grid_blocks;            // persistent grid size of the node/window loops
+  // flat per-sweep scratch
+  int64_t* opstart;           // nwin + 1
+  int64_t* kflat;             // nwin + 1
+  uint64_t* optime;           // op_cap
+  uint8_t* optype;            // op_cap
+  int64_t* parent;            // node_cap
+  uint8_t* flipb;             // node_cap
+  unsigned long long* acc;    // 5 node_cap
+  int64_t op_cap, node_cap;
+  lc::ChainDyn* dyn;          // nchain
+  int64_t* op_bases;          // nchain
+  int64_t* node_bases;        // nchain
+  int64_t* totals;            // 2: operators, nodes over all chains
+  int64_t* scan_tmp;          // LC_SCAN_BLOCKS + 1
+  uint64_t* stats;            // nchain * ST_WORDS
+  uint32_t* flags;            // overflow / error bits
+  unsigned long long* ring;   // ring_cap records of nchain * ST_WORDS + 1 words
+  uint32_t* ring_ctr;         // next record slot
+  uint32_t ring_cap;
+};
+
+// flags bits
+#define LC_FLAG_OPS 1u       // operator buffer too small
+#define LC_FLAG_NODES 2u     // operator or node buffer too small
+#define LC_FLAG_SYM 4u       // split-spin ends cannot be matched
+#define LC_FLAG_KEPT 8u      // a chain's kept-operator buffer too small
+
+hipError_t lc_launch_sweep(const LcSweepArgs& a, hipStream_t s);
+hipError_t lc_launch_scan(int64_t* a, int64_t n, int64_t* bsum, hipStream_t s);
+hipError_t lc_launch_init_chain(const lc::ChainDesc* d, int64_t n, hipStream_t s);
+hipError_t lc_launch_fill_u64(void* p, int64_t n, uint64_t v, hipStream_t s);

@@ -1,0 +1,935 @@
+// lc_kernels.hip -- HIP kernels (gfx950, wave64) of one continuous-time
+// loop-cluster update of the antiferromagnetic Heisenberg chain
+// (Todo, Matsuo, Shitara, arXiv:1810.07485, Sec. 2 and Sec. 3.2).
+//
+// Every kernel walks a flat index space that spans all resident chains
+// (windows, operators, loop-graph nodes or sites) with a grid-stride loop,
+// reading dynamic sizes from device memory, so one launch serves one chain
+// or a batch and the whole sweep can be captured in a graph.
+//
+// Data layout (flat over chains, chain-contiguous):
+//   window i = (chain, bond b, window k): b-major, 2^w windows per bond
+//   kstart[i]  first kept off-diagonal operator of window i (exclusive scan)
+//   ktime[]    kept operator times, (bond, time) order
+//   opstart[i] first operator of window i; optime[], optype[] (bit 0: type
+//   now, bit 1: type before the flip; 1 = off-diagonal)
+//   node ids per chain: boundary nodes [0, nbn), then lower(q) = nbn + 2q,
+//   upper(q) = nbn + 2q + 1 for operator q; flat id = node_base + local id.
+#include "lc_kernels.h"
+
+#include "lc_device.h"
+
+namespace lc {
+
+constexpr int kBlock = 256;
+constexpr int kCap = 24;  // candidates per window held in LDS; more are redrawn
+
+__device__ inline int lane_id() { return __lane_id(); }
+
+// Add v to *dst once per wave when all lanes agree on dst, else per lane.
+__device__ inline void wave_add_u64(unsigned long long* dst, uint64_t v) {
+  const unsigned long long d0 = __shfl(reinterpret_cast<unsigned long long>(dst), 0);
+  if (__all(reinterpret_cast<unsigned long long>(dst) == d0)) {
+    uint64_t s = v;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane_id() == 0 && s) atomicAdd(dst, static_cast<unsigned long long>(s));
+  } else if (v) {
+    atomicAdd(dst, static_cast<unsigned long long>(v));
+  }
+}
+
+__device__ inline void wave_add_u128(unsigned long long* lo, unsigned long long* hi, uint64_t xlo,
+                                     uint64_t xhi) {
+  const unsigned long long d0 = __shfl(reinterpret_cast<unsigned long long>(lo), 0);
+  if (__all(reinterpret_cast<unsigned long long>(lo) == d0)) {
+    // reduce 128-bit values across the wave
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const uint64_t ol = __shfl_xor(xlo, o), oh = __shfl_xor(xhi, o);
+      const uint64_t s = xlo + ol;
+      xhi = xhi + oh + (s < xlo ? 1u : 0u);
+      xlo = s;
+    }
+    if (lane_id() == 0 && (xlo | xhi)) atomic_add_u128(lo, hi, xlo, xhi);
+  } else if (xlo | xhi) {
+    atomic_add_u128(lo, hi, xlo, xhi);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Bonds touching a subspin x = (j, a): the 2S "left" bonds from (j-1, a') and
+// the 2S "right" bonds to (j+1, c).  For S=1/2 these are bonds j-1 and j.
+__device__ inline int64_t bond_touching(const ChainDesc& D, int64_t x, int idx) {
+  const int64_t ts = D.two_s;
+  const int64_t j = x / ts, a = x - j * ts;
+  if (idx < ts) {
+    const int64_t jl = (j == 0) ? D.L - 1 : j - 1;
+    return (jl * ts + idx) * ts + a;
+  }
+  return (j * ts + a) * ts + (idx - ts);
+}
+__device__ inline int64_t bond_x(const ChainDesc& D, int64_t b) { return b / D.two_s; }
+__device__ inline int64_t bond_y(const ChainDesc& D, int64_t b) {
+  const int64_t ts = D.two_s;
+  const int64_t c = b % ts, x = b / ts, j = x / ts;
+  const int64_t jn = (j + 1 == D.L) ? 0 : j + 1;
+  return jn * ts + c;
+}
+
+// Event (t1, b1) strictly precedes (t2, b2) on the time axis: earlier time,
+// or equal time and smaller bond index.
+__device__ inline bool precedes(uint64_t t1, int64_t b1, uint64_t t2, int64_t b2) {
+  return t1 < t2 || (t1 == t2 && b1 < b2);
+}
+
+// Parity of the kept off-diagonal operators of bond bb that precede (t, b).
+__device__ inline uint32_t kept_parity_before(const int64_t* __restrict__ kstart,
+                                              const uint64_t* __restrict__ ktime, int w,
+                                              int64_t bb, uint64_t k, uint64_t t, int64_t b) {
+  const int64_t i0 = bb << w;
+  const int64_t s = kstart[i0 + static_cast<int64_t>(k)], e = kstart[i0 + static_cast<int64_t>(k) + 1];
+  int64_t n = s - kstart[i0];
+  for (int64_t q = s; q < e; ++q) {
+    if (!precedes(ktime[q], bb, t, b)) break;
+    ++n;
+  }
+  return static_cast<uint32_t>(n & 1);
+}
+
+// Spins of the two ends of bond b just before (t, b) differ?  Kept operators
+// on b itself flip both ends and cancel; the rest come from the other bonds
+// touching either end (labeling rules ii/iii: horizontal graph only when
+// antiparallel).
+__device__ inline bool antiparallel_before(const ChainDesc& D, const uint8_t* __restrict__ s0,
+                                           const int64_t* __restrict__ kstart,
+                                           const uint64_t* __restrict__ ktime, int64_t b,
+                                           uint64_t k, uint64_t t) {
+  const int64_t x = bond_x(D, b), y = bond_y(D, b);
+  uint32_t p = static_cast<uint32_t>(s0[x] ^ s0[y]);
+  const int nt = 2 * D.two_s;
+  for (int q = 0; q < nt; ++q) {
+    const int64_t bx = bond_touching(D, x, q);
+    if (bx != b) p ^= kept_parity_before(kstart, ktime, D.w, bx, k, t, b);
+    const int64_t by = bond_touching(D, y, q);
+    if (by != b) p ^= kept_parity_before(kstart, ktime, D.w, by, k, t, b);
+  }
+  return p & 1u;
+}
+
+// Candidate j of window (b, k): the j-th uniform 64-bit draw placed in the
+// window.  Draw 0 is the upper half of call 0 (its lower half decides the
+// count); draws 2i-1 and 2i are the halves of call i.
+__device__ inline uint64_t cand_time(const ChainDesc& D, int64_t b, uint64_t k, int j, uint64_t v0) {
+  uint64_t v = v0;
+  if (j > 0) {
+    const uint32_t call = static_cast<uint32_t>((j + 1) >> 1);
+    const u32x4 r = philox10(D.seed, static_cast<uint32_t>(k), (DOM_INS << 24) | call,
+                             static_cast<uint32_t>(b), D.sweep);
+    v = (j & 1) ? lo64(r) : hi64(r);
+  }
+  return D.w == 0 ? v : ((k << (64 - D.w)) | (v >> D.w));
+}
+
+// ---------------------------------------------------------------------------
+// Insertion of diagonal operators and removal of old ones (steps 2-6):
+// per (bond, window) the Poisson count from one 64-bit draw against the
+// threshold table, the candidate times, the antiparallel test, then (WRITE)
+// the merge with the kept operators into the operator list.
+template <bool WRITE>
+__global__ __launch_bounds__(kBlock) void k_gen(const ChainDesc* __restrict__ descs,
+                                                const int64_t* __restrict__ win_bases, int nchain,
+                                                int64_t nwin, int64_t* __restrict__ opstart,
+                                                uint64_t* __restrict__ optime,
+                                                uint8_t* __restrict__ optype, int64_t op_cap,
+                                                unsigned long long* __restrict__ stats,
+                                                uint32_t* __restrict__ flags) {
+  __shared__ uint64_t slot[kCap * kBlock];
+  const int tid = threadIdx.x;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+  const int64_t start = static_cast<int64_t>(blockIdx.x) * kBlock + tid;
+  const int64_t iters = (nwin + stride - 1) / stride;
+  for (int64_t it = 0; it < iters; ++it) {
+    const int64_t i = start + it * stride;
+    const bool live = i < nwin;
+    int c = 0;
+    uint32_t ncand = 0, nacc = 0;
+    if (live) {
+      c = chain_of(win_bases, nchain, i);
+      const ChainDesc& D = descs[c];
+      const uint8_t* __restrict__ s0 = D.s0[D.cur];
+      const int64_t* __restrict__ kstart = D.kstart[D.cur];
+      const uint64_t* __restrict__ ktime = D.ktime[D.cur];
+      const int64_t li = i - D.win_base;
+      const int64_t b = li >> D.w;
+      const uint64_t k = static_cast<uint64_t>(li & ((int64_t(1) << D.w) - 1));
+      const u32x4 r0 = philox10(D.seed, static_cast<uint32_t>(k), DOM_INS << 24,
+                                static_cast<uint32_t>(b), D.sweep);
+      const uint64_t u = lo64(r0), v0 = hi64(r0);
+      int n = 0;
+      while (n < D.K && u >= D.T[n]) ++n;
+      ncand = static_cast<uint32_t>(n);
+      const bool inlds = n <= kCap;
+      uint64_t accm = 0;
+      for (int j = 0; j < n; ++j) {
+        const uint64_t t = cand_time(D, b, k, j, v0);
+        if (inlds) slot[j * kBlock + tid] = t;
+        if (antiparallel_before(D, s0, kstart, ktime, b, k, t)) accm |= (uint64_t(1) << j);
+      }
+      nacc = static_cast<uint32_t>(__popcll(accm));
+      const int64_t kb = kstart[li], ke = kstart[li + 1];
+      if (!WRITE) {
+        opstart[i] = (ke - kb) + nacc;
+      } else {
+        const int64_t base = opstart[i];
+        if (opstart[i + 1] > op_cap) {
+          atomicOr(flags, 1u);
+        } else {
+          auto tj = [&](int j) -> uint64_t {
+            return inlds ? slot[j * kBlock + tid] : cand_time(D, b, k, j, v0);
+          };
+          // accepted candidates: rank among accepted + kept at or before
+          for (int j = 0; j < n; ++j) {
+            if (!((accm >> j) & 1)) continue;
+            const uint64_t t = tj(j);
+            int64_t rank = 0;
+            for (int j2 = 0; j2 < n; ++j2) {
+              if (!((accm >> j2) & 1) || j2 == j) continue;
+              const uint64_t t2 = tj(j2);
+              rank += (t2 < t || (t2 == t && j2 < j)) ? 1 : 0;
+            }
+            for (int64_t q = kb; q < ke; ++q) rank += (ktime[q] <= t) ? 1 : 0;
+            optime[base + rank] = t;
+            optype[base + rank] = 0;
+          }
+          // kept operators: their index + accepted candidates strictly before
+          for (int64_t q = kb; q < ke; ++q) {
+            const uint64_t t = ktime[q];
+            int64_t rank = q - kb;
+            for (int j = 0; j < n; ++j)
+              if ((accm >> j) & 1) rank += (tj(j) < t) ? 1 : 0;
+            optime[base + rank] = t;
+            optype[base + rank] = 3;
+          }
+        }
+      }
+    }
+    if (!WRITE) {
+      unsigned long long* st = stats + static_cast<int64_t>(c) * ST_WORDS;
+      wave_add_u64(st + ST_CAND, live ? ncand : 0);
+      wave_add_u64(st + ST_ACC, live ? nacc : 0);
+    }
+  }
+}
+
+// Per-chain operator and node bases after the operator scan.
+__global__ void k_chain_bases(const ChainDesc* __restrict__ descs, int nchain,
+                              const int64_t* __restrict__ opstart, ChainDyn* __restrict__ dyn,
+                              int64_t* __restrict__ op_bases, int64_t* __restrict__ node_bases,
+                              int64_t* __restrict__ totals, int64_t op_cap, int64_t node_cap,
+                              unsigned long long* __restrict__ stats, uint32_t* __restrict__ flags) {
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nchain; c += gridDim.x * blockDim.x) {
+    const ChainDesc& D = descs[c];
+    const int64_t nw = D.n_bonds << D.w;
+    const int64_t ob = opstart[D.win_base], oe = opstart[D.win_base + nw];
+    ChainDyn d;
+    d.op_base = ob;
+    d.n_ops = oe - ob;
+    d.node_base = D.bnode_base + 2 * ob;
+    d.n_nodes = D.nbn + 2 * d.n_ops;
+    dyn[c] = d;
+    op_bases[c] = d.op_base;
+    node_bases[c] = d.node_base;
+    unsigned long long* st = stats + static_cast<int64_t>(c) * ST_WORDS;
+    st[ST_OPS] = static_cast<unsigned long long>(d.n_ops);
+    st[ST_NODES] = static_cast<unsigned long long>(d.n_nodes);
+    st[ST_KEPT_IN] = static_cast<unsigned long long>(D.kstart[D.cur][nw]);
+    if (c == nchain - 1) {
+      totals[0] = oe;                          // operators of all chains
+      totals[1] = d.node_base + d.n_nodes;     // loop-graph nodes of all chains
+      if (oe > op_cap || totals[1] > node_cap) atomicOr(flags, 2u);
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_init_parent(const int64_t* __restrict__ totals,
+                                                         int64_t node_cap,
+                                                         int64_t* __restrict__ parent) {
+  const int64_t n = min(totals[1], node_cap);
+  for (int64_t g = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; g < n;
+       g += static_cast<int64_t>(gridDim.x) * kBlock)
+    parent[g] = g;
+}
+
+// ---------------------------------------------------------------------------
+// Union-find, lock-free: roots are hooked to the smaller root with a CAS on
+// the parent word (parent[x] <= x always, so no cycle can form; leaves never
+// become roots again, which is what makes the finds safe without locks,
+// Sec. 3.2).  Finds halve the path as they go.
+__device__ inline int64_t uf_find(int64_t* parent, int64_t x) {
+  int64_t p = parent[x];
+  while (p != x) {
+    const int64_t gp = parent[p];
+    if (gp != p) parent[x] = gp;  // path halving; gp is an ancestor of x
+    x = p;
+    p = gp;
+  }
+  return x;
+}
+
+__device__ inline void uf_union(int64_t* parent, int64_t a, int64_t b) {
+  a = uf_find(parent, a);
+  b = uf_find(parent, b);
+  while (a != b) {
+    if (a < b) {
+      const int64_t t = a;
+      a = b;
+      b = t;
+    }
+    // hook root a (larger) below b (smaller)
+    const unsigned long long old =
+        atomicCAS(reinterpret_cast<unsigned long long*>(parent + a), static_cast<unsigned long long>(a),
+                  static_cast<unsigned long long>(b));
+    if (static_cast<int64_t>(old) == a) return;
+    a = uf_find(parent, static_cast<int64_t>(old));
+    b = uf_find(parent, b);
+  }
+}
+
+// Next event on subspin x after operator (t, b, q): the earliest operator on
+// any bond touching x that comes after it in (time, bond, index) order.
+// Returns a flat operator index or -1.
+__device__ inline int64_t next_event(const ChainDesc& D, const int64_t* __restrict__ opstart,
+                                     const uint64_t* __restrict__ optime, int64_t x, int64_t b,
+                                     uint64_t k, uint64_t t, int64_t q) {
+  int64_t best = -1, bestb = 0;
+  uint64_t bestt = 0;
+  const int nt = 2 * D.two_s;
+  const int64_t W = int64_t(1) << D.w;
+  for (int s = 0; s < nt; ++s) {
+    const int64_t bb = bond_touching(D, x, s);
+    const int64_t i0 = D.win_base + bb * W;
+    const int64_t bend = opstart[i0 + W];
+    int64_t cand;
+    if (bb == b) {
+      cand = (q + 1 < bend) ? q + 1 : -1;
+    } else {
+      int64_t idx = opstart[i0 + static_cast<int64_t>(k)];
+      const int64_t we = opstart[i0 + static_cast<int64_t>(k) + 1];
+      while (idx < we && precedes(optime[idx], bb, t, b)) ++idx;
+      cand = (idx < bend) ? idx : -1;
+    }
+    if (cand < 0) continue;
+    const uint64_t ct = optime[cand];
+    if (best < 0 || ct < bestt || (ct == bestt && (bb < bestb || (bb == bestb && cand < best)))) {
+      best = cand;
+      bestb = bb;
+      bestt = ct;
+    }
+  }
+  return best;
+}
+
+// Leg linking (Sec. 2, loops as trees of world-line fragments): the upper
+// node of every operator joins, on each of its two subspins, the lower node
+// of the next event there, or the top node of that subspin after the last.
+__global__ __launch_bounds__(kBlock) void k_link_ops(
+    const ChainDesc* __restrict__ descs, const int64_t* __restrict__ win_bases, int nchain,
+    int64_t nwin, const ChainDyn* __restrict__ dyn, const int64_t* __restrict__ opstart,
+    const uint64_t* __restrict__ optime, int64_t* __restrict__ parent,
+    const uint32_t* __restrict__ flags) {
+  if (*flags) return;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < nwin;
+       i += static_cast<int64_t>(gridDim.x) * kBlock) {
+    const int c = chain_of(win_bases, nchain, i);
+    const ChainDesc& D = descs[c];
+    const ChainDyn dy = dyn[c];
+    const int64_t li = i - D.win_base;
+    const int64_t b = li >> D.w;
+    const uint64_t k = static_cast<uint64_t>(li & ((int64_t(1) << D.w) - 1));
+    const int64_t xs[2] = {bond_x(D, b), bond_y(D, b)};
+    for (int64_t q = opstart[i]; q < opstart[i + 1]; ++q) {
+      const uint64_t t = optime[q];
+      const int64_t up = dy.node_base + D.nbn + 2 * (q - dy.op_base) + 1;
+      for (int e = 0; e < 2; ++e) {
+        const int64_t nx = next_event(D, opstart, optime, xs[e], b, k, t, q);
+        const int64_t top = (D.two_s == 1) ? xs[e] : D.n_sites + xs[e];
+        const int64_t to = (nx >= 0) ? dy.node_base + D.nbn + 2 * (nx - dy.op_base)
+                                     : dy.node_base + top;
+        uf_union(parent, up, to);
+      }
+    }
+  }
+}
+
+// Boundary nodes: bottom(x) joins the lower node of the first event on x;
+// an empty subspin joins bottom and top directly (S=1/2: one node, no edge).
+__global__ __launch_bounds__(kBlock) void k_link_sites(
+    const ChainDesc* __restrict__ descs, const int64_t* __restrict__ site_bases, int nchain,
+    int64_t nsites, const ChainDyn* __restrict__ dyn, const int64_t* __restrict__ opstart,
+    const uint64_t* __restrict__ optime, int64_t* __restrict__ parent,
+    const uint32_t* __restrict__ flags) {
+  if (*flags) return;
+  for (int64_t gi = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; gi < nsites;
+       gi += static_cast<int64_t>(gridDim.x) * kBlock) {
+    const int c = chain_of(site_bases, nchain, gi);
+    const ChainDesc& D = descs[c];
+    const ChainDyn dy = dyn[c];
+    const int64_t x = gi - D.site_base;
+    const int64_t W = int64_t(1) << D.w;
+    int64_t best = -1, bestb = 0;
+    uint64_t bestt = 0;
+    for (int s = 0; s < 2 * D.two_s; ++s) {
+      const int64_t bb = bond_touching(D, x, s);
+      const int64_t i0 = D.win_base + bb * W;
+      const int64_t f = opstart[i0];
+      if (f >= opstart[i0 + W]) continue;
+      const uint64_t ct = optime[f];
+      if (best < 0 || ct < bestt || (ct == bestt && bb < bestb)) {
+        best = f;
+        bestb = bb;
+        bestt = ct;
+      }
+    }
+    const int64_t bottom = dy.node_base + x;
+    if (best >= 0)
+      uf_union(parent, bottom, dy.node_base + D.nbn + 2 * (best - dy.op_base));
+    else if (D.two_s > 1)
+      uf_union(parent, bottom, dy.node_base + D.n_sites + x);
+  }
+}
+
+// Symmetrization of the 2S subspins of each spin (split-spin only): a
+// permutation pi drawn uniformly among those that map the up (down)
+// subspins at beta- onto the up (down) subspins at 0+; top(j,a) joins
+// bottom(j, pi(a)).  Fisher-Yates on the SYM stream of the spin.
+__global__ __launch_bounds__(kBlock) void k_symmetrize(
+    const ChainDesc* __restrict__ descs, const int64_t* __restrict__ spin_bases, int nchain,
+    int64_t nspins, const ChainDyn* __restrict__ dyn, int64_t* __restrict__ parent,
+    uint32_t* __restrict__ flags) {
+  if (*flags) return;
+  for (int64_t gj = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; gj < nspins;
+       gj += static_cast<int64_t>(gridDim.x) * kBlock) {
+    const int c = chain_of(spin_bases, nchain, gj);
+    const ChainDesc& D = descs[c];
+    if (D.two_s == 1) continue;
+    const ChainDyn dy = dyn[c];
+    const uint8_t* __restrict__ s0 = D.s0[D.cur];
+    const int64_t* __restrict__ kstart = D.kstart[D.cur];
+    int64_t* __restrict__ perm = D.perm;
+    const int64_t j = gj - D.spin_base;
+    const int ts = D.two_s;
+    const int64_t W = int64_t(1) << D.w;
+    int64_t up_t[8], dn_t[8], up_b[8], dn_b[8];
+    int nut = 0, ndt = 0, nub = 0, ndb = 0;
+    for (int a = 0; a < ts; ++a) {
+      const int64_t x = j * ts + a;
+      uint32_t par = 0;
+      for (int s = 0; s < 2 * ts; ++s) {
+        const int64_t bb = bond_touching(D, x, s);
+        const int64_t i0 = bb * W;
+        par ^= static_cast<uint32_t>((kstart[i0 + W] - kstart[i0]) & 1);
+      }
+      const uint32_t sb = s0[x];
+      if (sb ^ par)
+        up_t[nut++] = x;
+      else
+        dn_t[ndt++] = x;
+      if (sb)
+        up_b[nub++] = x;
+      else
+        dn_b[ndb++] = x;
+    }
+    if (nut != nub) {
+      atomicOr(flags, 4u);  // inconsistent world lines: cannot symmetrize
+      continue;
+    }
+    uint32_t d = 0;
+    uint64_t pending = 0;
+    auto draw = [&](uint64_t m) -> uint64_t {
+      uint64_t u;
+      if ((d & 1u) == 0) {
+        const u32x4 r = philox10(D.seed, static_cast<uint32_t>(j), (DOM_SYM << 24) | (d >> 1), 0u,
+                                 D.sweep);
+        u = lo64(r);
+        pending = hi64(r);
+      } else {
+        u = pending;
+      }
+      ++d;
+      return __umul64hi(u, m);
+    };
+    for (int i = nub - 1; i >= 1; --i) {
+      const int r = static_cast<int>(draw(static_cast<uint64_t>(i + 1)));
+      const int64_t tmp = up_b[i];
+      up_b[i] = up_b[r];
+      up_b[r] = tmp;
+    }
+    for (int i = ndb - 1; i >= 1; --i) {
+      const int r = static_cast<int>(draw(static_cast<uint64_t>(i + 1)));
+      const int64_t tmp = dn_b[i];
+      dn_b[i] = dn_b[r];
+      dn_b[r] = tmp;
+    }
+    for (int q = 0; q < nut; ++q) {
+      perm[up_t[q]] = up_b[q];
+      uf_union(parent, dy.node_base + D.n_sites + up_t[q], dy.node_base + up_b[q]);
+    }
+    for (int q = 0; q < ndt; ++q) {
+      perm[dn_t[q]] = dn_b[q];
+      uf_union(parent, dy.node_base + D.n_sites + dn_t[q], dy.node_base + dn_b[q]);
+    }
+  }
+}
+
+// Full path compression: parent[g] = root = smallest node of g's loop.
+__global__ __launch_bounds__(kBlock) void k_compress(const int64_t* __restrict__ totals,
+                                                      int64_t* __restrict__ parent,
+                                                      const uint32_t* __restrict__ flags) {
+  if (*flags) return;
+  const int64_t n = totals[1];
+  for (int64_t g = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; g < n;
+       g += static_cast<int64_t>(gridDim.x) * kBlock) {
+    int64_t r = g, p = parent[g];
+    while (p != r) {
+      r = p;
+      p = parent[r];
+    }
+    parent[g] = r;
+  }
+}
+
+// Loop-flip bit of a chain-local label: bit (label mod 128) of the Philox
+// block (label / 128) of the FLIP stream of this sweep.
+__device__ inline uint32_t flip_bit(const ChainDesc& D, int64_t label) {
+  const uint64_t q = static_cast<uint64_t>(label) >> 7;
+  const uint32_t i = static_cast<uint32_t>(label & 127);
+  const u32x4 r = philox10(D.seed, static_cast<uint32_t>(q),
+                           (DOM_FLIP << 24) | static_cast<uint32_t>((q >> 32) & 0xFFFFFFu), 0u,
+                           D.sweep);
+  const uint32_t wsel = i >> 5;
+  const uint32_t word = wsel == 0 ? r.x : (wsel == 1 ? r.y : (wsel == 2 ? r.z : r.w));
+  return (word >> (i & 31)) & 1u;
+}
+
+// Roots: draw the flip of each loop, count loops, clear its accumulators.
+__global__ __launch_bounds__(kBlock) void k_roots(
+    const ChainDesc* __restrict__ descs, const int64_t* __restrict__ node_bases, int nchain,
+    const int64_t* __restrict__ totals, const int64_t* __restrict__ parent,
+    uint8_t* __restrict__ flipb, unsigned long long* __restrict__ acc,
+    unsigned long long* __restrict__ stats, const uint32_t* __restrict__ flags) {
+  if (*flags) return;
+  const int64_t n = totals[1];
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+  const int64_t iters = (n + stride - 1) / stride;
+  for (int64_t it = 0; it < iters; ++it) {
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x + it * stride;
+    int c = 0;
+    uint64_t root = 0;
+    if (g < n) {
+      c = chain_of(node_bases, nchain, g);
+      if (parent[g] == g) {
+        root = 1;
+        flipb[g] = static_cast<uint8_t>(flip_bit(descs[c], g - node_bases[c]));
+        acc[5 * g + 0] = 0;
+        acc[5 * g + 1] = 0;
+        acc[5 * g + 2] = 0;
+        acc[5 * g + 3] = 0;
+        acc[5 * g + 4] = 0;
+      }
+    }
+    wave_add_u64(stats + static_cast<int64_t>(c) * ST_WORDS + ST_CLUSTERS, root);
+  }
+}
+
+// Per-loop accumulators (before the flip): nodes, boundary nodes at tau=0+,
+// their spin sum, and the loop length.  Length is a telescoping sum over the
+// loop's nodes: +2t at a lower node (two segments end there), -2t at an
+// upper node (two segments start there) and +2^64 at a top node.
+__global__ __launch_bounds__(kBlock) void k_accum(
+    const ChainDesc* __restrict__ descs, const int64_t* __restrict__ node_bases, int nchain,
+    const ChainDyn* __restrict__ dyn, const int64_t* __restrict__ totals,
+    const int64_t* __restrict__ parent, const uint64_t* __restrict__ optime,
+    unsigned long long* __restrict__ acc, const uint32_t* __restrict__ flags) {
+  if (*flags) return;
+  const int64_t n = totals[1];
+  for (int64_t g = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; g < n;
+       g += static_cast<int64_t>(gridDim.x) * kBlock) {
+    const int c = chain_of(node_bases, nchain, g);
+    const ChainDesc& D = descs[c];
+    const ChainDyn dy = dyn[c];
+    const int64_t v = g - dy.node_base;
+    const int64_t r = parent[g];
+    unsigned long long* a = acc + 5 * r;
+    atomicAdd(a + 0, 1ull);
+    uint64_t xlo = 0, xhi = 0;
+    if (v < D.nbn) {
+      const bool bottom = v < D.n_sites;
+      const bool top = (D.two_s == 1) || !bottom;
+      if (bottom) {
+        atomicAdd(a + 1, 1ull);
+        atomicAdd(a + 2, static_cast<unsigned long long>(2 * static_cast<int64_t>(D.s0[D.cur][v]) - 1));
+      }
+      if (top) xhi = 1;  // + 2^64
+    } else {
+      const int64_t q = (v - D.nbn) >> 1;
+      const uint64_t t = optime[dy.op_base + q];
+      // 2t as 65-bit value
+      const uint64_t tl = t << 1, th = t >> 63;
+      if (((v - D.nbn) & 1) == 0) {
+        xlo = tl;
+        xhi = th;
+      } else {  // -2t modulo 2^128
+        xlo = ~tl + 1;
+        xhi = ~th + (tl == 0 ? 1 : 0);
+      }
+    }
+    if (xlo | xhi) atomic_add_u128(a + 3, a + 4, xlo, xhi);
+  }
+}
+
+// Per-loop squares summed into the chain statistics.
+__global__ __launch_bounds__(kBlock) void k_cluster_sums(
+    const int64_t* __restrict__ node_bases, int nchain, const int64_t* __restrict__ totals,
+    const int64_t* __restrict__ parent, const unsigned long long* __restrict__ acc,
+    unsigned long long* __restrict__ stats, const uint32_t* __restrict__ flags) {
+  if (*flags) return;
+  const int64_t n = totals[1];
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+  const int64_t iters = (n + stride - 1) / stride;
+  for (int64_t it = 0; it < iters; ++it) {
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x + it * stride;
+    int c = 0;
+    uint64_t m2 = 0, n02 = 0, s2lo = 0, s2hi = 0, l2lo = 0, l2hi = 0, sz = 0;
+    if (g < n) {
+      c = chain_of(node_bases, nchain, g);
+      if (parent[g] == g) {
+        const unsigned long long* a = acc + 5 * g;
+        sz = a[0];
+        const int64_t n0 = static_cast<int64_t>(a[1]), m = static_cast<int64_t>(a[2]);
+        m2 = static_cast<uint64_t>(m * m);
+        n02 = static_cast<uint64_t>(n0 * n0);
+        const u128p s2 = mul64x64(sz, sz);
+        s2lo = s2.lo;
+        s2hi = s2.hi;
+        // (len >> 32)^2, len = (a[4] : a[3]) < 2^96
+        const uint64_t l32 = (a[3] >> 32) | (a[4] << 32);
+        const u128p l2 = mul64x64(l32, l32);
+        l2lo = l2.lo;
+        l2hi = l2.hi;
+      }
+    }
+    unsigned long long* st = stats + static_cast<int64_t>(c) * ST_WORDS;
+    wave_add_u64(st + ST_M2, m2);
+    wave_add_u64(st + ST_N0SQ, n02);
+    wave_add_u128(st + ST_SIZE2_LO, st + ST_SIZE2_HI, s2lo, s2hi);
+    wave_add_u128(st + ST_LEN2_LO, st + ST_LEN2_HI, l2lo, l2hi);
+    if (sz) atomicMax(st + ST_MAXSIZE, static_cast<unsigned long long>(sz));
+  }
+}
+
+// Cluster flip (step 7): the type of an operator changes when exactly one of
+// its two loops flips; kept (off-diagonal) operators are counted per window.
+__global__ __launch_bounds__(kBlock) void k_flip_ops(
+    const ChainDesc* __restrict__ descs, const int64_t* __restrict__ win_bases, int nchain,
+    int64_t nwin, const ChainDyn* __restrict__ dyn, const int64_t* __restrict__ opstart,
+    const int64_t* __restrict__ parent, const uint8_t* __restrict__ flipb,
+    uint8_t* __restrict__ optype, int64_t* __restrict__ kcnt, unsigned long long* __restrict__ stats,
+    const uint32_t* __restrict__ flags) {
+  if (*flags) return;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+  const int64_t iters = (nwin + stride - 1) / stride;
+  for (int64_t it = 0; it < iters; ++it) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x + it * stride;
+    int c = 0;
+    uint64_t kept = 0;
+    if (i < nwin) {
+      c = chain_of(win_bases, nchain, i);
+      const ChainDesc& D = descs[c];
+      const ChainDyn dy = dyn[c];
+      for (int64_t q = opstart[i]; q < opstart[i + 1]; ++q) {
+        const int64_t lo = dy.node_base + D.nbn + 2 * (q - dy.op_base);
+        const uint8_t v = optype[q];
+        const uint8_t ty = (v & 1) ^ flipb[parent[lo]] ^ flipb[parent[lo + 1]];
+        optype[q] = static_cast<uint8_t>(ty | (v & 2));
+        kept += ty;
+      }
+      kcnt[i] = static_cast<int64_t>(kept);
+    }
+    wave_add_u64(stats + static_cast<int64_t>(c) * ST_WORDS + ST_KEPT_OUT, kept);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_flip_sites(
+    const ChainDesc* __restrict__ descs, const int64_t* __restrict__ site_bases, int nchain,
+    int64_t nsites, const ChainDyn* __restrict__ dyn, const int64_t* __restrict__ parent,
+    const uint8_t* __restrict__ flipb, unsigned long long* __restrict__ stats,
+    const uint32_t* __restrict__ flags) {
+  if (*flags) return;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+  const int64_t iters = (nsites + stride - 1) / stride;
+  for (int64_t it = 0; it < iters; ++it) {
+    const int64_t gi = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x + it * stride;
+    int c = 0;
+    int64_t m = 0;
+    if (gi < nsites) {
+      c = chain_of(site_bases, nchain, gi);
+      const ChainDesc& D = descs[c];
+      const int64_t x = gi - D.site_base;
+      const uint8_t s = D.s0[D.cur][x] ^ flipb[parent[dyn[c].node_base + x]];
+      D.s0[D.cur ^ 1][x] = s;
+      m = 2 * static_cast<int64_t>(s) - 1;
+    }
+    wave_add_u64(stats + static_cast<int64_t>(c) * ST_WORDS + ST_MAFTER, static_cast<uint64_t>(m));
+  }
+}
+
+// The off-diagonal operators become the next sweep's world lines.
+__global__ __launch_bounds__(kBlock) void k_compact(const ChainDesc* __restrict__ descs,
+                                                     const int64_t* __restrict__ win_bases,
+                                                     int nchain, int64_t nwin,
+                                                     const int64_t* __restrict__ opstart,
+                                                     const uint64_t* __restrict__ optime,
+                                                     const uint8_t* __restrict__ optype,
+                                                     const int64_t* __restrict__ kflat,
+                                                     uint32_t* __restrict__ flags) {
+  if (*flags & 3u) return;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < nwin;
+       i += static_cast<int64_t>(gridDim.x) * kBlock) {
+    const int c = chain_of(win_bases, nchain, i);
+    const ChainDesc& D = descs[c];
+    const int64_t li = i - D.win_base;
+    const int64_t nw = D.n_bonds << D.w;
+    const int64_t kb = kflat[D.win_base];
+    if (kflat[D.win_base + nw] - kb > D.kept_cap) {
+      atomicOr(flags, 8u);
+      continue;
+    }
+    int64_t* __restrict__ ks = D.kstart[D.cur ^ 1];
+    uint64_t* __restrict__ kt = D.ktime[D.cur ^ 1];
+    int64_t o = kflat[i] - kb;
+    ks[li] = o;
+    if (li == nw - 1) ks[nw] = kflat[i + 1] - kb;
+    for (int64_t q = opstart[i]; q < opstart[i + 1]; ++q)
+      if (optype[q] & 1) kt[o++] = optime[q];
+  }
+}
+
+__global__ void k_advance(ChainDesc* __restrict__ descs, int nchain, const uint32_t* __restrict__ flags) {
+  if (*flags) return;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nchain; c += gridDim.x * blockDim.x) {
+    descs[c].sweep += 1;
+    descs[c].cur ^= 1;
+  }
+}
+
+// Append this sweep's statistics and flags to the host-visible record ring.
+__global__ void k_record(const unsigned long long* __restrict__ stats, int64_t nwords,
+                         const uint32_t* __restrict__ flags, unsigned long long* __restrict__ ring,
+                         uint32_t* __restrict__ ring_ctr, uint32_t ring_cap) {
+  const uint32_t slot = *ring_ctr;
+  __syncthreads();
+  if (slot < ring_cap) {
+    unsigned long long* dst = ring + static_cast<int64_t>(slot) * (nwords + 1);
+    for (int64_t i = threadIdx.x; i < nwords; i += blockDim.x) dst[i] = stats[i];
+    if (threadIdx.x == 0) dst[nwords] = *flags;
+  }
+  if (threadIdx.x == 0) *ring_ctr = slot + 1;
+}
+
+__global__ void k_fill_u64(unsigned long long* __restrict__ p, int64_t n, unsigned long long v) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+
+// Initial world lines: Neel state with a random phase, no operators.
+__global__ void k_init_chain(const ChainDesc* __restrict__ d) {
+  const ChainDesc& D = *d;
+  const u32x4 r = philox10(D.seed, 0u, DOM_INIT << 24, 0u, 0u);
+  const int64_t nw = D.n_bonds << D.w;
+  for (int64_t x = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; x < D.n_sites;
+       x += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    D.s0[D.cur][x] = static_cast<uint8_t>(((x / D.two_s) & 1) ^ (r.x & 1u));
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i <= nw;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    D.kstart[D.cur][i] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Device-wide exclusive scan of int64 in place (reduce, scan of block sums,
+// rescan).  a[0..n) -> exclusive prefix, a[n] = total.
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kBlock * kScanItems;
+
+__device__ inline int64_t block_exclusive_scan(int64_t v, int64_t* sh, int64_t& total) {
+  // wave inclusive scan
+  const int lane = lane_id(), wv = threadIdx.x >> 6;
+  int64_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sh[wv] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t s = 0;
+    for (int q = 0; q < kBlock / 64; ++q) {
+      const int64_t t = sh[q];
+      sh[q] = s;
+      s += t;
+    }
+    sh[kBlock / 64] = s;
+  }
+  __syncthreads();
+  const int64_t r = sh[wv] + x - v;
+  total = sh[kBlock / 64];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const int64_t* __restrict__ a, int64_t n,
+                                                         int64_t per_block,
+                                                         int64_t* __restrict__ bsum) {
+  __shared__ int64_t sh[kBlock / 64 + 1];
+  const int64_t s = blockIdx.x * per_block, e = min(n, s + per_block);
+  int64_t acc = 0;
+  for (int64_t i = s + threadIdx.x; i < e; i += kBlock) acc += a[i];
+  int64_t total;
+  block_exclusive_scan(acc, sh, total);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_blocks(int64_t* __restrict__ bsum, int nb) {
+  __shared__ int64_t sh[kBlock / 64 + 1];
+  int64_t carry = 0;
+  for (int base = 0; base < nb; base += kBlock) {
+    const int i = base + threadIdx.x;
+    const int64_t v = i < nb ? bsum[i] : 0;
+    int64_t total;
+    const int64_t ex = block_exclusive_scan(v, sh, total);
+    if (i < nb) bsum[i] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) bsum[nb] = carry;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_apply(int64_t* __restrict__ a, int64_t n,
+                                                        int64_t per_block,
+                                                        const int64_t* __restrict__ bsum) {
+  __shared__ int64_t sh[kBlock / 64 + 1];
+  const int64_t s = blockIdx.x * per_block, e = min(n, s + per_block);
+  int64_t carry = bsum[blockIdx.x];
+  for (int64_t t0 = s; t0 < e; t0 += kScanTile) {
+    int64_t v[kScanItems];
+    int64_t loc = 0;
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) {
+      const int64_t i = t0 + static_cast<int64_t>(threadIdx.x) * kScanItems + q;
+      v[q] = (i < e) ? a[i] : 0;
+      loc += v[q];
+    }
+    int64_t total;
+    int64_t run = carry + block_exclusive_scan(loc, sh, total);
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) {
+      const int64_t i = t0 + static_cast<int64_t>(threadIdx.x) * kScanItems + q;
+      if (i < e) a[i] = run;
+      run += v[q];
+    }
+    carry += total;
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) a[n] = carry;
+}
+
+}  // namespace lc
+
+// ---------------------------------------------------------------------------
+// Host-side launchers.
+using namespace lc;
+
+static int grid_for(int64_t n, int cap_blocks) {
+  int64_t b = (n + kBlock - 1) / kBlock;
+  if (b < 1) b = 1;
+  if (b > cap_blocks) b = cap_blocks;
+  return static_cast<int>(b);
+}
+
+hipError_t lc_launch_scan(int64_t* a, int64_t n, int64_t* bsum, hipStream_t s) {
+  // a has n+1 entries; bsum has kScanBlocks+1 entries
+  const int nb = LC_SCAN_BLOCKS;
+  int64_t per = (n + nb - 1) / nb;
+  per = ((per + kScanTile - 1) / kScanTile) * kScanTile;
+  if (per < kScanTile) per = kScanTile;
+  const int used = static_cast<int>((n + per - 1) / per > 0 ? (n + per - 1) / per : 1);
+  hipLaunchKernelGGL(k_scan_reduce, dim3(used), dim3(kBlock), 0, s, a, n, per, bsum);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kBlock), 0, s, bsum, used);
+  hipLaunchKernelGGL(k_scan_apply, dim3(used), dim3(kBlock), 0, s, a, n, per, bsum);
+  return hipGetLastError();
+}
+
+hipError_t lc_launch_sweep(const LcSweepArgs& A, hipStream_t s) {
+  const int G = A.grid_blocks;
+  unsigned long long* st = reinterpret_cast<unsigned long long*>(A.stats);
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(A.nchain * ST_WORDS, 64)), dim3(kBlock), 0, s, st,
+                     static_cast<int64_t>(A.nchain) * ST_WORDS, 0ull);
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s,
+                     reinterpret_cast<unsigned long long*>(A.flags), 1, 0ull);
+  // 1. count operators per window, 2. scan
+  hipLaunchKernelGGL((k_gen<false>), dim3(grid_for(A.nwin, G)), dim3(kBlock), 0, s, A.descs,
+                     A.win_bases, A.nchain, A.nwin, A.opstart, A.optime, A.optype, A.op_cap, st,
+                     A.flags);
+  (void)lc_launch_scan(A.opstart, A.nwin, A.scan_tmp, s);
+  hipLaunchKernelGGL(k_chain_bases, dim3(grid_for(A.nchain, 64)), dim3(kBlock), 0, s, A.descs,
+                     A.nchain, A.opstart, A.dyn, A.op_bases, A.node_bases, A.totals, A.op_cap,
+                     A.node_cap, st, A.flags);
+  // 3. write operators
+  hipLaunchKernelGGL((k_gen<true>), dim3(grid_for(A.nwin, G)), dim3(kBlock), 0, s, A.descs,
+                     A.win_bases, A.nchain, A.nwin, A.opstart, A.optime, A.optype, A.op_cap, st,
+                     A.flags);
+  // 4. loop graph and union-find
+  hipLaunchKernelGGL(k_init_parent, dim3(G), dim3(kBlock), 0, s, A.totals, A.node_cap, A.parent);
+  hipLaunchKernelGGL(k_link_ops, dim3(grid_for(A.nwin, G)), dim3(kBlock), 0, s, A.descs,
+                     A.win_bases, A.nchain, A.nwin, A.dyn, A.opstart, A.optime, A.parent, A.flags);
+  hipLaunchKernelGGL(k_link_sites, dim3(grid_for(A.nsites, G)), dim3(kBlock), 0, s, A.descs,
+                     A.site_bases, A.nchain, A.nsites, A.dyn, A.opstart, A.optime, A.parent,
+                     A.flags);
+  if (A.any_split)
+    hipLaunchKernelGGL(k_symmetrize, dim3(grid_for(A.nspins, G)), dim3(kBlock), 0, s, A.descs,
+                       A.spin_bases, A.nchain, A.nspins, A.dyn, A.parent, A.flags);
+  hipLaunchKernelGGL(k_compress, dim3(G), dim3(kBlock), 0, s, A.totals, A.parent, A.flags);
+  // 5. flips and estimators
+  hipLaunchKernelGGL(k_roots, dim3(G), dim3(kBlock), 0, s, A.descs, A.node_bases, A.nchain,
+                     A.totals, A.parent, A.flipb, A.acc, st, A.flags);
+  hipLaunchKernelGGL(k_accum, dim3(G), dim3(kBlock), 0, s, A.descs, A.node_bases, A.nchain, A.dyn,
+                     A.totals, A.parent, A.optime, A.acc, A.flags);
+  hipLaunchKernelGGL(k_cluster_sums, dim3(G), dim3(kBlock), 0, s, A.node_bases, A.nchain,
+                     A.totals, A.parent, A.acc, st, A.flags);
+  hipLaunchKernelGGL(k_flip_ops, dim3(grid_for(A.nwin, G)), dim3(kBlock), 0, s, A.descs,
+                     A.win_bases, A.nchain, A.nwin, A.dyn, A.opstart, A.parent, A.flipb,
+                     A.optype, A.kflat, st, A.flags);
+  hipLaunchKernelGGL(k_flip_sites, dim3(grid_for(A.nsites, G)), dim3(kBlock), 0, s, A.descs,
+                     A.site_bases, A.nchain, A.nsites, A.dyn, A.parent, A.flipb, st, A.flags);
+  // 6. next world lines
+  (void)lc_launch_scan(A.kflat, A.nwin, A.scan_tmp, s);
+  hipLaunchKernelGGL(k_compact, dim3(grid_for(A.nwin, G)), dim3(kBlock), 0, s, A.descs,
+                     A.win_bases, A.nchain, A.nwin, A.opstart, A.optime, A.optype, A.kflat,
+                     A.flags);
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, A.descs, A.nchain, A.flags);
+  hipLaunchKernelGGL(k_record, dim3(1), dim3(kBlock), 0, s, st,
+                     static_cast<int64_t>(A.nchain) * ST_WORDS, A.flags, A.ring, A.ring_ctr,
+                     A.ring_cap);
+  return hipGetLastError();
+}
+
+hipError_t lc_launch_init_chain(const ChainDesc* d, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_chain, dim3(grid_for(n, 1024)), dim3(kBlock), 0, s, d);
+  return hipGetLastError();
+}
+
+hipError_t lc_launch_fill_u64(void* p, int64_t n, uint64_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 1024)), dim3(kBlock), 0, s,
+                     reinterpret_cast<unsigned long long*>(p), n, static_cast<unsigned long long>(v));
+  return hipGetLastError();
+}
