@@ -1,0 +1,153 @@
+#!/usr/bin/env python3
+"""Throughput of the loop-cluster update on one MI355X.
+
+Workload: the medium single chain -- S=1/2 antiferromagnetic Heisenberg
+chain, J=1, L=65,536 spins, periodic, beta=4,096, Philox seed 1, random
+initial Neel world lines (about 1.86e8 operators per sweep).  One step is
+one full sweep of the hot path (insertion, operator merge, linking,
+union-find, flip, estimators, next world lines) on device-resident state.
+
+Prints one JSON line: operators ("graph vertices") per second over exactly
+--steps sweeps after --warmup untimed sweeps, with the per-phase HIP-event
+timing of those same sweeps, the roofline entry of the dominant kernel and
+the CPU oracle's rate on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "graph vertices/sec & MC sweeps/sec on 1 GPU, batched/served vs plain; HBM GB/s"
+WORKLOAD = dict(workload="S=1/2 Heisenberg chain L=65536 beta=4096 seed 1, single chain",
+                L=65536, S=0.5, beta=4096.0, seed=1)
+HBM_PEAK_GBS = 8000.0
+
+
+def phase_bytes(n_ops, n_nodes, n_clusters, n_win, n_sites, kept_in, kept_out):
+    """Algorithmic HBM bytes of each phase for one sweep (compulsory traffic:
+    every array element the phase must read or write, counted once).
+
+    n_ops operators, n_nodes loop-graph nodes, n_win (bond, window) cells,
+    kept_in / kept_out off-diagonal operators before / after the sweep."""
+    N, V, Cl, W, S = n_ops, n_nodes, n_clusters, n_win, n_sites
+    return {
+        "gen_count": 8 * kept_in + 8 * W + S + 8 * W,
+        "scan_ops": 24 * W,
+        "gen_write": 8 * kept_in + 8 * W + 8 * W + 9 * N,
+        "init_parent": 8 * V,
+        "link_ops": 8 * W + 8 * N + 16 * V,
+        "link_sites": 24 * S,
+        "compress": 16 * V,
+        "roots": 8 * V + 41 * Cl,
+        "accum": 8 * V + 8 * N + S + 80 * Cl,
+        "cluster_sums": 8 * V + 40 * Cl,
+        "flip": 16 * W + 2 * N + 16 * N + Cl + 10 * S,
+        "scan_kept": 24 * W,
+        "compact": 24 * W + 9 * N + 8 * kept_out,
+        "setup": 0,
+    }
+
+
+def cpu_baseline(lc, L=4096, beta=4096.0, seed=1, gpu_therm=30, budget_s=12.0):
+    """The oracle's rate on a bounded sample: a chain with the benchmark's
+    beta and L=4,096 (1/16 of the spins), thermalised on the GPU, imported
+    into the oracle, then timed for whole oracle sweeps (>= 1, up to about
+    budget_s seconds).  Single-threaded C."""
+    from oracle import oracle
+
+    g = lc.Chain(L, 0.5, beta, seed)
+    g.update(gpu_therm, accumulate=False)
+    st = g.export_state()
+    o = oracle.Chain(L, 0.5, beta, seed)
+    o.import_state(*st)
+    ops, t0 = 0, time.perf_counter()
+    while True:
+        ops += o.sweep()["n_ops"]
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    g.close()
+    return {"value": ops / el, "unit": "vertices/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle sweeps of a thermalised S=1/2 chain L={L} beta={beta:g} "
+                      f"(same beta, 1/16 of the spins): {ops} operators in {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the chain is not "
+              "sharded across GPUs in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1810_07485_amd as lc
+
+    torch.cuda.set_device(0)
+    w = WORKLOAD
+    chain = lc.Chain(w["L"], w["S"], w["beta"], w["seed"])
+    chain.update(args.warmup, accumulate=False)
+    chain.reset_measurements()
+    chain.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    chain.update(args.steps, accumulate=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    m = chain.measure()
+    prof, nsw = chain.profile()
+    last = chain.last_sweep()
+    assert m["n_sweeps"] == args.steps == nsw
+    ops_total = m["mean_ops"] * args.steps
+    n_sites = chain.n_sites
+    frag_total = (2 * m["mean_ops"] + n_sites) * args.steps
+    wtab = lc.lc_debug_window_table(w["beta"])
+    n_win = chain.n_bonds << wtab[0]
+    pb = phase_bytes(m["mean_ops"], 2 * m["mean_ops"] + n_sites, m["mean_clusters"], n_win,
+                     n_sites, last["n_kept_in"], last["n_kept_out"])
+    phase_ms = {k: v / nsw for k, v in prof.items()}
+    dom = max(phase_ms, key=phase_ms.get)
+    achieved = pb[dom] / (phase_ms[dom] * 1e-3) / 1e9
+    total_bytes = sum(pb.values())
+    out = {
+        "metric": METRIC,
+        "value": ops_total / el,
+        "unit": "vertices/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": dict(w),
+        "sweeps_per_s": args.steps / el,
+        "fragments_per_s": frag_total / el,
+        "hbm_gbs_algorithmic": total_bytes * args.steps / el / 1e9,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": pb[dom], "avg_ms": phase_ms[dom]},
+        "phase_ms": phase_ms,
+        "observables": {"e": m["e"], "ops_per_L_beta": m["mean_ops"] / (w["L"] * w["beta"]),
+                        "loops_per_L_beta": m["mean_clusters"] / (w["L"] * w["beta"])},
+    }
+    chain.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(lc)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -183,6 +183,20 @@ void lc_batch_free(lc_batch *b);
 /* Same launch configuration for a chain run alone. */
 int lc_set_schedule(lc_chain *c, int grid_blocks, int use_graph);
 
+/* ---- timing -------------------------------------------------------------
+ * With profiling on, every sweep is launched directly (no graph) with a HIP
+ * event recorded on the chain's (or batch's) stream between its phases, and
+ * the host synchronises once per sweep.  lc_profile returns, for each of the
+ * lc_phase_count() phases (names from lc_phase_name), the summed
+ * milliseconds over the completed sweeps since profiling was switched on, and
+ * that sweep count.  Results of the sweeps are unchanged. */
+int lc_phase_count(void);
+const char *lc_phase_name(int phase);
+int lc_set_profiling(lc_chain *c, int on);
+int lc_profile(const lc_chain *c, double *ms, int n, int64_t *sweeps);
+int lc_batch_set_profiling(lc_batch *b, int on);
+int lc_batch_profile(const lc_batch *b, double *ms, int n, int64_t *sweeps);
+
 /* ---- testing hooks (host code of the library, no GPU needed) ------------
  * The library's host twin of its Philox4x32-10 and its Poisson window rule:
  * w (2^w windows per bond), mu = beta / 2^(w+1) and thresholds

@@ -103,6 +103,12 @@ def load():
         "lc_batch_set_schedule": ([vp, C.c_int, C.c_int], C.c_int),
         "lc_batch_free": ([vp], None),
         "lc_set_schedule": ([vp, C.c_int, C.c_int], C.c_int),
+        "lc_phase_count": ([], C.c_int),
+        "lc_phase_name": ([C.c_int], C.c_char_p),
+        "lc_set_profiling": ([vp, C.c_int], C.c_int),
+        "lc_profile": ([vp, C.POINTER(C.c_double), C.c_int, p64], C.c_int),
+        "lc_batch_set_profiling": ([vp, C.c_int], C.c_int),
+        "lc_batch_profile": ([vp, C.POINTER(C.c_double), C.c_int, p64], C.c_int),
         "lc_debug_philox": ([C.c_uint64, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)], C.c_int),
         "lc_debug_window_table": ([C.c_double, pi, C.POINTER(C.c_double), pu64, pi], C.c_int),
     }
@@ -225,6 +231,13 @@ class Chain:
         _check(load().lc_set_schedule(self._h, int(grid_blocks), int(bool(use_graph))),
                "lc_set_schedule")
 
+    def set_profiling(self, on: bool = True):
+        _check(load().lc_set_profiling(self._h, int(bool(on))), "lc_set_profiling")
+
+    def profile(self) -> tuple:
+        """(dict phase -> summed ms, sweeps) since profiling was switched on."""
+        return _profile(load().lc_profile, self._h)
+
     def export_state(self):
         lib = load()
         n, sw = C.c_int64(0), C.c_int64()
@@ -319,3 +332,22 @@ class Batch:
     def set_schedule(self, grid_blocks: int = 0, use_graph: bool = True):
         _check(load().lc_batch_set_schedule(self._h, int(grid_blocks), int(bool(use_graph))),
                "lc_batch_set_schedule")
+
+    def set_profiling(self, on: bool = True):
+        _check(load().lc_batch_set_profiling(self._h, int(bool(on))), "lc_batch_set_profiling")
+
+    def profile(self) -> tuple:
+        return _profile(load().lc_batch_profile, self._h)
+
+
+def phase_names() -> list:
+    lib = load()
+    return [lib.lc_phase_name(i).decode() for i in range(lib.lc_phase_count())]
+
+
+def _profile(fn, h) -> tuple:
+    names = phase_names()
+    ms = (C.c_double * len(names))()
+    n = C.c_int64()
+    _check(fn(h, ms, len(names), C.byref(n)), "lc_profile")
+    return dict(zip(names, list(ms))), n.value

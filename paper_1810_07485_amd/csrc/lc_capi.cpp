@@ -174,6 +174,16 @@ struct Engine {
   hipGraphExec_t gexec = nullptr;
   bool graph_ok = false;
   std::vector<unsigned long long> hring;
+  // per-phase timing (HIP events between the kernels of each sweep)
+  bool profiling = false;
+  std::vector<hipEvent_t> ev;
+  std::vector<double> ph_ms;
+  int64_t ph_sweeps = 0;
+
+  void drop_events() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    ev.clear();
+  }
 
   void drop_graph() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -182,6 +192,7 @@ struct Engine {
   }
   void release_all() {
     drop_graph();
+    drop_events();
     descs.release(mem);
     win_bases.release(mem);
     site_bases.release(mem);
@@ -349,10 +360,19 @@ LcSweepArgs sweep_args(Engine& E) {
   A.ring = E.ring.p;
   A.ring_ctr = E.ring_ctr.p;
   A.ring_cap = kRing;
+  A.events = E.profiling ? reinterpret_cast<void**>(E.ev.data()) : nullptr;
   return A;
 }
 
 int launch_one(Engine& E) {
+  if (E.profiling) {
+    if (E.ev.empty()) {
+      E.ev.resize(LC_PH_COUNT + 1);
+      for (auto& e : E.ev)
+        if (hipEventCreate(&e) != hipSuccess) return LC_EDEVICE;
+    }
+    return hip_err(lc_launch_sweep(sweep_args(E), E.stream));
+  }
   if (E.use_graph) {
     if (!E.graph_ok) {
       hipGraph_t g = nullptr;
@@ -429,7 +449,8 @@ int run_engine(Engine& E, int64_t n_sweeps, int accumulate) {
   int64_t done = 0;
   int stuck = 0;
   while (done < n_sweeps) {
-    const int chunk = static_cast<int>(std::min<int64_t>(n_sweeps - done, kRing));
+    const int chunk =
+        E.profiling ? 1 : static_cast<int>(std::min<int64_t>(n_sweeps - done, kRing));
     if (hip_err(lc_launch_fill_u64(E.ring_ctr.p, 1, 0, E.stream)) != LC_OK) return LC_EDEVICE;
     for (int q = 0; q < chunk; ++q)
       if ((rc = launch_one(E)) != LC_OK) return rc;
@@ -446,6 +467,15 @@ int run_engine(Engine& E, int64_t n_sweeps, int accumulate) {
       for (int i = 0; i < nch; ++i) apply_record(E.chains[i], r + i * lc::ST_WORDS, accumulate != 0);
     }
     done += ok;
+    if (E.profiling && ok) {
+      if (E.ph_ms.size() != LC_PH_COUNT) E.ph_ms.assign(LC_PH_COUNT, 0.0);
+      for (int p = 0; p < LC_PH_COUNT; ++p) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, E.ev[p], E.ev[p + 1]) != hipSuccess) return LC_EDEVICE;
+        E.ph_ms[p] += ms;
+      }
+      E.ph_sweeps += 1;
+    }
     for (int i = 0; i < nch; ++i) {
       lc_chain* c = E.chains[i];
       c->last_engine = &E;
@@ -917,6 +947,54 @@ int lc_batch_set_schedule(lc_batch* b, int grid_blocks, int use_graph) {
   b->eng.use_graph = use_graph != 0;
   b->eng.drop_graph();
   return LC_OK;
+}
+
+static const char* const kPhaseNames[LC_PH_COUNT] = {
+    "setup",     "gen_count", "scan_ops", "gen_write",    "init_parent", "link_ops",  "link_sites",
+    "compress",  "roots",     "accum",    "cluster_sums", "flip",        "scan_kept", "compact"};
+
+int lc_phase_count(void) { return LC_PH_COUNT; }
+
+const char* lc_phase_name(int phase) {
+  return (phase >= 0 && phase < LC_PH_COUNT) ? kPhaseNames[phase] : nullptr;
+}
+
+static int set_profiling(Engine* E, int on) {
+  E->profiling = on != 0;
+  E->ph_ms.assign(LC_PH_COUNT, 0.0);
+  E->ph_sweeps = 0;
+  if (!E->profiling) E->drop_events();
+  return LC_OK;
+}
+
+static int get_profile(const Engine* E, double* ms, int n, int64_t* sweeps) {
+  if (!ms || n < 0) return LC_EINVAL;
+  for (int p = 0; p < n && p < LC_PH_COUNT; ++p)
+    ms[p] = p < static_cast<int>(E->ph_ms.size()) ? E->ph_ms[p] : 0.0;
+  if (sweeps) *sweeps = E->ph_sweeps;
+  return LC_OK;
+}
+
+int lc_set_profiling(lc_chain* c, int on) {
+  if (!c) return LC_EINVAL;
+  Engine* E = own_engine(c);
+  if (!E) return LC_ENOMEM;
+  return set_profiling(E, on);
+}
+
+int lc_profile(const lc_chain* c, double* ms, int n, int64_t* sweeps) {
+  if (!c || !c->own) return LC_EINVAL;
+  return get_profile(c->own, ms, n, sweeps);
+}
+
+int lc_batch_set_profiling(lc_batch* b, int on) {
+  if (!b) return LC_EINVAL;
+  return set_profiling(&b->eng, on);
+}
+
+int lc_batch_profile(const lc_batch* b, double* ms, int n, int64_t* sweeps) {
+  if (!b) return LC_EINVAL;
+  return get_profile(&b->eng, ms, n, sweeps);
 }
 
 void lc_batch_free(lc_batch* b) {

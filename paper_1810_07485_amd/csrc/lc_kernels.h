@@ -37,6 +37,27 @@ struct LcSweepArgs {
   unsigned long long* ring;   // ring_cap records of nchain * ST_WORDS + 1 words
   uint32_t* ring_ctr;         // next record slot
   uint32_t ring_cap;
+  void** events;              // LC_PH_COUNT + 1 hipEvent_t marks, or null
+};
+
+// Phases of a sweep, in launch order; events[p] is recorded before phase p
+// and events[LC_PH_COUNT] after the last.
+enum LcPhase {
+  LC_PH_SETUP = 0,
+  LC_PH_GEN_COUNT,
+  LC_PH_SCAN_OPS,
+  LC_PH_GEN_WRITE,
+  LC_PH_INIT_PARENT,
+  LC_PH_LINK_OPS,
+  LC_PH_LINK_SITES,
+  LC_PH_COMPRESS,
+  LC_PH_ROOTS,
+  LC_PH_ACCUM,
+  LC_PH_CLUSTER_SUMS,
+  LC_PH_FLIP,
+  LC_PH_SCAN_KEPT,
+  LC_PH_COMPACT,
+  LC_PH_COUNT
 };
 
 // flags bits

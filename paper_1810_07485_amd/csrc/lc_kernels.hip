@@ -57,6 +57,47 @@ __device__ inline void wave_add_u128(unsigned long long* lo, unsigned long long*
   }
 }
 
+__device__ inline uint64_t wave_max_u64(uint64_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint64_t w = __shfl_xor(v, o);
+    v = w > v ? w : v;
+  }
+  return v;
+}
+
+// Per-thread partial sums of one chain's statistics.  A thread walks its
+// items in increasing flat index, so it meets each chain in one stretch: the
+// sums go to the chain's counters when the thread moves on to another chain
+// (per lane, rare) and once at the end (one atomic per wave when the wave
+// agrees on the chain).
+template <int N>
+struct Partial {
+  int c;
+  uint64_t v[N];
+  __device__ Partial() : c(-1) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = 0;
+  }
+  __device__ void at(int cn, unsigned long long* stats, const int (&idx)[N]) {
+    if (cn == c) return;
+    if (c >= 0) {
+#pragma unroll
+      for (int i = 0; i < N; ++i)
+        if (v[i]) atomicAdd(stats + static_cast<int64_t>(c) * ST_WORDS + idx[i], v[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = 0;
+    c = cn;
+  }
+  // convergent: every lane of the wave must call it
+  __device__ void flush(unsigned long long* stats, const int (&idx)[N]) {
+    const int cf = c < 0 ? 0 : c;
+#pragma unroll
+    for (int i = 0; i < N; ++i) wave_add_u64(stats + static_cast<int64_t>(cf) * ST_WORDS + idx[i], v[i]);
+  }
+};
+
 // ---------------------------------------------------------------------------
 // Bonds touching a subspin x = (j, a): the 2S "left" bonds from (j-1, a') and
 // the 2S "right" bonds to (j+1, c).  For S=1/2 these are bonds j-1 and j.
@@ -148,14 +189,13 @@ __global__ __launch_bounds__(kBlock) void k_gen(const ChainDesc* __restrict__ de
   const int tid = threadIdx.x;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
   const int64_t start = static_cast<int64_t>(blockIdx.x) * kBlock + tid;
-  const int64_t iters = (nwin + stride - 1) / stride;
-  for (int64_t it = 0; it < iters; ++it) {
-    const int64_t i = start + it * stride;
-    const bool live = i < nwin;
-    int c = 0;
+  constexpr int kIdx[2] = {ST_CAND, ST_ACC};
+  Partial<2> part;
+  for (int64_t i = start; i < nwin; i += stride) {
     uint32_t ncand = 0, nacc = 0;
-    if (live) {
-      c = chain_of(win_bases, nchain, i);
+    {
+      const int c = chain_of(win_bases, nchain, i);
+      if (!WRITE) part.at(c, stats, kIdx);
       const ChainDesc& D = descs[c];
       const uint8_t* __restrict__ s0 = D.s0[D.cur];
       const int64_t* __restrict__ kstart = D.kstart[D.cur];
@@ -214,12 +254,10 @@ __global__ __launch_bounds__(kBlock) void k_gen(const ChainDesc* __restrict__ de
         }
       }
     }
-    if (!WRITE) {
-      unsigned long long* st = stats + static_cast<int64_t>(c) * ST_WORDS;
-      wave_add_u64(st + ST_CAND, live ? ncand : 0);
-      wave_add_u64(st + ST_ACC, live ? nacc : 0);
-    }
+    part.v[0] += ncand;
+    part.v[1] += nacc;
   }
+  if (!WRITE) part.flush(stats, kIdx);
 }
 
 // Per-chain operator and node bases after the operator scan.
@@ -520,26 +558,22 @@ __global__ __launch_bounds__(kBlock) void k_roots(
     unsigned long long* __restrict__ stats, const uint32_t* __restrict__ flags) {
   if (*flags) return;
   const int64_t n = totals[1];
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
-  const int64_t iters = (n + stride - 1) / stride;
-  for (int64_t it = 0; it < iters; ++it) {
-    const int64_t g = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x + it * stride;
-    int c = 0;
-    uint64_t root = 0;
-    if (g < n) {
-      c = chain_of(node_bases, nchain, g);
-      if (parent[g] == g) {
-        root = 1;
-        flipb[g] = static_cast<uint8_t>(flip_bit(descs[c], g - node_bases[c]));
-        acc[5 * g + 0] = 0;
-        acc[5 * g + 1] = 0;
-        acc[5 * g + 2] = 0;
-        acc[5 * g + 3] = 0;
-        acc[5 * g + 4] = 0;
-      }
-    }
-    wave_add_u64(stats + static_cast<int64_t>(c) * ST_WORDS + ST_CLUSTERS, root);
+  constexpr int kIdx[1] = {ST_CLUSTERS};
+  Partial<1> part;
+  for (int64_t g = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; g < n;
+       g += static_cast<int64_t>(gridDim.x) * kBlock) {
+    if (parent[g] != g) continue;
+    const int c = chain_of(node_bases, nchain, g);
+    part.at(c, stats, kIdx);
+    part.v[0] += 1;
+    flipb[g] = static_cast<uint8_t>(flip_bit(descs[c], g - node_bases[c]));
+    acc[5 * g + 0] = 0;
+    acc[5 * g + 1] = 0;
+    acc[5 * g + 2] = 0;
+    acc[5 * g + 3] = 0;
+    acc[5 * g + 4] = 0;
   }
+  part.flush(stats, kIdx);
 }
 
 // Per-loop accumulators (before the flip): nodes, boundary nodes at tau=0+,
@@ -595,36 +629,53 @@ __global__ __launch_bounds__(kBlock) void k_cluster_sums(
     unsigned long long* __restrict__ stats, const uint32_t* __restrict__ flags) {
   if (*flags) return;
   const int64_t n = totals[1];
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
-  const int64_t iters = (n + stride - 1) / stride;
-  for (int64_t it = 0; it < iters; ++it) {
-    const int64_t g = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x + it * stride;
-    int c = 0;
-    uint64_t m2 = 0, n02 = 0, s2lo = 0, s2hi = 0, l2lo = 0, l2hi = 0, sz = 0;
-    if (g < n) {
-      c = chain_of(node_bases, nchain, g);
-      if (parent[g] == g) {
-        const unsigned long long* a = acc + 5 * g;
-        sz = a[0];
-        const int64_t n0 = static_cast<int64_t>(a[1]), m = static_cast<int64_t>(a[2]);
-        m2 = static_cast<uint64_t>(m * m);
-        n02 = static_cast<uint64_t>(n0 * n0);
-        const u128p s2 = mul64x64(sz, sz);
-        s2lo = s2.lo;
-        s2hi = s2.hi;
-        // (len >> 32)^2, len = (a[4] : a[3]) < 2^96
-        const uint64_t l32 = (a[3] >> 32) | (a[4] << 32);
-        const u128p l2 = mul64x64(l32, l32);
-        l2lo = l2.lo;
-        l2hi = l2.hi;
-      }
+  int cc = -1;
+  uint64_t m2 = 0, n02 = 0, s2lo = 0, s2hi = 0, l2lo = 0, l2hi = 0, mx = 0;
+  auto flush_lane = [&]() {
+    unsigned long long* st = stats + static_cast<int64_t>(cc) * ST_WORDS;
+    if (m2) atomicAdd(st + ST_M2, m2);
+    if (n02) atomicAdd(st + ST_N0SQ, n02);
+    if (s2lo | s2hi) atomic_add_u128(st + ST_SIZE2_LO, st + ST_SIZE2_HI, s2lo, s2hi);
+    if (l2lo | l2hi) atomic_add_u128(st + ST_LEN2_LO, st + ST_LEN2_HI, l2lo, l2hi);
+    if (mx) atomicMax(st + ST_MAXSIZE, mx);
+    m2 = n02 = s2lo = s2hi = l2lo = l2hi = mx = 0;
+  };
+  for (int64_t g = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; g < n;
+       g += static_cast<int64_t>(gridDim.x) * kBlock) {
+    if (parent[g] != g) continue;
+    const int c = chain_of(node_bases, nchain, g);
+    if (c != cc) {
+      if (cc >= 0) flush_lane();
+      cc = c;
     }
-    unsigned long long* st = stats + static_cast<int64_t>(c) * ST_WORDS;
-    wave_add_u64(st + ST_M2, m2);
-    wave_add_u64(st + ST_N0SQ, n02);
-    wave_add_u128(st + ST_SIZE2_LO, st + ST_SIZE2_HI, s2lo, s2hi);
-    wave_add_u128(st + ST_LEN2_LO, st + ST_LEN2_HI, l2lo, l2hi);
-    if (sz) atomicMax(st + ST_MAXSIZE, static_cast<unsigned long long>(sz));
+    const unsigned long long* a = acc + 5 * g;
+    const uint64_t sz = a[0];
+    const int64_t n0 = static_cast<int64_t>(a[1]), m = static_cast<int64_t>(a[2]);
+    m2 += static_cast<uint64_t>(m * m);
+    n02 += static_cast<uint64_t>(n0 * n0);
+    const u128p q2 = mul64x64(sz, sz);
+    s2lo += q2.lo;
+    s2hi += q2.hi + (s2lo < q2.lo ? 1u : 0u);
+    // (len >> 32)^2, len = (a[4] : a[3]) < 2^96
+    const uint64_t l32 = (a[3] >> 32) | (a[4] << 32);
+    const u128p l2 = mul64x64(l32, l32);
+    l2lo += l2.lo;
+    l2hi += l2.hi + (l2lo < l2.lo ? 1u : 0u);
+    mx = sz > mx ? sz : mx;
+  }
+  // one atomic per wave and statistic
+  const int cf = cc < 0 ? 0 : cc;
+  unsigned long long* st = stats + static_cast<int64_t>(cf) * ST_WORDS;
+  wave_add_u64(st + ST_M2, m2);
+  wave_add_u64(st + ST_N0SQ, n02);
+  wave_add_u128(st + ST_SIZE2_LO, st + ST_SIZE2_HI, s2lo, s2hi);
+  wave_add_u128(st + ST_LEN2_LO, st + ST_LEN2_HI, l2lo, l2hi);
+  const unsigned long long d0 = __shfl(reinterpret_cast<unsigned long long>(st), 0);
+  if (__all(reinterpret_cast<unsigned long long>(st) == d0)) {
+    const uint64_t wm = wave_max_u64(mx);
+    if (lane_id() == 0 && wm) atomicMax(st + ST_MAXSIZE, wm);
+  } else if (mx) {
+    atomicMax(st + ST_MAXSIZE, mx);
   }
 }
 
@@ -637,27 +688,26 @@ __global__ __launch_bounds__(kBlock) void k_flip_ops(
     uint8_t* __restrict__ optype, int64_t* __restrict__ kcnt, unsigned long long* __restrict__ stats,
     const uint32_t* __restrict__ flags) {
   if (*flags) return;
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
-  const int64_t iters = (nwin + stride - 1) / stride;
-  for (int64_t it = 0; it < iters; ++it) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x + it * stride;
-    int c = 0;
+  constexpr int kIdx[1] = {ST_KEPT_OUT};
+  Partial<1> part;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < nwin;
+       i += static_cast<int64_t>(gridDim.x) * kBlock) {
+    const int c = chain_of(win_bases, nchain, i);
+    part.at(c, stats, kIdx);
+    const ChainDesc& D = descs[c];
+    const ChainDyn dy = dyn[c];
     uint64_t kept = 0;
-    if (i < nwin) {
-      c = chain_of(win_bases, nchain, i);
-      const ChainDesc& D = descs[c];
-      const ChainDyn dy = dyn[c];
-      for (int64_t q = opstart[i]; q < opstart[i + 1]; ++q) {
-        const int64_t lo = dy.node_base + D.nbn + 2 * (q - dy.op_base);
-        const uint8_t v = optype[q];
-        const uint8_t ty = (v & 1) ^ flipb[parent[lo]] ^ flipb[parent[lo + 1]];
-        optype[q] = static_cast<uint8_t>(ty | (v & 2));
-        kept += ty;
-      }
-      kcnt[i] = static_cast<int64_t>(kept);
+    for (int64_t q = opstart[i]; q < opstart[i + 1]; ++q) {
+      const int64_t lo = dy.node_base + D.nbn + 2 * (q - dy.op_base);
+      const uint8_t v = optype[q];
+      const uint8_t ty = (v & 1) ^ flipb[parent[lo]] ^ flipb[parent[lo + 1]];
+      optype[q] = static_cast<uint8_t>(ty | (v & 2));
+      kept += ty;
     }
-    wave_add_u64(stats + static_cast<int64_t>(c) * ST_WORDS + ST_KEPT_OUT, kept);
+    kcnt[i] = static_cast<int64_t>(kept);
+    part.v[0] += kept;
   }
+  part.flush(stats, kIdx);
 }
 
 __global__ __launch_bounds__(kBlock) void k_flip_sites(
@@ -666,22 +716,19 @@ __global__ __launch_bounds__(kBlock) void k_flip_sites(
     const uint8_t* __restrict__ flipb, unsigned long long* __restrict__ stats,
     const uint32_t* __restrict__ flags) {
   if (*flags) return;
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
-  const int64_t iters = (nsites + stride - 1) / stride;
-  for (int64_t it = 0; it < iters; ++it) {
-    const int64_t gi = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x + it * stride;
-    int c = 0;
-    int64_t m = 0;
-    if (gi < nsites) {
-      c = chain_of(site_bases, nchain, gi);
-      const ChainDesc& D = descs[c];
-      const int64_t x = gi - D.site_base;
-      const uint8_t s = D.s0[D.cur][x] ^ flipb[parent[dyn[c].node_base + x]];
-      D.s0[D.cur ^ 1][x] = s;
-      m = 2 * static_cast<int64_t>(s) - 1;
-    }
-    wave_add_u64(stats + static_cast<int64_t>(c) * ST_WORDS + ST_MAFTER, static_cast<uint64_t>(m));
+  constexpr int kIdx[1] = {ST_MAFTER};
+  Partial<1> part;
+  for (int64_t gi = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; gi < nsites;
+       gi += static_cast<int64_t>(gridDim.x) * kBlock) {
+    const int c = chain_of(site_bases, nchain, gi);
+    part.at(c, stats, kIdx);
+    const ChainDesc& D = descs[c];
+    const int64_t x = gi - D.site_base;
+    const uint8_t s = D.s0[D.cur][x] ^ flipb[parent[dyn[c].node_base + x]];
+    D.s0[D.cur ^ 1][x] = s;
+    part.v[0] += static_cast<uint64_t>(2 * static_cast<int64_t>(s) - 1);
   }
+  part.flush(stats, kIdx);
 }
 
 // The off-diagonal operators become the next sweep's world lines.
@@ -872,47 +919,65 @@ hipError_t lc_launch_scan(int64_t* a, int64_t n, int64_t* bsum, hipStream_t s) {
 hipError_t lc_launch_sweep(const LcSweepArgs& A, hipStream_t s) {
   const int G = A.grid_blocks;
   unsigned long long* st = reinterpret_cast<unsigned long long*>(A.stats);
+  // optional timing marks between phases (see LcPhase)
+  auto mark = [&](int ph) {
+    if (A.events) (void)hipEventRecord(static_cast<hipEvent_t>(A.events[ph]), s);
+  };
+  mark(LC_PH_SETUP);
   hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(A.nchain * ST_WORDS, 64)), dim3(kBlock), 0, s, st,
                      static_cast<int64_t>(A.nchain) * ST_WORDS, 0ull);
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s,
                      reinterpret_cast<unsigned long long*>(A.flags), 1, 0ull);
   // 1. count operators per window, 2. scan
+  mark(LC_PH_GEN_COUNT);
   hipLaunchKernelGGL((k_gen<false>), dim3(grid_for(A.nwin, G)), dim3(kBlock), 0, s, A.descs,
                      A.win_bases, A.nchain, A.nwin, A.opstart, A.optime, A.optype, A.op_cap, st,
                      A.flags);
+  mark(LC_PH_SCAN_OPS);
   (void)lc_launch_scan(A.opstart, A.nwin, A.scan_tmp, s);
   hipLaunchKernelGGL(k_chain_bases, dim3(grid_for(A.nchain, 64)), dim3(kBlock), 0, s, A.descs,
                      A.nchain, A.opstart, A.dyn, A.op_bases, A.node_bases, A.totals, A.op_cap,
                      A.node_cap, st, A.flags);
   // 3. write operators
+  mark(LC_PH_GEN_WRITE);
   hipLaunchKernelGGL((k_gen<true>), dim3(grid_for(A.nwin, G)), dim3(kBlock), 0, s, A.descs,
                      A.win_bases, A.nchain, A.nwin, A.opstart, A.optime, A.optype, A.op_cap, st,
                      A.flags);
   // 4. loop graph and union-find
+  mark(LC_PH_INIT_PARENT);
   hipLaunchKernelGGL(k_init_parent, dim3(G), dim3(kBlock), 0, s, A.totals, A.node_cap, A.parent);
+  mark(LC_PH_LINK_OPS);
   hipLaunchKernelGGL(k_link_ops, dim3(grid_for(A.nwin, G)), dim3(kBlock), 0, s, A.descs,
                      A.win_bases, A.nchain, A.nwin, A.dyn, A.opstart, A.optime, A.parent, A.flags);
+  mark(LC_PH_LINK_SITES);
   hipLaunchKernelGGL(k_link_sites, dim3(grid_for(A.nsites, G)), dim3(kBlock), 0, s, A.descs,
                      A.site_bases, A.nchain, A.nsites, A.dyn, A.opstart, A.optime, A.parent,
                      A.flags);
   if (A.any_split)
     hipLaunchKernelGGL(k_symmetrize, dim3(grid_for(A.nspins, G)), dim3(kBlock), 0, s, A.descs,
                        A.spin_bases, A.nchain, A.nspins, A.dyn, A.parent, A.flags);
+  mark(LC_PH_COMPRESS);
   hipLaunchKernelGGL(k_compress, dim3(G), dim3(kBlock), 0, s, A.totals, A.parent, A.flags);
   // 5. flips and estimators
+  mark(LC_PH_ROOTS);
   hipLaunchKernelGGL(k_roots, dim3(G), dim3(kBlock), 0, s, A.descs, A.node_bases, A.nchain,
                      A.totals, A.parent, A.flipb, A.acc, st, A.flags);
+  mark(LC_PH_ACCUM);
   hipLaunchKernelGGL(k_accum, dim3(G), dim3(kBlock), 0, s, A.descs, A.node_bases, A.nchain, A.dyn,
                      A.totals, A.parent, A.optime, A.acc, A.flags);
+  mark(LC_PH_CLUSTER_SUMS);
   hipLaunchKernelGGL(k_cluster_sums, dim3(G), dim3(kBlock), 0, s, A.node_bases, A.nchain,
                      A.totals, A.parent, A.acc, st, A.flags);
+  mark(LC_PH_FLIP);
   hipLaunchKernelGGL(k_flip_ops, dim3(grid_for(A.nwin, G)), dim3(kBlock), 0, s, A.descs,
                      A.win_bases, A.nchain, A.nwin, A.dyn, A.opstart, A.parent, A.flipb,
                      A.optype, A.kflat, st, A.flags);
   hipLaunchKernelGGL(k_flip_sites, dim3(grid_for(A.nsites, G)), dim3(kBlock), 0, s, A.descs,
                      A.site_bases, A.nchain, A.nsites, A.dyn, A.parent, A.flipb, st, A.flags);
   // 6. next world lines
+  mark(LC_PH_SCAN_KEPT);
   (void)lc_launch_scan(A.kflat, A.nwin, A.scan_tmp, s);
+  mark(LC_PH_COMPACT);
   hipLaunchKernelGGL(k_compact, dim3(grid_for(A.nwin, G)), dim3(kBlock), 0, s, A.descs,
                      A.win_bases, A.nchain, A.nwin, A.opstart, A.optime, A.optype, A.kflat,
                      A.flags);
@@ -920,6 +985,7 @@ hipError_t lc_launch_sweep(const LcSweepArgs& A, hipStream_t s) {
   hipLaunchKernelGGL(k_record, dim3(1), dim3(kBlock), 0, s, st,
                      static_cast<int64_t>(A.nchain) * ST_WORDS, A.flags, A.ring, A.ring_ctr,
                      A.ring_cap);
+  mark(LC_PH_COUNT);
   return hipGetLastError();
 }
 

@@ -1,0 +1,120 @@
+"""Batching: every member of a batch evolves exactly as it does alone.
+
+Independent chains of uneven L, beta and S advanced by one launch sequence
+per sweep must produce, chain by chain, the same world lines and the same
+integers as when each runs alone; joining and leaving between sweeps (the
+serving pattern) must not perturb the others.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+CASES = [(16, 0.5, 8.0, 1), (64, 0.5, 64.0, 2), (130, 0.5, 100.5, 3), (1024, 0.5, 20.0, 4),
+         (8, 1.0, 16.5, 5), (4, 4.0, 1.0, 6), (2048, 0.5, 512.0, 7), (6, 1.5, 3.0, 8)]
+
+
+@pytest.fixture(scope="module")
+def lc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    import paper_1810_07485_amd as lc
+    lc.load()
+    return lc
+
+
+def alone(lc, case, sweeps):
+    c = lc.Chain(*case)
+    stats = []
+    for _ in range(sweeps):
+        c.update(1)
+        stats.append(c.last_sweep())
+    return c.export_state(), stats, c.measure()
+
+
+def same_state(a, b):
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(np.asarray(x), np.asarray(y))
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_equals_alone(lc, graph):
+    sweeps = 6
+    ref = [alone(lc, case, sweeps) for case in CASES]
+    b = lc.Batch()
+    b.set_schedule(0, graph)
+    chains = [lc.Chain(*case) for case in CASES]
+    for c in chains:
+        b.add(c)
+    stats = [[] for _ in chains]
+    for _ in range(sweeps):
+        b.update(1)
+        for i, c in enumerate(chains):
+            stats[i].append(c.last_sweep())
+    for i, c in enumerate(chains):
+        same_state(c.export_state(), ref[i][0])
+        assert stats[i] == ref[i][1], CASES[i]
+        assert c.measure() == ref[i][2]
+    b.close()
+
+
+def test_batch_multi_sweep_update(lc):
+    """n sweeps in one call (one host synchronisation per chunk of sweeps)."""
+    ref = [alone(lc, case, 9) for case in CASES[:4]]
+    b = lc.Batch()
+    chains = [lc.Chain(*case) for case in CASES[:4]]
+    for c in chains:
+        b.add(c)
+    b.update(9)
+    for i, c in enumerate(chains):
+        same_state(c.export_state(), ref[i][0])
+        assert c.last_sweep() == ref[i][1][-1]
+    b.close()
+
+
+def test_join_and_leave_between_sweeps(lc):
+    """Chains join and leave a running batch; each matches its alone-run."""
+    sweeps = {i: 4 + (i % 3) for i in range(len(CASES))}
+    ref = {i: alone(lc, CASES[i], sweeps[i]) for i in sweeps}
+    b = lc.Batch()
+    chains = {i: lc.Chain(*CASES[i]) for i in sweeps}
+    done = {i: 0 for i in sweeps}
+    active = []
+    pending = list(sweeps)
+    step = 0
+    while pending or active:
+        # admit up to two new chains every other step
+        if pending and step % 2 == 0:
+            for _ in range(2):
+                if pending:
+                    i = pending.pop(0)
+                    b.add(chains[i])
+                    active.append(i)
+        b.update(1)
+        step += 1
+        for i in list(active):
+            done[i] += 1
+            if done[i] == sweeps[i]:
+                b.remove(chains[i])
+                active.remove(i)
+    for i in sweeps:
+        same_state(chains[i].export_state(), ref[i][0])
+        assert chains[i].last_sweep() == ref[i][1][-1]
+        assert chains[i].measure() == ref[i][2]
+    b.close()
+
+
+def test_chain_alone_after_batch(lc):
+    """A chain run in a batch, removed, then run alone continues exactly."""
+    ref = alone(lc, CASES[3], 7)
+    c = lc.Chain(*CASES[3])
+    c.update(2)
+    b = lc.Batch()
+    b.add(c)
+    b.update(3)
+    b.remove(c)
+    c.update(2)
+    same_state(c.export_state(), ref[0])
+    assert c.last_sweep() == ref[1][-1]
+    b.close()

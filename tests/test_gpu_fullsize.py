@@ -1,0 +1,112 @@
+"""Parity at the benchmark's full size (L=65,536, beta=4,096), through the C ABI.
+
+The oracle needs minutes per sweep at this size, so its results are stored
+as digests written by tests/golden/make_digest_golden.py (which calls only
+the oracle): every integer of each sweep's statistics and SHA-256 digests of
+the world lines, the operators and the loop labels.  The library runs in the
+launch configuration the benchmark times (graph replay, default grid).
+A later, thermalised sweep is checked on sampled operators (spins just below
+each sampled operator recomputed from the exported world lines) and on
+identities that hold at any size.
+"""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "digest_L65536_beta4096.json")
+
+
+def sha(*arrays):
+    h = hashlib.sha256()
+    for a in arrays:
+        h.update(np.ascontiguousarray(a).tobytes())
+    return h.hexdigest()
+
+
+@pytest.fixture(scope="module")
+def lc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    import paper_1810_07485_amd as lc
+    lc.load()
+    return lc
+
+
+@pytest.fixture(scope="module")
+def chain(lc):
+    with open(GOLD) as f:
+        g = json.load(f)
+    c = lc.Chain(g["L"], g["S"], g["beta"], g["seed"])
+    c.gold = g
+    return c
+
+
+def test_thresholds_match_golden(lc, chain):
+    w, mu, T = lc.lc_debug_window_table(chain.gold["beta"])
+    assert w == chain.gold["window_w"] and mu == chain.gold["mu"]
+    assert [str(t) for t in T] == chain.gold["thresholds"]
+
+
+def test_sweeps_bit_exact_against_oracle_digests(chain):
+    for s, rec in enumerate(chain.gold["sweeps"]):
+        chain.update(1)
+        st = chain.last_sweep()
+        assert st == rec["stats"], s
+        s0, off, kt, sw = chain.export_state()
+        assert sw == rec["next_sweep"]
+        assert sha(s0, off, kt) == rec["state"], s
+        b, t, ty0, _ = chain.export_ops()
+        assert sha(b.astype(np.int64), t, ty0) == rec["ops"], s
+        assert sha(chain.export_labels()) == rec["labels"], s
+
+
+def test_thermalised_sweep_properties(chain):
+    """After more sweeps: sampled operators sit on antiparallel spins before
+    and after the flip, every site keeps an even number of jumps, and the
+    node, loop and energy identities hold."""
+    chain.update(12)
+    s0, off, kt, sw = chain.export_state()
+    chain.update(1)
+    st = chain.last_sweep()
+    b, t, ty0, ty1 = chain.export_ops()
+    L = chain.L
+    assert st["n_nodes"] == L + 2 * st["n_ops"]
+    assert st["n_ops"] == st["n_kept_in"] + st["n_acc"]
+    assert int(ty0.sum()) == st["n_kept_in"] and int(ty1.sum()) == st["n_kept_out"]
+    # kept operators are exactly the previous world lines
+    np.testing.assert_array_equal(t[ty0 == 1], kt)
+    # operators ordered by (bond, time)
+    assert (np.diff(b) >= 0).all()
+    same = np.diff(b) == 0
+    assert (np.diff(t)[same] >= 0).all()
+    # even number of jumps on every site after the flip
+    bk = b[ty1 == 1]
+    par = np.bincount(bk, minlength=L) + np.bincount((bk + 1) % L, minlength=L)
+    assert (par % 2 == 0).all()
+    # sampled operators: spins of both ends just below them, from s0 and the
+    # off-diagonal operators of the neighbouring bonds (before the flip)
+    bounds = np.searchsorted(b, np.arange(L + 1))
+    rng = np.random.default_rng(5)
+    for k in rng.choice(len(b), 300, replace=False):
+        bb, tt = int(b[k]), int(t[k])
+        x, y = bb, (bb + 1) % L
+        def par_before(bond):
+            lo, hi = bounds[bond], bounds[bond + 1]
+            tb, ob = t[lo:hi], ty0[lo:hi]
+            n = np.searchsorted(tb, tt, side="left")
+            cnt = int(ob[:n].sum())
+            # equal times: earlier bond index comes first
+            if bond < bb:
+                n2 = np.searchsorted(tb, tt, side="right")
+                cnt += int(ob[n:n2].sum())
+            return cnt & 1
+        sx = int(s0[x]) ^ par_before((bb - 1) % L)
+        sy = int(s0[y]) ^ par_before((bb + 1) % L)
+        assert sx != sy, k
+    e = 0.25 - st["n_ops"] / (chain.beta * L)
+    assert abs(e - (0.25 - np.log(2))) < 5e-3
