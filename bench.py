@@ -44,10 +44,14 @@ def phase_bytes(n_ops, n_nodes, n_clusters, n_win, n_sites, kept_in, kept_out):
         "link_ops": 8 * W + 8 * N + 16 * V,
         "link_sites": 24 * S,
         "compress": 16 * V,
-        "roots": 8 * V + 41 * Cl,
-        "accum": 8 * V + 8 * N + S + 80 * Cl,
-        "cluster_sums": 8 * V + 40 * Cl,
-        "flip": 16 * W + 2 * N + 16 * N + Cl + 10 * S,
+        # roots: count roots per chunk (8V), assign loop index, flip bit and
+        # chain, clear the four record words (8V + 8C + 1C + 4C + 32C)
+        "roots": 16 * V + 45 * Cl,
+        # accum: parent word per node, time and type per operator, bottom
+        # spins; read-modify-write of 4 words per loop record
+        "accum": 8 * V + 9 * N + S + 64 * Cl,
+        "cluster_sums": 36 * Cl,
+        "flip": 8 * V + 2 * N + Cl + 8 * W + 2 * S,
         "scan_kept": 24 * W,
         "compact": 24 * W + 9 * N + 8 * kept_out,
         "setup": 0,

@@ -169,7 +169,9 @@ struct Engine {
   DBuf<uint64_t> optime;
   DBuf<uint8_t> optype, flipb;
   DBuf<unsigned long long> acc;
-  int64_t nwin = 0, nsites = 0, nspins = 0, sum_nbn = 0, op_cap = 0, node_cap = 0;
+  DBuf<int64_t> rcnt;
+  DBuf<int32_t> root_chain;
+  int64_t nwin = 0, nsites = 0, nspins = 0, sum_nbn = 0, op_cap = 0, node_cap = 0, root_cap = 0;
   bool any_split = false;
   hipGraphExec_t gexec = nullptr;
   bool graph_ok = false;
@@ -213,6 +215,8 @@ struct Engine {
     optype.release(mem);
     flipb.release(mem);
     acc.release(mem);
+    rcnt.release(mem);
+    root_chain.release(mem);
   }
 };
 
@@ -260,6 +264,23 @@ int64_t ops_estimate(const lc_chain* c) {
   return c->n_kept + static_cast<int64_t>(cand + 6.0 * std::sqrt(cand + 1.0)) + 1024;
 }
 
+// Loop records (accumulators, flip bits, chain of each loop) for cap loops.
+int ensure_roots(Engine& E, int64_t cap) {
+  if (E.root_cap >= cap) return LC_OK;
+  E.flipb.release(E.mem);
+  E.acc.release(E.mem);
+  E.root_chain.release(E.mem);
+  if (!(E.flipb.ensure(E.mem, cap) && E.acc.ensure(E.mem, 4 * static_cast<size_t>(cap)) &&
+        E.root_chain.ensure(E.mem, cap))) {
+    E.root_cap = 0;
+    E.dirty = true;
+    return LC_ENOMEM;
+  }
+  E.root_cap = cap;
+  E.drop_graph();
+  return LC_OK;
+}
+
 // (Re)build the flat layout of an engine's chains and upload descriptors.
 int layout(Engine& E) {
   const int n = static_cast<int>(E.chains.size());
@@ -295,10 +316,7 @@ int layout(Engine& E) {
     E.optime.release(m);
     E.optype.release(m);
     E.parent.release(m);
-    E.flipb.release(m);
-    E.acc.release(m);
-    ok = E.optime.ensure(m, ops) && E.optype.ensure(m, ops) && E.parent.ensure(m, nc2) &&
-         E.flipb.ensure(m, nc2) && E.acc.ensure(m, 5 * static_cast<size_t>(nc2));
+    ok = E.optime.ensure(m, ops) && E.optype.ensure(m, ops) && E.parent.ensure(m, nc2);
     if (!ok) {
       E.op_cap = E.node_cap = 0;
       return LC_ENOMEM;
@@ -306,6 +324,10 @@ int layout(Engine& E) {
     E.op_cap = ops;
     E.node_cap = nc2;
   }
+  // loops are about 0.29 of the nodes at low temperature; grown on overflow
+  if (!E.rcnt.ensure(m, static_cast<size_t>(E.node_cap / 4096 + 2)) ||
+      ensure_roots(E, E.node_cap / 2 + 65536) != LC_OK)
+    return LC_ENOMEM;
   E.nwin = nwin;
   E.nsites = nsites;
   E.nspins = nspins;
@@ -348,6 +370,9 @@ LcSweepArgs sweep_args(Engine& E) {
   A.parent = E.parent.p;
   A.flipb = E.flipb.p;
   A.acc = E.acc.p;
+  A.root_chain = E.root_chain.p;
+  A.root_cap = E.root_cap;
+  A.rcnt = E.rcnt.p;
   A.op_cap = E.op_cap;
   A.node_cap = E.node_cap;
   A.dyn = E.dyn.p;
@@ -501,17 +526,23 @@ int run_engine(Engine& E, int64_t n_sweeps, int accumulate) {
       E.optime.release(E.mem);
       E.optype.release(E.mem);
       E.parent.release(E.mem);
-      E.flipb.release(E.mem);
-      E.acc.release(E.mem);
       if (!(E.optime.ensure(E.mem, ops) && E.optype.ensure(E.mem, ops) &&
-            E.parent.ensure(E.mem, nodes) && E.flipb.ensure(E.mem, nodes) &&
-            E.acc.ensure(E.mem, 5 * static_cast<size_t>(nodes)))) {
+            E.parent.ensure(E.mem, nodes))) {
         E.op_cap = E.node_cap = 0;
         E.dirty = true;
         return LC_ENOMEM;
       }
       E.op_cap = ops;
       E.node_cap = nodes;
+    }
+    if (bad & LC_FLAG_ROOTS) {
+      int64_t cnt = 0;
+      const int64_t nch = (E.node_cap + 4095) / 4096;
+      if (hipMemcpy(&cnt, E.rcnt.p + nch, sizeof(cnt), hipMemcpyDeviceToHost) != hipSuccess)
+        return LC_EDEVICE;
+      const int64_t need = static_cast<int64_t>(cnt);
+      if ((rc = ensure_roots(E, std::max<int64_t>(need + need / 4 + 65536, 2 * E.root_cap))) != LC_OK)
+        return rc;
     }
     if (bad & LC_FLAG_KEPT) {
       for (int i = 0; i < nch; ++i) {
@@ -550,7 +581,9 @@ size_t footprint_bytes(int64_t L, int two_s, double beta) {
   const double ops = kept + 0.5 * n_bonds * beta + 6 * std::sqrt(0.5 * n_bonds * beta + 1) + 1024;
   const double nodes = nbn + 2 * ops;
   const double state = 2 * n_sites + 2 * 8 * (nwin + 1) + 2 * 8 * kept + 8 * n_sites;
-  const double scratch = 2 * 8 * (nwin + 1) + 9 * ops + nodes * (8 + 1 + 40);
+  // window scans, operators (time + type), parent words, loop records for
+  // up to half the nodes (32 B accumulators + flip byte + chain index)
+  const double scratch = 2 * 8 * (nwin + 1) + 9 * ops + nodes * 8 + (nodes / 2) * (32 + 1 + 4);
   return static_cast<size_t>(state + scratch + (1 << 20));
 }
 
@@ -847,7 +880,8 @@ int lc_export_labels(const lc_chain* c, int64_t* labels, int64_t* n_nodes) {
   if (hipMemcpy(labels, c->last_engine->parent.p + d.node_base, d.n_nodes * sizeof(int64_t),
                 hipMemcpyDeviceToHost) != hipSuccess)
     return LC_EDEVICE;
-  for (int64_t v = 0; v < d.n_nodes; ++v) labels[v] -= d.node_base;
+  // parent words: a root holds a negative code, every other node its root
+  for (int64_t v = 0; v < d.n_nodes; ++v) labels[v] = labels[v] < 0 ? v : labels[v] - d.node_base;
   return LC_OK;
 }
 

@@ -24,9 +24,11 @@ struct LcSweepArgs {
   uint64_t* optime;           // op_cap
   uint8_t* optype;            // op_cap
   int64_t* parent;            // node_cap
-  uint8_t* flipb;             // node_cap
-  unsigned long long* acc;    // 5 node_cap
-  int64_t op_cap, node_cap;
+  uint8_t* flipb;             // root_cap: flip bit of each loop
+  unsigned long long* acc;    // 4 root_cap: loop accumulators
+  int32_t* root_chain;        // root_cap: chain of each loop
+  int64_t op_cap, node_cap, root_cap;
+  int64_t* rcnt;              // loops per node chunk, scanned (node_cap / 4096 + 2)
   lc::ChainDyn* dyn;          // nchain
   int64_t* op_bases;          // nchain
   int64_t* node_bases;        // nchain
@@ -65,6 +67,7 @@ enum LcPhase {
 #define LC_FLAG_NODES 2u     // operator or node buffer too small
 #define LC_FLAG_SYM 4u       // split-spin ends cannot be matched
 #define LC_FLAG_KEPT 8u      // a chain's kept-operator buffer too small
+#define LC_FLAG_ROOTS 16u    // loop-record buffer too small
 
 hipError_t lc_launch_sweep(const LcSweepArgs& a, hipStream_t s);
 hipError_t lc_launch_scan(int64_t* a, int64_t n, int64_t* bsum, hipStream_t s);

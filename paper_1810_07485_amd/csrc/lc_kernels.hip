@@ -550,36 +550,125 @@ __device__ inline uint32_t flip_bit(const ChainDesc& D, int64_t label) {
   return (word >> (i & 31)) & 1u;
 }
 
-// Roots: draw the flip of each loop, count loops, clear its accumulators.
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kBlock * kScanItems;
+
+__device__ inline int64_t block_exclusive_scan(int64_t v, int64_t* sh, int64_t& total) {
+  // wave inclusive scan
+  const int lane = lane_id(), wv = threadIdx.x >> 6;
+  int64_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sh[wv] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t s = 0;
+    for (int q = 0; q < kBlock / 64; ++q) {
+      const int64_t t = sh[q];
+      sh[q] = s;
+      s += t;
+    }
+    sh[kBlock / 64] = s;
+  }
+  __syncthreads();
+  const int64_t r = sh[wv] + x - v;
+  total = sh[kBlock / 64];
+  __syncthreads();
+  return r;
+}
+
+// After compression the parent word of every node names its loop: a root
+// (the loop's smallest node) holds -1 - i, i the loop's compact index, and
+// every other node holds its root.
+__device__ inline int64_t loop_index(const int64_t* __restrict__ parent, int64_t g) {
+  int64_t p = parent[g];
+  if (p >= 0) p = parent[p];
+  return -1 - p;
+}
+
+// Roots get compact loop indices in node order: roots are counted per chunk
+// of kRootChunk nodes, the counts are scanned, and each chunk numbers its
+// roots from its offset (no shared counter).
+constexpr int kRootPer = 16;                      // nodes per thread
+constexpr int kRootChunk = kBlock * kRootPer;     // nodes per chunk
+
+__global__ __launch_bounds__(kBlock) void k_root_count(const int64_t* __restrict__ totals,
+                                                        const int64_t* __restrict__ parent,
+                                                        int64_t nchunks, int64_t* __restrict__ rcnt,
+                                                        const uint32_t* __restrict__ flags) {
+  __shared__ int64_t sh[kBlock / 64 + 1];
+  if (*flags) return;
+  const int64_t n = totals[1];
+  for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+    const int64_t g0 = ch * kRootChunk + static_cast<int64_t>(threadIdx.x) * kRootPer;
+    int64_t cnt = 0;
+    for (int s = 0; s < kRootPer; ++s) {
+      const int64_t g = g0 + s;
+      if (g < n && parent[g] == g) ++cnt;
+    }
+    int64_t total;
+    block_exclusive_scan(cnt, sh, total);
+    if (threadIdx.x == 0) rcnt[ch] = total;
+  }
+}
+
+// Roots: compact index (stored as the code -1 - index in the root's parent
+// word), flip bit of the loop, cleared accumulators, loop count.
 __global__ __launch_bounds__(kBlock) void k_roots(
     const ChainDesc* __restrict__ descs, const int64_t* __restrict__ node_bases, int nchain,
-    const int64_t* __restrict__ totals, const int64_t* __restrict__ parent,
-    uint8_t* __restrict__ flipb, unsigned long long* __restrict__ acc,
-    unsigned long long* __restrict__ stats, const uint32_t* __restrict__ flags) {
+    const int64_t* __restrict__ totals, int64_t* __restrict__ parent, uint8_t* __restrict__ flipb,
+    unsigned long long* __restrict__ acc, int32_t* __restrict__ root_chain, int64_t root_cap,
+    int64_t nchunks, const int64_t* __restrict__ rbase, unsigned long long* __restrict__ stats,
+    uint32_t* __restrict__ flags) {
+  __shared__ int64_t sh[kBlock / 64 + 1];
   if (*flags) return;
+  if (rbase[nchunks] > root_cap) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flags, LC_FLAG_ROOTS);
+    return;
+  }
   const int64_t n = totals[1];
   constexpr int kIdx[1] = {ST_CLUSTERS};
   Partial<1> part;
-  for (int64_t g = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; g < n;
-       g += static_cast<int64_t>(gridDim.x) * kBlock) {
-    if (parent[g] != g) continue;
-    const int c = chain_of(node_bases, nchain, g);
-    part.at(c, stats, kIdx);
-    part.v[0] += 1;
-    flipb[g] = static_cast<uint8_t>(flip_bit(descs[c], g - node_bases[c]));
-    acc[5 * g + 0] = 0;
-    acc[5 * g + 1] = 0;
-    acc[5 * g + 2] = 0;
-    acc[5 * g + 3] = 0;
-    acc[5 * g + 4] = 0;
+  for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+    const int64_t g0 = ch * kRootChunk + static_cast<int64_t>(threadIdx.x) * kRootPer;
+    int64_t cnt = 0;
+    for (int s = 0; s < kRootPer; ++s) {
+      const int64_t g = g0 + s;
+      if (g < n && parent[g] == g) ++cnt;
+    }
+    int64_t total;
+    int64_t idx = rbase[ch] + block_exclusive_scan(cnt, sh, total);
+    for (int s = 0; s < kRootPer && cnt > 0; ++s) {
+      const int64_t g = g0 + s;
+      if (!(g < n && parent[g] == g)) continue;
+      const int c = chain_of(node_bases, nchain, g);
+      part.at(c, stats, kIdx);
+      part.v[0] += 1;
+      parent[g] = -1 - idx;
+      root_chain[idx] = c;
+      flipb[idx] = static_cast<uint8_t>(flip_bit(descs[c], g - node_bases[c]));
+      unsigned long long* a = acc + 4 * idx;
+      a[0] = 0;
+      a[1] = 0;
+      a[2] = 0;
+      a[3] = 0;
+      ++idx;
+      --cnt;
+    }
   }
   part.flush(stats, kIdx);
 }
 
-// Per-loop accumulators (before the flip): nodes, boundary nodes at tau=0+,
-// their spin sum, and the loop length.  Length is a telescoping sum over the
-// loop's nodes: +2t at a lower node (two segments end there), -2t at an
-// upper node (two segments start there) and +2^64 at a top node.
+// Per-loop accumulators (before the flip), four 64-bit words per loop:
+//   [0] nodes + (top nodes << 40)
+//   [1] sum of +-hi32(t), [2] sum of +-lo32(t)  over operator nodes: lower
+//       nodes count +t, upper nodes -t (two vertical segments end / start)
+//   [3] bottom nodes + (their spin sum << 32)
+// so the loop length is 2^64 tops + 2 (2^32 [1] + [2]) ticks.  Every word
+// takes plain additions without carries between words.
 __global__ __launch_bounds__(kBlock) void k_accum(
     const ChainDesc* __restrict__ descs, const int64_t* __restrict__ node_bases, int nchain,
     const ChainDyn* __restrict__ dyn, const int64_t* __restrict__ totals,
@@ -587,48 +676,92 @@ __global__ __launch_bounds__(kBlock) void k_accum(
     unsigned long long* __restrict__ acc, const uint32_t* __restrict__ flags) {
   if (*flags) return;
   const int64_t n = totals[1];
-  for (int64_t g = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; g < n;
-       g += static_cast<int64_t>(gridDim.x) * kBlock) {
-    const int c = chain_of(node_bases, nchain, g);
-    const ChainDesc& D = descs[c];
-    const ChainDyn dy = dyn[c];
-    const int64_t v = g - dy.node_base;
-    const int64_t r = parent[g];
-    unsigned long long* a = acc + 5 * r;
-    atomicAdd(a + 0, 1ull);
-    uint64_t xlo = 0, xhi = 0;
-    if (v < D.nbn) {
-      const bool bottom = v < D.n_sites;
-      const bool top = (D.two_s == 1) || !bottom;
-      if (bottom) {
-        atomicAdd(a + 1, 1ull);
-        atomicAdd(a + 2, static_cast<unsigned long long>(2 * static_cast<int64_t>(D.s0[D.cur][v]) - 1));
-      }
-      if (top) xhi = 1;  // + 2^64
-    } else {
-      const int64_t q = (v - D.nbn) >> 1;
-      const uint64_t t = optime[dy.op_base + q];
-      // 2t as 65-bit value
-      const uint64_t tl = t << 1, th = t >> 63;
-      if (((v - D.nbn) & 1) == 0) {
-        xlo = tl;
-        xhi = th;
-      } else {  // -2t modulo 2^128
-        xlo = ~tl + 1;
-        xhi = ~th + (tl == 0 ? 1 : 0);
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+  const int64_t iters = (n + stride - 1) / stride;
+  for (int64_t it = 0; it < iters; ++it) {
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x + it * stride;
+    bool active = g < n;
+    int64_t r = -1;
+    uint64_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
+    if (active) {
+      const int c = chain_of(node_bases, nchain, g);
+      const ChainDesc& D = descs[c];
+      const ChainDyn dy = dyn[c];
+      const int64_t v = g - dy.node_base;
+      r = loop_index(parent, g);
+      w0 = 1;
+      if (v < D.nbn) {
+        const bool bottom = v < D.n_sites;
+        if ((D.two_s == 1) || !bottom) w0 += 1ull << 40;  // top node: + 2^64
+        if (bottom)
+          w3 = 1ull + (static_cast<uint64_t>(2 * static_cast<int64_t>(D.s0[D.cur][v]) - 1) << 32);
+      } else {
+        const int64_t q = (v - D.nbn) >> 1;
+        const uint64_t t = optime[dy.op_base + q];
+        const uint64_t th = t >> 32, tl = t & 0xFFFFFFFFull;
+        if (((v - D.nbn) & 1) == 0) {
+          w1 = th;
+          w2 = tl;
+        } else {
+          w1 = 0 - th;
+          w2 = 0 - tl;
+        }
       }
     }
-    if (xlo | xhi) atomic_add_u128(a + 3, a + 4, xlo, xhi);
+    // Reduce by loop within the wave: bitonic sort of (loop, sums) over the
+    // 64 lanes, segmented sums, then one set of atomics per distinct loop
+    // (about 27 distinct loops per 64 consecutive nodes at low temperature).
+    const int lane = lane_id();
+    int64_t key = active ? r : INT64_MAX;
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        const int64_t pk = __shfl_xor(key, j);
+        const uint64_t p0 = __shfl_xor(w0, j), p1 = __shfl_xor(w1, j);
+        const uint64_t p2 = __shfl_xor(w2, j), p3 = __shfl_xor(w3, j);
+        const bool ascending = (lane & k) == 0, lower = (lane & j) == 0;
+        const bool take = (lower == ascending) ? (pk < key) : (pk > key);
+        if (take) {
+          key = pk;
+          w0 = p0;
+          w1 = p1;
+          w2 = p2;
+          w3 = p3;
+        }
+      }
+    }
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int64_t qk = __shfl_up(key, d);
+      const uint64_t q0 = __shfl_up(w0, d), q1 = __shfl_up(w1, d);
+      const uint64_t q2 = __shfl_up(w2, d), q3 = __shfl_up(w3, d);
+      if (lane >= d && qk == key) {
+        w0 += q0;
+        w1 += q1;
+        w2 += q2;
+        w3 += q3;
+      }
+    }
+    const int64_t nk = __shfl_down(key, 1);
+    if (key != INT64_MAX && (lane == 63 || nk != key)) {
+      unsigned long long* a = acc + 4 * key;
+      atomicAdd(a + 0, static_cast<unsigned long long>(w0));
+      if (w1) atomicAdd(a + 1, static_cast<unsigned long long>(w1));
+      if (w2) atomicAdd(a + 2, static_cast<unsigned long long>(w2));
+      if (w3) atomicAdd(a + 3, static_cast<unsigned long long>(w3));
+    }
   }
 }
 
-// Per-loop squares summed into the chain statistics.
+// Per-loop squares summed into the chain statistics (walks the compact loop
+// records; the chain of a loop is found from its index range).
 __global__ __launch_bounds__(kBlock) void k_cluster_sums(
-    const int64_t* __restrict__ node_bases, int nchain, const int64_t* __restrict__ totals,
-    const int64_t* __restrict__ parent, const unsigned long long* __restrict__ acc,
+    const int32_t* __restrict__ root_chain, const int64_t* __restrict__ nloops,
+    int64_t root_cap, const unsigned long long* __restrict__ acc,
     unsigned long long* __restrict__ stats, const uint32_t* __restrict__ flags) {
   if (*flags) return;
-  const int64_t n = totals[1];
+  const int64_t n = *nloops < root_cap ? *nloops : root_cap;
   int cc = -1;
   uint64_t m2 = 0, n02 = 0, s2lo = 0, s2hi = 0, l2lo = 0, l2hi = 0, mx = 0;
   auto flush_lane = [&]() {
@@ -640,30 +773,37 @@ __global__ __launch_bounds__(kBlock) void k_cluster_sums(
     if (mx) atomicMax(st + ST_MAXSIZE, mx);
     m2 = n02 = s2lo = s2hi = l2lo = l2hi = mx = 0;
   };
-  for (int64_t g = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; g < n;
-       g += static_cast<int64_t>(gridDim.x) * kBlock) {
-    if (parent[g] != g) continue;
-    const int c = chain_of(node_bases, nchain, g);
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kBlock) {
+    const int c = root_chain[i];
     if (c != cc) {
       if (cc >= 0) flush_lane();
       cc = c;
     }
-    const unsigned long long* a = acc + 5 * g;
-    const uint64_t sz = a[0];
-    const int64_t n0 = static_cast<int64_t>(a[1]), m = static_cast<int64_t>(a[2]);
+    const unsigned long long* a = acc + 4 * i;
+    const uint64_t sz = a[0] & ((1ull << 40) - 1), tops = a[0] >> 40;
+    const int64_t n0 = static_cast<int64_t>(a[3] & 0xFFFFFFFFull);
+    const int64_t m = static_cast<int64_t>(static_cast<int32_t>(a[3] >> 32));
     m2 += static_cast<uint64_t>(m * m);
     n02 += static_cast<uint64_t>(n0 * n0);
     const u128p q2 = mul64x64(sz, sz);
     s2lo += q2.lo;
     s2hi += q2.hi + (s2lo < q2.lo ? 1u : 0u);
-    // (len >> 32)^2, len = (a[4] : a[3]) < 2^96
-    const uint64_t l32 = (a[3] >> 32) | (a[4] << 32);
+    // len = 2^64 tops + 2^33 S_hi + 2 S_lo as a signed 128-bit sum, then >> 32
+    const int64_t shi = static_cast<int64_t>(a[1]), slo = static_cast<int64_t>(a[2]);
+    uint64_t llo = static_cast<uint64_t>(slo) << 1;
+    uint64_t lhi = static_cast<uint64_t>(slo >> 63);  // sign extension of 2 S_lo
+    const uint64_t hlo = static_cast<uint64_t>(shi) << 33;
+    const uint64_t hhi = static_cast<uint64_t>(shi >> 31);  // arithmetic: bits 31.. of shi
+    const uint64_t t1 = llo + hlo;
+    lhi = lhi + hhi + (t1 < llo ? 1u : 0u) + tops;
+    llo = t1;
+    const uint64_t l32 = (llo >> 32) | (lhi << 32);  // len >> 32, len < 2^96
     const u128p l2 = mul64x64(l32, l32);
     l2lo += l2.lo;
     l2hi += l2.hi + (l2lo < l2.lo ? 1u : 0u);
     mx = sz > mx ? sz : mx;
   }
-  // one atomic per wave and statistic
   const int cf = cc < 0 ? 0 : cc;
   unsigned long long* st = stats + static_cast<int64_t>(cf) * ST_WORDS;
   wave_add_u64(st + ST_M2, m2);
@@ -700,7 +840,8 @@ __global__ __launch_bounds__(kBlock) void k_flip_ops(
     for (int64_t q = opstart[i]; q < opstart[i + 1]; ++q) {
       const int64_t lo = dy.node_base + D.nbn + 2 * (q - dy.op_base);
       const uint8_t v = optype[q];
-      const uint8_t ty = (v & 1) ^ flipb[parent[lo]] ^ flipb[parent[lo + 1]];
+      const uint8_t ty =
+          (v & 1) ^ flipb[loop_index(parent, lo)] ^ flipb[loop_index(parent, lo + 1)];
       optype[q] = static_cast<uint8_t>(ty | (v & 2));
       kept += ty;
     }
@@ -724,7 +865,7 @@ __global__ __launch_bounds__(kBlock) void k_flip_sites(
     part.at(c, stats, kIdx);
     const ChainDesc& D = descs[c];
     const int64_t x = gi - D.site_base;
-    const uint8_t s = D.s0[D.cur][x] ^ flipb[parent[dyn[c].node_base + x]];
+    const uint8_t s = D.s0[D.cur][x] ^ flipb[loop_index(parent, dyn[c].node_base + x)];
     D.s0[D.cur ^ 1][x] = s;
     part.v[0] += static_cast<uint64_t>(2 * static_cast<int64_t>(s) - 1);
   }
@@ -740,7 +881,8 @@ __global__ __launch_bounds__(kBlock) void k_compact(const ChainDesc* __restrict_
                                                      const uint8_t* __restrict__ optype,
                                                      const int64_t* __restrict__ kflat,
                                                      uint32_t* __restrict__ flags) {
-  if (*flags & 3u) return;
+  // a sweep with any overflow or error is discarded: kflat may be stale
+  if (*flags) return;
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < nwin;
        i += static_cast<int64_t>(gridDim.x) * kBlock) {
     const int c = chain_of(win_bases, nchain, i);
@@ -806,36 +948,6 @@ __global__ void k_init_chain(const ChainDesc* __restrict__ d) {
 // ---------------------------------------------------------------------------
 // Device-wide exclusive scan of int64 in place (reduce, scan of block sums,
 // rescan).  a[0..n) -> exclusive prefix, a[n] = total.
-constexpr int kScanItems = 16;
-constexpr int kScanTile = kBlock * kScanItems;
-
-__device__ inline int64_t block_exclusive_scan(int64_t v, int64_t* sh, int64_t& total) {
-  // wave inclusive scan
-  const int lane = lane_id(), wv = threadIdx.x >> 6;
-  int64_t x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int64_t y = __shfl_up(x, o);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) sh[wv] = x;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int64_t s = 0;
-    for (int q = 0; q < kBlock / 64; ++q) {
-      const int64_t t = sh[q];
-      sh[q] = s;
-      s += t;
-    }
-    sh[kBlock / 64] = s;
-  }
-  __syncthreads();
-  const int64_t r = sh[wv] + x - v;
-  total = sh[kBlock / 64];
-  __syncthreads();
-  return r;
-}
-
 __global__ __launch_bounds__(kBlock) void k_scan_reduce(const int64_t* __restrict__ a, int64_t n,
                                                          int64_t per_block,
                                                          int64_t* __restrict__ bsum) {
@@ -960,14 +1072,22 @@ hipError_t lc_launch_sweep(const LcSweepArgs& A, hipStream_t s) {
   hipLaunchKernelGGL(k_compress, dim3(G), dim3(kBlock), 0, s, A.totals, A.parent, A.flags);
   // 5. flips and estimators
   mark(LC_PH_ROOTS);
-  hipLaunchKernelGGL(k_roots, dim3(G), dim3(kBlock), 0, s, A.descs, A.node_bases, A.nchain,
-                     A.totals, A.parent, A.flipb, A.acc, st, A.flags);
+  {
+    const int64_t nch = (A.node_cap + kRootChunk - 1) / kRootChunk;
+    hipLaunchKernelGGL(k_root_count, dim3(grid_for(nch, G)), dim3(kBlock), 0, s, A.totals,
+                       A.parent, nch, A.rcnt, A.flags);
+    (void)lc_launch_scan(A.rcnt, nch, A.scan_tmp, s);
+    hipLaunchKernelGGL(k_roots, dim3(grid_for(nch, G)), dim3(kBlock), 0, s, A.descs, A.node_bases,
+                       A.nchain, A.totals, A.parent, A.flipb, A.acc, A.root_chain, A.root_cap, nch,
+                       A.rcnt, st, A.flags);
+  }
   mark(LC_PH_ACCUM);
   hipLaunchKernelGGL(k_accum, dim3(G), dim3(kBlock), 0, s, A.descs, A.node_bases, A.nchain, A.dyn,
                      A.totals, A.parent, A.optime, A.acc, A.flags);
   mark(LC_PH_CLUSTER_SUMS);
-  hipLaunchKernelGGL(k_cluster_sums, dim3(G), dim3(kBlock), 0, s, A.node_bases, A.nchain,
-                     A.totals, A.parent, A.acc, st, A.flags);
+  hipLaunchKernelGGL(k_cluster_sums, dim3(G), dim3(kBlock), 0, s, A.root_chain,
+                     A.rcnt + (A.node_cap + kRootChunk - 1) / kRootChunk, A.root_cap, A.acc, st,
+                     A.flags);
   mark(LC_PH_FLIP);
   hipLaunchKernelGGL(k_flip_ops, dim3(grid_for(A.nwin, G)), dim3(kBlock), 0, s, A.descs,
                      A.win_bases, A.nchain, A.nwin, A.dyn, A.opstart, A.parent, A.flipb,
