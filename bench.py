@@ -7,6 +7,9 @@ initial Neel world lines (about 1.86e8 operators per sweep).  One step is
 one full sweep of the hot path (insertion, operator merge, linking,
 union-find, flip, estimators, next world lines) on device-resident state.
 
+--workload largest runs the largest single-GPU chain instead (L=262,144,
+beta=16,384, about 3e9 operators per sweep).
+
 Prints one JSON line: operators ("graph vertices") per second over exactly
 --steps sweeps after --warmup untimed sweeps, with the per-phase HIP-event
 timing of those same sweeps, the roofline entry of the dominant kernel and
@@ -24,8 +27,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "graph vertices/sec & MC sweeps/sec on 1 GPU, batched/served vs plain; HBM GB/s"
-WORKLOAD = dict(workload="S=1/2 Heisenberg chain L=65536 beta=4096 seed 1, single chain",
-                L=65536, S=0.5, beta=4096.0, seed=1)
+WORKLOADS = {
+    "medium": dict(workload="S=1/2 Heisenberg chain L=65536 beta=4096 seed 1, single chain",
+                   L=65536, S=0.5, beta=4096.0, seed=1),
+    "largest": dict(workload="S=1/2 Heisenberg chain L=262144 beta=16384 seed 1, single chain",
+                    L=262144, S=0.5, beta=16384.0, seed=1),
+}
 HBM_PEAK_GBS = 8000.0
 
 
@@ -44,13 +51,13 @@ def phase_bytes(n_ops, n_nodes, n_clusters, n_win, n_sites, kept_in, kept_out):
         "link_ops": 8 * W + 8 * N + 16 * V,
         "link_sites": 24 * S,
         "compress": 16 * V,
-        # roots: count roots per chunk (8V), assign loop index, flip bit and
-        # chain, clear the four record words (8V + 8C + 1C + 4C + 32C)
-        "roots": 16 * V + 45 * Cl,
-        # accum: parent word per node, time and type per operator, bottom
-        # spins; read-modify-write of 4 words per loop record
-        "accum": 8 * V + 9 * N + S + 64 * Cl,
-        "cluster_sums": 36 * Cl,
+        # roots: count roots per chunk (8V), assign loop index and flip bit,
+        # clear the three record words (8V + 8C + 1C + 24C)
+        "roots": 16 * V + 33 * Cl,
+        # accum: parent word per node, time per operator, bottom spins;
+        # read-modify-write of 3 words per loop record
+        "accum": 8 * V + 8 * N + S + 48 * Cl,
+        "cluster_sums": 24 * Cl,
         "flip": 8 * V + 2 * N + Cl + 8 * W + 2 * S,
         "scan_kept": 24 * W,
         "compact": 24 * W + 9 * N + 8 * kept_out,
@@ -58,9 +65,9 @@ def phase_bytes(n_ops, n_nodes, n_clusters, n_win, n_sites, kept_in, kept_out):
     }
 
 
-def cpu_baseline(lc, L=4096, beta=4096.0, seed=1, gpu_therm=30, budget_s=12.0):
-    """The oracle's rate on a bounded sample: a chain with the benchmark's
-    beta and L=4,096 (1/16 of the spins), thermalised on the GPU, imported
+def cpu_baseline(lc, L, beta, seed=1, gpu_therm=30, budget_s=12.0):
+    """The oracle's rate on a bounded sample: a chain with the workload's
+    beta and fewer spins (L beta = 2^24), thermalised on the GPU, imported
     into the oracle, then timed for whole oracle sweeps (>= 1, up to about
     budget_s seconds).  Single-threaded C."""
     from oracle import oracle
@@ -79,7 +86,7 @@ def cpu_baseline(lc, L=4096, beta=4096.0, seed=1, gpu_therm=30, budget_s=12.0):
     g.close()
     return {"value": ops / el, "unit": "vertices/s", "cores": 1, "kind": "oracle",
             "sample": f"oracle sweeps of a thermalised S=1/2 chain L={L} beta={beta:g} "
-                      f"(same beta, 1/16 of the spins): {ops} operators in {el:.1f} s"}
+                      f"(same beta, fewer spins): {ops} operators in {el:.1f} s"}
 
 
 def main():
@@ -88,6 +95,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="medium",
+                    help="medium: L=65536 beta=4096 (default); largest: L=262144 beta=16384")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the chain is not "
@@ -98,7 +107,7 @@ def main():
     import paper_1810_07485_amd as lc
 
     torch.cuda.set_device(0)
-    w = WORKLOAD
+    w = WORKLOADS[args.workload]
     chain = lc.Chain(w["L"], w["S"], w["beta"], w["seed"])
     chain.update(args.warmup, accumulate=False)
     chain.reset_measurements()
@@ -149,7 +158,8 @@ def main():
     }
     chain.close()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(lc)
+        Ls = max(1024, int(2 ** 24 / w["beta"]) // 2 * 2)
+        out["cpu_baseline"] = cpu_baseline(lc, Ls, w["beta"])
     print(json.dumps(out), flush=True)
 
 

@@ -29,6 +29,7 @@ namespace {
 
 constexpr int kDefaultGrid = 2048;  // 256 CUs x 8 workgroups
 constexpr int kRing = 64;           // sweeps per host synchronisation
+constexpr int kAccWords = LC_ACC_WORDS;
 
 struct Mem {
   lc_alloc a{};
@@ -168,9 +169,8 @@ struct Engine {
   DBuf<int64_t> opstart, kflat, parent;
   DBuf<uint64_t> optime;
   DBuf<uint8_t> optype, flipb;
-  DBuf<unsigned long long> acc;
-  DBuf<int64_t> rcnt;
-  DBuf<int32_t> root_chain;
+  DBuf<unsigned long long> acc, bacc;
+  DBuf<int64_t> rcnt, loop_bases;
   int64_t nwin = 0, nsites = 0, nspins = 0, sum_nbn = 0, op_cap = 0, node_cap = 0, root_cap = 0;
   bool any_split = false;
   hipGraphExec_t gexec = nullptr;
@@ -215,8 +215,9 @@ struct Engine {
     optype.release(mem);
     flipb.release(mem);
     acc.release(mem);
+    bacc.release(mem);
     rcnt.release(mem);
-    root_chain.release(mem);
+    loop_bases.release(mem);
   }
 };
 
@@ -258,20 +259,44 @@ ChainDesc make_desc(const lc_chain* c, int64_t win_base, int64_t site_base, int6
   return d;
 }
 
-int64_t ops_estimate(const lc_chain* c) {
-  // operators = kept + accepted <= kept + candidates; candidates ~ Poisson
-  const double cand = 0.5 * static_cast<double>(c->n_bonds) * c->beta;
-  return c->n_kept + static_cast<int64_t>(cand + 6.0 * std::sqrt(cand + 1.0)) + 1024;
+// Loops: every boundary node may be alone; operator nodes form loops of at
+// least two nodes, about 0.29 loops per node at low temperature (0.398 loops
+// and 0.693 operators per unit L beta for S=1/2).  Grown on overflow.
+int64_t loops_estimate(int64_t nbn, int64_t ops) {
+  return nbn + static_cast<int64_t>(0.32 * 2.0 * static_cast<double>(ops)) + 65536;
 }
 
-// Loop records (accumulators, flip bits, chain of each loop) for cap loops.
+// Initial kept-operator capacity per buffer: about 0.3 off-diagonal
+// operators per bond and unit beta at low temperature; grown on overflow.
+int64_t kept_initial(int64_t n_bonds, double beta) {
+  return static_cast<int64_t>(0.36 * static_cast<double>(n_bonds) * beta) + 1024;
+}
+
+// Operator capacity of the next sweep.  Operators = kept + accepted
+// <= kept + candidates (candidates ~ Poisson(beta N_b / 2)); and on average
+// <N> = beta (N_b / 4 - E) <= beta (N_b / 4 + L S (S + 1)), because each
+// sub-bond term is bounded below by -S(S+1) / (2S)^2.  The smaller of the two
+// plus six standard deviations; a sweep that still overflows is replayed.
+double ops_bound(double n_kept, double n_bonds, double L, int two_s, double beta) {
+  const double cand = 0.5 * n_bonds * beta;
+  const double S = 0.5 * two_s;
+  const double mean_max = beta * (0.25 * n_bonds + L * S * (S + 1.0));
+  const double b = std::min(n_kept + cand, mean_max);
+  return b + 6.0 * std::sqrt(b + 1.0) + 1024.0;
+}
+
+int64_t ops_estimate(const lc_chain* c) {
+  return static_cast<int64_t>(ops_bound(static_cast<double>(c->n_kept),
+                                        static_cast<double>(c->n_bonds),
+                                        static_cast<double>(c->L), c->two_s, c->beta));
+}
+
+// Loop records (accumulators, flip bits) for cap loops.
 int ensure_roots(Engine& E, int64_t cap) {
   if (E.root_cap >= cap) return LC_OK;
   E.flipb.release(E.mem);
   E.acc.release(E.mem);
-  E.root_chain.release(E.mem);
-  if (!(E.flipb.ensure(E.mem, cap) && E.acc.ensure(E.mem, 4 * static_cast<size_t>(cap)) &&
-        E.root_chain.ensure(E.mem, cap))) {
+  if (!(E.flipb.ensure(E.mem, cap) && E.acc.ensure(E.mem, kAccWords * static_cast<size_t>(cap)))) {
     E.root_cap = 0;
     E.dirty = true;
     return LC_ENOMEM;
@@ -309,7 +334,8 @@ int layout(Engine& E) {
             E.stats.ensure(m, nc * lc::ST_WORDS) && E.flags.ensure(m, 2) && E.ring_ctr.ensure(m, 2) &&
             E.ring.ensure(m, static_cast<size_t>(kRing) * (nc * lc::ST_WORDS + 1)) &&
             E.opstart.ensure(m, static_cast<size_t>(nwin) + 1) &&
-            E.kflat.ensure(m, static_cast<size_t>(nwin) + 1);
+            E.kflat.ensure(m, static_cast<size_t>(nwin) + 1) && E.loop_bases.ensure(m, nc) &&
+            E.bacc.ensure(m, static_cast<size_t>(std::max<int64_t>(nsites, 1)));
   if (!ok) return LC_ENOMEM;
   if (E.op_cap < ops) {
     const int64_t nc2 = nbn + 2 * ops;
@@ -324,9 +350,8 @@ int layout(Engine& E) {
     E.op_cap = ops;
     E.node_cap = nc2;
   }
-  // loops are about 0.29 of the nodes at low temperature; grown on overflow
   if (!E.rcnt.ensure(m, static_cast<size_t>(E.node_cap / 4096 + 2)) ||
-      ensure_roots(E, E.node_cap / 2 + 65536) != LC_OK)
+      ensure_roots(E, loops_estimate(nbn, E.op_cap)) != LC_OK)
     return LC_ENOMEM;
   E.nwin = nwin;
   E.nsites = nsites;
@@ -370,7 +395,8 @@ LcSweepArgs sweep_args(Engine& E) {
   A.parent = E.parent.p;
   A.flipb = E.flipb.p;
   A.acc = E.acc.p;
-  A.root_chain = E.root_chain.p;
+  A.bacc = E.bacc.p;
+  A.loop_bases = E.loop_bases.p;
   A.root_cap = E.root_cap;
   A.rcnt = E.rcnt.p;
   A.op_cap = E.op_cap;
@@ -577,13 +603,15 @@ size_t footprint_bytes(int64_t L, int two_s, double beta) {
   const double n_bonds = static_cast<double>(two_s) * two_s * L;
   const double nwin = n_bonds * std::ldexp(1.0, w);
   const double nbn = two_s == 1 ? n_sites : 2 * n_sites;
-  const double kept = 0.5 * n_bonds * beta + 1024;  // initial kept capacity
-  const double ops = kept + 0.5 * n_bonds * beta + 6 * std::sqrt(0.5 * n_bonds * beta + 1) + 1024;
+  const double kept = static_cast<double>(kept_initial(static_cast<int64_t>(n_bonds), beta));
+  const double ops = ops_bound(kept, n_bonds, static_cast<double>(L), two_s, beta);
   const double nodes = nbn + 2 * ops;
+  const double loops = static_cast<double>(loops_estimate(static_cast<int64_t>(nbn), static_cast<int64_t>(ops)));
   const double state = 2 * n_sites + 2 * 8 * (nwin + 1) + 2 * 8 * kept + 8 * n_sites;
-  // window scans, operators (time + type), parent words, loop records for
-  // up to half the nodes (32 B accumulators + flip byte + chain index)
-  const double scratch = 2 * 8 * (nwin + 1) + 9 * ops + nodes * 8 + (nodes / 2) * (32 + 1 + 4);
+  // window scans, operators (time + type), parent words, loop records
+  // (24 B accumulators + flip byte), boundary records
+  const double scratch =
+      2 * 8 * (nwin + 1) + 9 * ops + nodes * 8 + loops * (8 * kAccWords + 1) + 8 * n_sites;
   return static_cast<size_t>(state + scratch + (1 << 20));
 }
 
@@ -656,7 +684,7 @@ int lc_init_lattice(int64_t L, double S, double beta, uint64_t seed, const lc_al
     c->mem.a = *alloc;
     c->mem.user = true;
   }
-  const int64_t kcap = static_cast<int64_t>(0.5 * static_cast<double>(c->n_bonds) * beta) + 1024;
+  const int64_t kcap = kept_initial(c->n_bonds, beta);
   bool ok = true;
   for (int q = 0; q < 2; ++q)
     ok = ok && c->s0[q].ensure(c->mem, c->n_sites) &&

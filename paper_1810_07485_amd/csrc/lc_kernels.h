@@ -8,6 +8,7 @@
 #include "lc_device.h"
 
 #define LC_SCAN_BLOCKS 1024
+#define LC_ACC_WORDS 3  // accumulator words per loop record
 
 struct LcSweepArgs {
   lc::ChainDesc* descs;       // nchain descriptors
@@ -25,8 +26,9 @@ struct LcSweepArgs {
   uint8_t* optype;            // op_cap
   int64_t* parent;            // node_cap
   uint8_t* flipb;             // root_cap: flip bit of each loop
-  unsigned long long* acc;    // 4 root_cap: loop accumulators
-  int32_t* root_chain;        // root_cap: chain of each loop
+  unsigned long long* acc;    // 3 root_cap: loop accumulators
+  unsigned long long* bacc;   // nsites: boundary sums of loops rooted at each bottom node
+  int64_t* loop_bases;        // nchain: first loop index of each chain
   int64_t op_cap, node_cap, root_cap;
   int64_t* rcnt;              // loops per node chunk, scanned (node_cap / 4096 + 2)
   lc::ChainDyn* dyn;          // nchain

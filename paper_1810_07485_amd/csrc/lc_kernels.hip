@@ -592,6 +592,7 @@ __device__ inline int64_t loop_index(const int64_t* __restrict__ parent, int64_t
 // Roots get compact loop indices in node order: roots are counted per chunk
 // of kRootChunk nodes, the counts are scanned, and each chunk numbers its
 // roots from its offset (no shared counter).
+constexpr int kAccWords = LC_ACC_WORDS;
 constexpr int kRootPer = 16;                      // nodes per thread
 constexpr int kRootChunk = kBlock * kRootPer;     // nodes per chunk
 
@@ -616,11 +617,14 @@ __global__ __launch_bounds__(kBlock) void k_root_count(const int64_t* __restrict
 }
 
 // Roots: compact index (stored as the code -1 - index in the root's parent
-// word), flip bit of the loop, cleared accumulators, loop count.
+// word), flip bit of the loop, cleared accumulators, loop count.  A loop
+// through a boundary node has a bottom boundary node as its smallest node
+// (boundary ids come first, and every top node is joined to a bottom one),
+// so its boundary sums live in a per-subspin record bacc[site], cleared here.
 __global__ __launch_bounds__(kBlock) void k_roots(
     const ChainDesc* __restrict__ descs, const int64_t* __restrict__ node_bases, int nchain,
     const int64_t* __restrict__ totals, int64_t* __restrict__ parent, uint8_t* __restrict__ flipb,
-    unsigned long long* __restrict__ acc, int32_t* __restrict__ root_chain, int64_t root_cap,
+    unsigned long long* __restrict__ acc, unsigned long long* __restrict__ bacc, int64_t root_cap,
     int64_t nchunks, const int64_t* __restrict__ rbase, unsigned long long* __restrict__ stats,
     uint32_t* __restrict__ flags) {
   __shared__ int64_t sh[kBlock / 64 + 1];
@@ -647,14 +651,15 @@ __global__ __launch_bounds__(kBlock) void k_roots(
       const int c = chain_of(node_bases, nchain, g);
       part.at(c, stats, kIdx);
       part.v[0] += 1;
+      const ChainDesc& D = descs[c];
+      const int64_t v = g - node_bases[c];
       parent[g] = -1 - idx;
-      root_chain[idx] = c;
-      flipb[idx] = static_cast<uint8_t>(flip_bit(descs[c], g - node_bases[c]));
-      unsigned long long* a = acc + 4 * idx;
+      flipb[idx] = static_cast<uint8_t>(flip_bit(D, v));
+      unsigned long long* a = acc + kAccWords * idx;
       a[0] = 0;
       a[1] = 0;
       a[2] = 0;
-      a[3] = 0;
+      if (v < D.n_sites) bacc[D.site_base + v] = 0;
       ++idx;
       --cnt;
     }
@@ -662,18 +667,20 @@ __global__ __launch_bounds__(kBlock) void k_roots(
   part.flush(stats, kIdx);
 }
 
-// Per-loop accumulators (before the flip), four 64-bit words per loop:
+// Per-loop accumulators (before the flip), three 64-bit words per loop:
 //   [0] nodes + (top nodes << 40)
 //   [1] sum of +-hi32(t), [2] sum of +-lo32(t)  over operator nodes: lower
 //       nodes count +t, upper nodes -t (two vertical segments end / start)
-//   [3] bottom nodes + (their spin sum << 32)
 // so the loop length is 2^64 tops + 2 (2^32 [1] + [2]) ticks.  Every word
-// takes plain additions without carries between words.
+// takes plain additions without carries between words (the sums are exact
+// modulo 2^64 and their true values fit).  Bottom boundary nodes add
+// 1 + (spin << 32) to bacc of their loop's root subspin.
 __global__ __launch_bounds__(kBlock) void k_accum(
     const ChainDesc* __restrict__ descs, const int64_t* __restrict__ node_bases, int nchain,
     const ChainDyn* __restrict__ dyn, const int64_t* __restrict__ totals,
     const int64_t* __restrict__ parent, const uint64_t* __restrict__ optime,
-    unsigned long long* __restrict__ acc, const uint32_t* __restrict__ flags) {
+    unsigned long long* __restrict__ acc, unsigned long long* __restrict__ bacc,
+    const uint32_t* __restrict__ flags) {
   if (*flags) return;
   const int64_t n = totals[1];
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
@@ -682,19 +689,22 @@ __global__ __launch_bounds__(kBlock) void k_accum(
     const int64_t g = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x + it * stride;
     bool active = g < n;
     int64_t r = -1;
-    uint64_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
+    uint64_t w0 = 0, w1 = 0, w2 = 0;
     if (active) {
       const int c = chain_of(node_bases, nchain, g);
       const ChainDesc& D = descs[c];
       const ChainDyn dy = dyn[c];
       const int64_t v = g - dy.node_base;
-      r = loop_index(parent, g);
+      const int64_t p = parent[g];
+      r = -1 - (p >= 0 ? parent[p] : p);
       w0 = 1;
       if (v < D.nbn) {
         const bool bottom = v < D.n_sites;
         if ((D.two_s == 1) || !bottom) w0 += 1ull << 40;  // top node: + 2^64
-        if (bottom)
-          w3 = 1ull + (static_cast<uint64_t>(2 * static_cast<int64_t>(D.s0[D.cur][v]) - 1) << 32);
+        const int64_t root = (p >= 0 ? p : g) - dy.node_base;
+        if (bottom && root < D.n_sites)  // always true: the root is a bottom node
+          atomicAdd(bacc + D.site_base + root,
+                    1ull + (static_cast<uint64_t>(2 * static_cast<int64_t>(D.s0[D.cur][v]) - 1) << 32));
       } else {
         const int64_t q = (v - D.nbn) >> 1;
         const uint64_t t = optime[dy.op_base + q];
@@ -719,7 +729,7 @@ __global__ __launch_bounds__(kBlock) void k_accum(
       for (int j = k >> 1; j > 0; j >>= 1) {
         const int64_t pk = __shfl_xor(key, j);
         const uint64_t p0 = __shfl_xor(w0, j), p1 = __shfl_xor(w1, j);
-        const uint64_t p2 = __shfl_xor(w2, j), p3 = __shfl_xor(w3, j);
+        const uint64_t p2 = __shfl_xor(w2, j);
         const bool ascending = (lane & k) == 0, lower = (lane & j) == 0;
         const bool take = (lower == ascending) ? (pk < key) : (pk > key);
         if (take) {
@@ -727,7 +737,6 @@ __global__ __launch_bounds__(kBlock) void k_accum(
           w0 = p0;
           w1 = p1;
           w2 = p2;
-          w3 = p3;
         }
       }
     }
@@ -735,57 +744,60 @@ __global__ __launch_bounds__(kBlock) void k_accum(
     for (int d = 1; d < 64; d <<= 1) {
       const int64_t qk = __shfl_up(key, d);
       const uint64_t q0 = __shfl_up(w0, d), q1 = __shfl_up(w1, d);
-      const uint64_t q2 = __shfl_up(w2, d), q3 = __shfl_up(w3, d);
+      const uint64_t q2 = __shfl_up(w2, d);
       if (lane >= d && qk == key) {
         w0 += q0;
         w1 += q1;
         w2 += q2;
-        w3 += q3;
       }
     }
     const int64_t nk = __shfl_down(key, 1);
     if (key != INT64_MAX && (lane == 63 || nk != key)) {
-      unsigned long long* a = acc + 4 * key;
+      unsigned long long* a = acc + kAccWords * key;
       atomicAdd(a + 0, static_cast<unsigned long long>(w0));
       if (w1) atomicAdd(a + 1, static_cast<unsigned long long>(w1));
       if (w2) atomicAdd(a + 2, static_cast<unsigned long long>(w2));
-      if (w3) atomicAdd(a + 3, static_cast<unsigned long long>(w3));
     }
   }
+}
+
+// First loop index of each chain: a chain's node 0 is always a root (the
+// smallest node of its loop) and loops are numbered in node order.
+__global__ void k_loop_bases(const int64_t* __restrict__ node_bases, int nchain,
+                             const int64_t* __restrict__ parent, int64_t* __restrict__ loop_bases,
+                             const uint32_t* __restrict__ flags) {
+  if (*flags) return;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nchain; c += gridDim.x * blockDim.x)
+    loop_bases[c] = -1 - parent[node_bases[c]];
 }
 
 // Per-loop squares summed into the chain statistics (walks the compact loop
 // records; the chain of a loop is found from its index range).
 __global__ __launch_bounds__(kBlock) void k_cluster_sums(
-    const int32_t* __restrict__ root_chain, const int64_t* __restrict__ nloops,
+    const int64_t* __restrict__ loop_bases, int nchain, const int64_t* __restrict__ nloops,
     int64_t root_cap, const unsigned long long* __restrict__ acc,
     unsigned long long* __restrict__ stats, const uint32_t* __restrict__ flags) {
   if (*flags) return;
   const int64_t n = *nloops < root_cap ? *nloops : root_cap;
   int cc = -1;
-  uint64_t m2 = 0, n02 = 0, s2lo = 0, s2hi = 0, l2lo = 0, l2hi = 0, mx = 0;
+  int64_t cend = 0;  // first loop index past chain cc
+  uint64_t s2lo = 0, s2hi = 0, l2lo = 0, l2hi = 0, mx = 0;
   auto flush_lane = [&]() {
     unsigned long long* st = stats + static_cast<int64_t>(cc) * ST_WORDS;
-    if (m2) atomicAdd(st + ST_M2, m2);
-    if (n02) atomicAdd(st + ST_N0SQ, n02);
     if (s2lo | s2hi) atomic_add_u128(st + ST_SIZE2_LO, st + ST_SIZE2_HI, s2lo, s2hi);
     if (l2lo | l2hi) atomic_add_u128(st + ST_LEN2_LO, st + ST_LEN2_HI, l2lo, l2hi);
     if (mx) atomicMax(st + ST_MAXSIZE, mx);
-    m2 = n02 = s2lo = s2hi = l2lo = l2hi = mx = 0;
+    s2lo = s2hi = l2lo = l2hi = mx = 0;
   };
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * kBlock) {
-    const int c = root_chain[i];
-    if (c != cc) {
+    if (cc < 0 || i >= cend) {
       if (cc >= 0) flush_lane();
-      cc = c;
+      cc = chain_of(loop_bases, nchain, i);
+      cend = cc + 1 < nchain ? loop_bases[cc + 1] : n;
     }
-    const unsigned long long* a = acc + 4 * i;
+    const unsigned long long* a = acc + kAccWords * i;
     const uint64_t sz = a[0] & ((1ull << 40) - 1), tops = a[0] >> 40;
-    const int64_t n0 = static_cast<int64_t>(a[3] & 0xFFFFFFFFull);
-    const int64_t m = static_cast<int64_t>(static_cast<int32_t>(a[3] >> 32));
-    m2 += static_cast<uint64_t>(m * m);
-    n02 += static_cast<uint64_t>(n0 * n0);
     const u128p q2 = mul64x64(sz, sz);
     s2lo += q2.lo;
     s2hi += q2.hi + (s2lo < q2.lo ? 1u : 0u);
@@ -806,8 +818,6 @@ __global__ __launch_bounds__(kBlock) void k_cluster_sums(
   }
   const int cf = cc < 0 ? 0 : cc;
   unsigned long long* st = stats + static_cast<int64_t>(cf) * ST_WORDS;
-  wave_add_u64(st + ST_M2, m2);
-  wave_add_u64(st + ST_N0SQ, n02);
   wave_add_u128(st + ST_SIZE2_LO, st + ST_SIZE2_HI, s2lo, s2hi);
   wave_add_u128(st + ST_LEN2_LO, st + ST_LEN2_HI, l2lo, l2hi);
   const unsigned long long d0 = __shfl(reinterpret_cast<unsigned long long>(st), 0);
@@ -851,23 +861,34 @@ __global__ __launch_bounds__(kBlock) void k_flip_ops(
   part.flush(stats, kIdx);
 }
 
+// New spins at tau = 0; the boundary estimators of every loop whose root is
+// this subspin's bottom node (n0 = bottom nodes, m = their spin sum before
+// the flip) are squared into the chain statistics.
 __global__ __launch_bounds__(kBlock) void k_flip_sites(
     const ChainDesc* __restrict__ descs, const int64_t* __restrict__ site_bases, int nchain,
     int64_t nsites, const ChainDyn* __restrict__ dyn, const int64_t* __restrict__ parent,
-    const uint8_t* __restrict__ flipb, unsigned long long* __restrict__ stats,
-    const uint32_t* __restrict__ flags) {
+    const uint8_t* __restrict__ flipb, const unsigned long long* __restrict__ bacc,
+    unsigned long long* __restrict__ stats, const uint32_t* __restrict__ flags) {
   if (*flags) return;
-  constexpr int kIdx[1] = {ST_MAFTER};
-  Partial<1> part;
+  constexpr int kIdx[3] = {ST_MAFTER, ST_M2, ST_N0SQ};
+  Partial<3> part;
   for (int64_t gi = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; gi < nsites;
        gi += static_cast<int64_t>(gridDim.x) * kBlock) {
     const int c = chain_of(site_bases, nchain, gi);
     part.at(c, stats, kIdx);
     const ChainDesc& D = descs[c];
     const int64_t x = gi - D.site_base;
-    const uint8_t s = D.s0[D.cur][x] ^ flipb[loop_index(parent, dyn[c].node_base + x)];
+    const int64_t p = parent[dyn[c].node_base + x];
+    const uint8_t s = D.s0[D.cur][x] ^ flipb[-1 - (p >= 0 ? parent[p] : p)];
     D.s0[D.cur ^ 1][x] = s;
     part.v[0] += static_cast<uint64_t>(2 * static_cast<int64_t>(s) - 1);
+    if (p < 0) {  // root of its loop
+      const uint64_t b = bacc[gi];
+      const int64_t n0 = static_cast<int64_t>(b & 0xFFFFFFFFull);
+      const int64_t m = static_cast<int64_t>(static_cast<int32_t>(b >> 32));
+      part.v[1] += static_cast<uint64_t>(m * m);
+      part.v[2] += static_cast<uint64_t>(n0 * n0);
+    }
   }
   part.flush(stats, kIdx);
 }
@@ -1078,14 +1099,16 @@ hipError_t lc_launch_sweep(const LcSweepArgs& A, hipStream_t s) {
                        A.parent, nch, A.rcnt, A.flags);
     (void)lc_launch_scan(A.rcnt, nch, A.scan_tmp, s);
     hipLaunchKernelGGL(k_roots, dim3(grid_for(nch, G)), dim3(kBlock), 0, s, A.descs, A.node_bases,
-                       A.nchain, A.totals, A.parent, A.flipb, A.acc, A.root_chain, A.root_cap, nch,
+                       A.nchain, A.totals, A.parent, A.flipb, A.acc, A.bacc, A.root_cap, nch,
                        A.rcnt, st, A.flags);
+    hipLaunchKernelGGL(k_loop_bases, dim3(grid_for(A.nchain, 64)), dim3(kBlock), 0, s,
+                       A.node_bases, A.nchain, A.parent, A.loop_bases, A.flags);
   }
   mark(LC_PH_ACCUM);
   hipLaunchKernelGGL(k_accum, dim3(G), dim3(kBlock), 0, s, A.descs, A.node_bases, A.nchain, A.dyn,
-                     A.totals, A.parent, A.optime, A.acc, A.flags);
+                     A.totals, A.parent, A.optime, A.acc, A.bacc, A.flags);
   mark(LC_PH_CLUSTER_SUMS);
-  hipLaunchKernelGGL(k_cluster_sums, dim3(G), dim3(kBlock), 0, s, A.root_chain,
+  hipLaunchKernelGGL(k_cluster_sums, dim3(G), dim3(kBlock), 0, s, A.loop_bases, A.nchain,
                      A.rcnt + (A.node_cap + kRootChunk - 1) / kRootChunk, A.root_cap, A.acc, st,
                      A.flags);
   mark(LC_PH_FLIP);
@@ -1093,7 +1116,8 @@ hipError_t lc_launch_sweep(const LcSweepArgs& A, hipStream_t s) {
                      A.win_bases, A.nchain, A.nwin, A.dyn, A.opstart, A.parent, A.flipb,
                      A.optype, A.kflat, st, A.flags);
   hipLaunchKernelGGL(k_flip_sites, dim3(grid_for(A.nsites, G)), dim3(kBlock), 0, s, A.descs,
-                     A.site_bases, A.nchain, A.nsites, A.dyn, A.parent, A.flipb, st, A.flags);
+                     A.site_bases, A.nchain, A.nsites, A.dyn, A.parent, A.flipb, A.bacc, st,
+                     A.flags);
   // 6. next world lines
   mark(LC_PH_SCAN_KEPT);
   (void)lc_launch_scan(A.kflat, A.nwin, A.scan_tmp, s);

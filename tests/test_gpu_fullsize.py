@@ -110,3 +110,61 @@ def test_thermalised_sweep_properties(chain):
         assert sx != sy, k
     e = 0.25 - st["n_ops"] / (chain.beta * L)
     assert abs(e - (0.25 - np.log(2))) < 5e-3
+
+
+def _antiparallel_below(s0, off, kt, L, idx):
+    """For kept operators idx of world lines (s0, off, kt), whether the two
+    spins just below each are antiparallel (operators of the same bond flip
+    both ends and cancel; equal times order by bond index)."""
+    b = np.searchsorted(off, idx, side="right") - 1
+    out = np.empty(len(idx), dtype=bool)
+    for n, (k, bb) in enumerate(zip(idx, b)):
+        bb = int(bb)
+        tt = kt[k]
+        def par_before(bond):
+            tb = kt[off[bond]:off[bond + 1]]
+            cnt = int(np.searchsorted(tb, tt, side="left"))
+            if bond < bb:
+                cnt = int(np.searchsorted(tb, tt, side="right"))
+            return cnt & 1
+        sx = int(s0[bb]) ^ par_before((bb - 1) % L)
+        sy = int(s0[(bb + 1) % L]) ^ par_before((bb + 1) % L)
+        out[n] = sx != sy
+    return out
+
+
+def test_largest_single_gpu_chain(lc, chain):
+    """L=262,144, beta=16,384 (about 3e9 operators per sweep): per-sweep
+    identities, valid world lines on sampled operators, even jump counts,
+    and the energy near the Bethe value 1/4 - ln 2."""
+    chain.close()  # release the medium chain
+    L, beta = 262144, 16384.0
+    c = lc.Chain(L, 0.5, beta, 1)
+    try:
+        e_seen = []
+        for s in range(12):
+            c.update(1)
+            st = c.last_sweep()
+            assert st["n_nodes"] == L + 2 * st["n_ops"], s
+            assert st["n_ops"] == st["n_kept_in"] + st["n_acc"], s
+            assert st["n_acc"] <= st["n_cand"] and st["n_kept_out"] <= st["n_ops"], s
+            assert 0 < st["n_clusters"] <= st["n_nodes"], s
+            assert st["max_size"] <= st["n_nodes"], s
+            e_seen.append(0.25 - st["n_ops"] / (beta * L))
+            print(f"sweep {s}: ops {st['n_ops']} loops {st['n_clusters']} e {e_seen[-1]:.6f}",
+                  flush=True)
+        s0, off, kt, sw = c.export_state()
+        assert sw == 12 and len(kt) == st["n_kept_out"] and off[-1] == len(kt)
+        assert (np.diff(off) >= 0).all()
+        cnt = np.diff(off)
+        assert ((cnt + np.roll(cnt, 1)) % 2 == 0).all()  # even jumps per site
+        rng = np.random.default_rng(7)
+        idx = np.sort(rng.choice(len(kt), 400, replace=False))
+        assert _antiparallel_below(s0, off, kt, L, idx).all()
+        # times sorted within each bond
+        for bnd in rng.choice(L, 64, replace=False):
+            tb = kt[off[bnd]:off[bnd + 1]]
+            assert (tb[1:] >= tb[:-1]).all()
+        assert abs(np.mean(e_seen[-4:]) - (0.25 - np.log(2))) < 2e-3
+    finally:
+        c.close()
