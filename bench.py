@@ -8,7 +8,13 @@ one full sweep of the hot path (insertion, operator merge, linking,
 union-find, flip, estimators, next world lines) on device-resident state.
 
 --workload largest runs the largest single-GPU chain instead (L=262,144,
-beta=16,384, about 3e9 operators per sweep).
+beta=16,384, about 3e9 operators per sweep).  --workload batch runs 512
+independent chains (L log-uniform in [64, 16,384], beta uniform in [L/4, L]):
+one step is one sweep of every chain, timed as 512 sequential plain updates
+and as footprint-packed, autotuned batches.  --workload serve runs the
+request loop on a Poisson stream of jobs (S in {1/2, 4}, L in {1024, 4096,
+16384}, beta in {L/2, L}; sweep counts scaled by --serve-sweep-scale) with
+continuous batching, and reports p50/p99 per-sweep latency and throughput.
 
 Prints one JSON line: operators ("graph vertices") per second over exactly
 --steps sweeps after --warmup untimed sweeps, with the per-phase HIP-event
@@ -89,15 +95,166 @@ def cpu_baseline(lc, L, beta, seed=1, gpu_therm=30, budget_s=12.0):
                       f"(same beta, fewer spins): {ops} operators in {el:.1f} s"}
 
 
+def _ops_since_reset(chains):
+    tot = 0.0
+    for c in chains:
+        m = c.measure()
+        tot += m["mean_ops"] * m["n_sweeps"]
+    return tot
+
+
+def _timed_passes(step, chains, steps):
+    import torch
+    for c in chains:
+        c.reset_measurements()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    return el, _ops_since_reset(chains)
+
+
+def bench_batch(args, lc):
+    """512 chains: sequential plain updates vs footprint-packed batches."""
+    import torch
+    from paper_1810_07485_amd import batching, workloads
+
+    inst = workloads.batch_instances()
+    chains = [lc.Chain(i.L, i.S, i.beta, i.seed) for i in inst]
+    budget = 48 << 30
+
+    def plain_pass(cs=chains):
+        for c in cs:
+            c.update(1)
+
+    for _ in range(args.warmup):
+        plain_pass()
+    el_p, ops_p = _timed_passes(plain_pass, chains, args.steps)
+    # small-chain subset (launch overhead dominates): plain vs one batch
+    small = sorted(chains, key=lambda c: c.L * c.beta)[:256]
+    el_sp, ops_sp = _timed_passes(lambda: plain_pass(small), small, args.steps)
+
+    sb = lc.Batch()
+    for c in small:
+        sb.add(c)
+    sgrid, _ = sb.autotune((256, 512, 1024, 2048), 1)
+    el_sb, ops_sb = _timed_passes(lambda: sb.update(1), small, args.steps)
+    sb.close()
+
+    runner = batching.BatchRunner(chains, budget)
+    tune = runner.autotune((1024, 2048, 4096), 1)
+    runner.update(1, accumulate=False)
+    el_b, ops_b = _timed_passes(lambda: runner.update(1), chains, args.steps)
+    n_groups = len(runner.groups)
+    runner.close()
+    out = {
+        "metric": METRIC,
+        "value": ops_b / el_b,
+        "unit": "vertices/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el_b / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "512 independent S=1/2 chains, L log-uniform in [64,16384] even, "
+                               "beta uniform in [L/4,L], seeds 1..512 (numpy default_rng(20181017)); "
+                               "one step = one sweep of every chain",
+                   "chains": len(chains), "scratch_budget_bytes": budget},
+        "plain": {"value": ops_p / el_p, "ms_per_step": el_p / args.steps * 1e3,
+                  "how": "512 sequential lc_update(1) calls per step, each chain's own graph"},
+        "batched": {"groups": n_groups, "grids": [g for g, _ in tune],
+                    "group_ms_per_sweep": [round(ms, 3) for _, ms in tune]},
+        "speedup_vs_plain": (ops_b / el_b) / (ops_p / el_p),
+        "small_chains": {"chains": len(small), "ops_per_step": ops_sp / args.steps,
+                         "plain_value": ops_sp / el_sp, "batched_value": ops_sb / el_sb,
+                         "grid": sgrid, "speedup": (ops_sb / el_sb) / (ops_sp / el_sp)},
+        "roofline": None,
+    }
+    for c in chains:
+        c.close()
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(lc, 4096, 4096.0)
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args, lc):
+    """Continuous-batching request loop on a Poisson job stream."""
+    import dataclasses
+    import torch
+    from paper_1810_07485_amd import serve, workloads
+
+    total = torch.cuda.get_device_properties(0).total_memory
+    budget = int(0.85 * total)
+    # plain single-chain throughput on one of the mix's chains (calibration)
+    cal = lc.Chain(16384, 0.5, 16384.0, 7)
+    cal.update(3, accumulate=False)
+    el, ops = _timed_passes(lambda: cal.update(1), [cal], 3)
+    cal.close()
+    plain = ops / el
+    jobs = workloads.serving_jobs(args.serve_jobs, rate=1.0)
+    jobs = [dataclasses.replace(j, sweeps=max(1, int(round(j.sweeps * args.serve_sweep_scale))))
+            for j in jobs]
+    dens = {0.5: 0.693, 4.0: 33.5}  # operators per unit L beta at low temperature
+    fits = [j for j in jobs if serve.job_bytes(j) <= budget]
+    mean_ops = sum(dens[j.S] * j.L * j.beta * j.sweeps for j in fits) / max(1, len(fits))
+    rate = 0.8 * plain / mean_ops  # jobs per second at 80 % of plain capacity
+    jobs = workloads.serving_jobs(args.serve_jobs, rate=rate)
+    jobs = [dataclasses.replace(j, sweeps=max(1, int(round(j.sweeps * args.serve_sweep_scale))))
+            for j in jobs]
+    rep = serve.Server(budget).run(jobs, log=lambda m: print(m, file=sys.stderr, flush=True))
+    sm = rep.summary()
+    out = {
+        "metric": METRIC,
+        "value": sm["ops_per_s_busy"],
+        "unit": "vertices/s",
+        "n_gpus": 1,
+        "steps": rep.iterations,
+        "warmup": 0,
+        "ms_per_step": rep.busy_s / max(1, rep.iterations) * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": f"serving: {args.serve_jobs} Poisson-arrival jobs (numpy default_rng(20181018)), "
+                               "S in {1/2,4}, L in {1024,4096,16384}, beta in {L/2,L}, sweeps in {100,1000} "
+                               f"scaled by {args.serve_sweep_scale}; admission by footprint within "
+                               f"{budget / 2**30:.0f} GiB; one step = one iteration (one sweep of every "
+                               "resident job)",
+                   "arrival_rate_per_s": rate},
+        "serving": sm,
+        "plain": {"value": plain, "how": "one S=1/2 L=16384 beta=16384 chain alone, lc_update"},
+        "roofline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 20; largest 5; batch 3)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps first (default 10; largest 4; batch 2)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="medium",
-                    help="medium: L=65536 beta=4096 (default); largest: L=262144 beta=16384")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["batch", "serve"], default="medium",
+                    help="medium: L=65536 beta=4096 (default); largest: L=262144 beta=16384; "
+                         "batch: 512 chains; serve: request loop")
+    ap.add_argument("--serve-jobs", type=int, default=24)
+    ap.add_argument("--serve-sweep-scale", type=float, default=0.1)
     args = ap.parse_args()
+    dflt = {"medium": (20, 10), "largest": (5, 4), "batch": (3, 2), "serve": (0, 0)}[args.workload]
+    if args.steps is None:
+        args.steps = dflt[0]
+    if args.warmup is None:
+        args.warmup = dflt[1]
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the chain is not "
               "sharded across GPUs in this build", file=sys.stderr)
@@ -107,6 +264,12 @@ def main():
     import paper_1810_07485_amd as lc
 
     torch.cuda.set_device(0)
+    if args.workload == "batch":
+        bench_batch(args, lc)
+        return
+    if args.workload == "serve":
+        bench_serve(args, lc)
+        return
     w = WORKLOADS[args.workload]
     chain = lc.Chain(w["L"], w["S"], w["beta"], w["seed"])
     chain.update(args.warmup, accumulate=False)

@@ -31,6 +31,12 @@
  *    every call returns after that stream has finished it.
  *  - Calls on one chain or batch must not overlap; different chains may be
  *    driven from different threads when they use different streams.
+ *  - Per-sweep scratch (operator lists, union-find parent words, loop
+ *    records) belongs to an arena shared by every engine -- a chain run
+ *    alone, or a batch -- with the same stream and allocator; sweeps on one
+ *    stream run one after another, so the arena is sized for the largest
+ *    engine that used it, not for the sum.  Engines sharing an arena are
+ *    serialised by a lock.  The arena is freed with the last engine.
  */
 #ifndef LC_H
 #define LC_H
@@ -97,9 +103,16 @@ typedef struct {
   double mean_ops, mean_clusters;
 } lc_measurement;
 
-/* Device bytes one chain needs when run alone (state plus per-sweep scratch).
+/* Device bytes one chain needs when run alone (state plus per-sweep scratch),
+ * an estimate of the steady-state allocation (buffers grow on overflow).
  * Used for admission; LC_EINVAL on bad parameters. */
 int lc_footprint(int64_t L, double S, double beta, size_t *bytes);
+
+/* The same estimate split into the chain's own world-line state, resident as
+ * long as the chain lives, and the per-sweep scratch it asks of its arena
+ * (a set of chains on one stream needs the sum of their states plus the
+ * scratch of the largest engine). */
+int lc_footprint_parts(int64_t L, double S, double beta, size_t *state, size_t *scratch);
 
 /* init_lattice: a chain of L spins S at inverse temperature beta with Philox
  * key `seed`, in the Neel state with a random phase and no operators.
@@ -142,8 +155,8 @@ int lc_import_state(lc_chain *c, const uint8_t *s0, const int64_t *bond_off, con
 /* Operators of the most recent sweep in canonical (bond, time) order:
  * op_bond, op_time, and their type before (op_type0) and after (op_type1)
  * the flip, 1 = off-diagonal.  *n_ops: capacity in, count out; all arrays
- * NULL queries the count.  Valid until the next sweep of the chain or of
- * its batch. */
+ * NULL queries the count.  Valid until the next sweep of any engine sharing
+ * the chain's arena (LC_ESTATE afterwards). */
 int lc_export_ops(const lc_chain *c, int64_t *op_bond, uint64_t *op_time, uint8_t *op_type0,
                   uint8_t *op_type1, int64_t *n_ops);
 
@@ -151,7 +164,7 @@ int lc_export_ops(const lc_chain *c, int64_t *op_bond, uint64_t *op_time, uint8_
  * loop through node v.  Nodes: boundary nodes first (S = 1/2: one per spin;
  * split spins: bottom(x) = x and top(x) = n_sites + x), then operator q has
  * lower node nbn + 2q and upper node nbn + 2q + 1.  *n_nodes: capacity in,
- * count out. */
+ * count out.  Same validity as lc_export_ops. */
 int lc_export_labels(const lc_chain *c, int64_t *labels, int64_t *n_nodes);
 
 /* Symmetrization permutation of the most recent sweep (split spins): top
@@ -182,6 +195,17 @@ void lc_batch_free(lc_batch *b);
 
 /* Same launch configuration for a chain run alone. */
 int lc_set_schedule(lc_chain *c, int grid_blocks, int use_graph);
+
+/* Autotuner (schedule only): for each of the n_grids candidate grid sizes
+ * grids[i] (> 0), runs trial_sweeps (>= 1) real sweeps of the batch with
+ * graph replay, not accumulated, timed on the host clock after one warm-up
+ * sweep; then keeps the fastest.  *best_grid and *ms_per_sweep (either may be
+ * NULL) receive the choice and its time.  The sweeps advance the chains
+ * exactly as lc_batch_update(b, n, 0) would. */
+int lc_batch_autotune(lc_batch *b, const int *grids, int n_grids, int trial_sweeps, int *best_grid,
+                      double *ms_per_sweep);
+int lc_autotune(lc_chain *c, const int *grids, int n_grids, int trial_sweeps, int *best_grid,
+                double *ms_per_sweep);
 
 /* ---- timing -------------------------------------------------------------
  * With profiling on, every sweep is launched directly (no graph) with a HIP

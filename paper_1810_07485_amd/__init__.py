@@ -11,6 +11,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import sys
 
 import numpy as np
 
@@ -82,6 +83,10 @@ def load():
     vp = C.c_void_p
     sig = {
         "lc_footprint": ([C.c_int64, C.c_double, C.c_double, C.POINTER(C.c_size_t)], C.c_int),
+        "lc_footprint_parts": ([C.c_int64, C.c_double, C.c_double, C.POINTER(C.c_size_t),
+                                C.POINTER(C.c_size_t)], C.c_int),
+        "lc_autotune": ([vp, pi, C.c_int, C.c_int, pi, C.POINTER(C.c_double)], C.c_int),
+        "lc_batch_autotune": ([vp, pi, C.c_int, C.c_int, pi, C.POINTER(C.c_double)], C.c_int),
         "lc_init_lattice": ([C.c_int64, C.c_double, C.c_double, C.c_uint64, C.POINTER(Alloc), vp,
                              C.POINTER(vp)], C.c_int),
         "lc_update": ([vp, C.c_int64, C.c_int], C.c_int),
@@ -142,6 +147,24 @@ def lc_footprint(L: int, S: float, beta: float) -> int:
     return n.value
 
 
+def lc_footprint_parts(L: int, S: float, beta: float) -> tuple:
+    """(state bytes, scratch bytes) of one chain (see lc_footprint_parts)."""
+    st, sc = C.c_size_t(), C.c_size_t()
+    _check(load().lc_footprint_parts(int(L), float(S), float(beta), C.byref(st), C.byref(sc)),
+           "lc_footprint_parts")
+    return st.value, sc.value
+
+
+def _autotune(fn, h, grids, trial_sweeps):
+    g = (C.c_int * len(grids))(*[int(x) for x in grids])
+    best, ms = C.c_int(), C.c_double()
+    _check(fn(h, g, len(grids), int(trial_sweeps), C.byref(best), C.byref(ms)), "autotune")
+    return best.value, ms.value
+
+
+DEFAULT_GRIDS = (512, 1024, 2048, 4096, 8192)
+
+
 def lc_debug_philox(seed: int, ctr) -> tuple:
     c = (C.c_uint32 * 4)(*[int(x) & 0xFFFFFFFF for x in ctr])
     o = (C.c_uint32 * 4)()
@@ -171,7 +194,10 @@ class _TorchMemory:
         def _alloc(nbytes, _stream, _ctx):
             try:
                 return torch.cuda.caching_allocator_alloc(int(nbytes), dev, self.stream)
-            except Exception:  # out of memory -> NULL, reported as LC_ENOMEM
+            except Exception as e:  # out of memory -> NULL, reported as LC_ENOMEM
+                if os.environ.get("LC_VERBOSE", "0") not in ("", "0"):
+                    print(f"[lc] torch allocation of {int(nbytes)} bytes failed: {e}",
+                          file=sys.stderr, flush=True)
                 return None
 
         def _free(ptr, _nbytes, _stream, _ctx):
@@ -185,6 +211,36 @@ class _TorchMemory:
         return C.c_void_p(self.stream.cuda_stream)
 
 
+_MEMORIES = {}
+_STREAMS = {}
+
+
+def library_stream(device=None):
+    """The stream chains and batches use by default: one per device, created
+    by torch at default priority.  (The legacy null stream cannot be captured
+    into graphs, and engines on one stream share one scratch arena.)"""
+    import torch
+    dev = torch.cuda.current_device() if device is None else int(device)
+    st = _STREAMS.get(dev)
+    if st is None:
+        st = _STREAMS[dev] = torch.cuda.Stream(device=dev)
+    return st
+
+
+def _torch_memory(stream=None) -> _TorchMemory:
+    """One allocator object per torch stream: engines with the same stream and
+    allocator share the library's per-sweep scratch arena."""
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible: the loop-cluster library runs only on the device")
+    st = stream if stream is not None else library_stream()
+    key = (st.device.index, st.cuda_stream)
+    m = _MEMORIES.get(key)
+    if m is None:
+        m = _MEMORIES[key] = _TorchMemory(st)
+    return m
+
+
 class Chain:
     """One Markov chain: ``lc_init_lattice`` / ``lc_update`` / ``lc_measure``."""
 
@@ -193,7 +249,7 @@ class Chain:
         lib = load()
         self.L, self.S, self.beta, self.seed = int(L), float(S), float(beta), int(seed)
         self.two_s = int(round(2 * S))
-        self._mem = _TorchMemory(stream) if torch_memory else None
+        self._mem = _torch_memory(stream) if torch_memory else None
         h = C.c_void_p()
         alloc = C.byref(self._mem.alloc) if self._mem else None
         strm = self._mem.handle if self._mem else None
@@ -233,6 +289,10 @@ class Chain:
 
     def set_profiling(self, on: bool = True):
         _check(load().lc_set_profiling(self._h, int(bool(on))), "lc_set_profiling")
+
+    def autotune(self, grids=DEFAULT_GRIDS, trial_sweeps: int = 2) -> tuple:
+        """Pick the fastest grid size (runs real, unaccumulated sweeps)."""
+        return _autotune(load().lc_autotune, self._h, grids, trial_sweeps)
 
     def profile(self) -> tuple:
         """(dict phase -> summed ms, sweeps) since profiling was switched on."""
@@ -300,7 +360,7 @@ class Batch:
 
     def __init__(self, stream=None, torch_memory: bool = True):
         lib = load()
-        self._mem = _TorchMemory(stream) if torch_memory else None
+        self._mem = _torch_memory(stream) if torch_memory else None
         h = C.c_void_p()
         alloc = C.byref(self._mem.alloc) if self._mem else None
         strm = self._mem.handle if self._mem else None
@@ -335,6 +395,10 @@ class Batch:
 
     def set_profiling(self, on: bool = True):
         _check(load().lc_batch_set_profiling(self._h, int(bool(on))), "lc_batch_set_profiling")
+
+    def autotune(self, grids=DEFAULT_GRIDS, trial_sweeps: int = 2) -> tuple:
+        """Pick the fastest grid size (runs real, unaccumulated sweeps)."""
+        return _autotune(load().lc_batch_autotune, self._h, grids, trial_sweeps)
 
     def profile(self) -> tuple:
         return _profile(load().lc_batch_profile, self._h)

@@ -1,10 +1,14 @@
 // lc_capi.cpp -- engine and C ABI of the loop-cluster library (host side).
 //
 // A chain owns its world lines (double-buffered spins and kept-operator
-// lists on the device).  An engine owns the per-sweep scratch of a set of
-// chains and queues one sweep as a fixed sequence of kernel launches over
-// flat index spaces (lc_kernels.hip), optionally captured once as a HIP
-// graph.  The host reads back one small record per sweep: the exact integer
+// lists on the device).  An engine (a chain run alone, or a batch) queues one
+// sweep of its chains as a fixed sequence of kernel launches over flat index
+// spaces (lc_kernels.hip), optionally captured once as a HIP graph.  The
+// large per-sweep scratch (operators, parent words, loop records) lives in an
+// arena shared by every engine on the same stream and allocator: sweeps on
+// one stream run one after another, so the arena is sized for the largest
+// engine instead of the sum, and a buffer that moves invalidates the graphs
+// captured with it (generation counter).  The host reads back one small record per sweep: the exact integer
 // statistics and an overflow flag.  On overflow the scratch or the chain
 // buffers grow and the same sweep is run again; its random numbers are
 // addressed by (seed, sweep, entity), so the replay is bit-identical.
@@ -13,8 +17,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -31,15 +39,28 @@ constexpr int kDefaultGrid = 2048;  // 256 CUs x 8 workgroups
 constexpr int kRing = 64;           // sweeps per host synchronisation
 constexpr int kAccWords = LC_ACC_WORDS;
 
+// LC_VERBOSE=1 in the environment traces scratch growth and failed
+// allocations on stderr.
+bool verbose() {
+  static const bool v = [] {
+    const char* e = std::getenv("LC_VERBOSE");
+    return e && *e && *e != '0';
+  }();
+  return v;
+}
+
 struct Mem {
   lc_alloc a{};
   bool user = false;
   hipStream_t s = nullptr;
   void* get(size_t bytes) const {
     if (bytes < 8) bytes = 8;
-    if (user) return a.alloc(bytes, s, a.ctx);
     void* p = nullptr;
-    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    if (user)
+      p = a.alloc(bytes, s, a.ctx);
+    else if (hipMalloc(&p, bytes) != hipSuccess)
+      p = nullptr;
+    if (!p && verbose()) std::fprintf(stderr, "[lc] allocation of %zu bytes failed\n", bytes);
     return p;
   }
   void put(void* p, size_t bytes) const {
@@ -49,6 +70,10 @@ struct Mem {
       a.free(p, bytes, s, a.ctx);
     else
       (void)hipFree(p);
+  }
+  bool same(const Mem& o) const {
+    return user == o.user && s == o.s &&
+           (!user || (a.alloc == o.a.alloc && a.free == o.a.free && a.ctx == o.a.ctx));
   }
 };
 
@@ -117,6 +142,77 @@ struct Accum {
   u128 ops = 0, m2 = 0, ma2 = 0, n02 = 0, len2 = 0, clusters = 0;
 };
 
+// Per-sweep scratch shared by the engines of one stream and allocator.
+struct Arena {
+  Mem mem;
+  int refs = 0;
+  uint64_t gen = 1;   // bumped whenever a buffer is reallocated
+  uint64_t runs = 0;  // bumped by every group of sweeps (export validity)
+  std::mutex mu;      // one engine at a time
+  DBuf<int64_t> opstart, kflat, parent, rcnt;
+  DBuf<uint64_t> optime;
+  DBuf<uint8_t> optype, flipb;
+  DBuf<unsigned long long> acc, bacc;
+  int64_t op_cap = 0, node_cap = 0, root_cap = 0;
+
+  void release_all() {
+    opstart.release(mem);
+    kflat.release(mem);
+    parent.release(mem);
+    rcnt.release(mem);
+    optime.release(mem);
+    optype.release(mem);
+    flipb.release(mem);
+    acc.release(mem);
+    bacc.release(mem);
+    op_cap = node_cap = root_cap = 0;
+    ++gen;
+  }
+  // grow b to hold want elements; a move bumps the generation
+  template <class T>
+  bool grow(DBuf<T>& b, size_t want) {
+    if (want <= b.n && b.p) return true;
+    if (verbose())
+      std::fprintf(stderr, "[lc] arena %p: buffer %zu -> %zu bytes (total before %.3f GB)\n",
+                   static_cast<void*>(this), b.n * sizeof(T), want * sizeof(T), bytes() / 1e9);
+    b.release(mem);
+    ++gen;
+    return b.ensure(mem, want);
+  }
+  double bytes() const {
+    return 8.0 * (opstart.n + kflat.n + parent.n + rcnt.n + optime.n + acc.n + bacc.n) +
+           static_cast<double>(optype.n + flipb.n);
+  }
+};
+
+std::mutex g_arena_mu;
+std::vector<Arena*> g_arenas;
+
+Arena* arena_get(const Mem& m) {
+  std::lock_guard<std::mutex> g(g_arena_mu);
+  for (Arena* a : g_arenas)
+    if (a->mem.same(m)) {
+      ++a->refs;
+      return a;
+    }
+  Arena* a = new (std::nothrow) Arena();
+  if (!a) return nullptr;
+  a->mem = m;
+  a->refs = 1;
+  g_arenas.push_back(a);
+  return a;
+}
+
+void arena_put(Arena* a) {
+  if (!a) return;
+  std::lock_guard<std::mutex> g(g_arena_mu);
+  if (--a->refs > 0) return;
+  g_arenas.erase(std::find(g_arenas.begin(), g_arenas.end(), a));
+  (void)hipStreamSynchronize(a->mem.s);
+  a->release_all();
+  delete a;
+}
+
 }  // namespace
 
 struct Engine;
@@ -148,33 +244,30 @@ struct lc_chain {
   lc_batch* batch = nullptr; // batch membership
   Engine* last_engine = nullptr;
   int last_index = 0;
+  uint64_t last_run = 0;  // arena run that holds this chain's last sweep
 };
 
 struct Engine {
   Mem mem;
   hipStream_t stream = nullptr;
+  Arena* ar = nullptr;  // shared per-sweep scratch
   std::vector<lc_chain*> chains;
   bool dirty = true;
   int grid = kDefaultGrid;
   bool use_graph = true;
   // per-chain small arrays
   DBuf<ChainDesc> descs;
-  DBuf<int64_t> win_bases, site_bases, spin_bases, op_bases, node_bases;
+  DBuf<int64_t> win_bases, site_bases, spin_bases, op_bases, node_bases, loop_bases;
   DBuf<ChainDyn> dyn;
   DBuf<int64_t> totals, scan_tmp;
   DBuf<uint64_t> stats;
   DBuf<uint32_t> flags, ring_ctr;
   DBuf<unsigned long long> ring;
-  // flat scratch
-  DBuf<int64_t> opstart, kflat, parent;
-  DBuf<uint64_t> optime;
-  DBuf<uint8_t> optype, flipb;
-  DBuf<unsigned long long> acc, bacc;
-  DBuf<int64_t> rcnt, loop_bases;
-  int64_t nwin = 0, nsites = 0, nspins = 0, sum_nbn = 0, op_cap = 0, node_cap = 0, root_cap = 0;
+  int64_t nwin = 0, nsites = 0, nspins = 0, sum_nbn = 0;
   bool any_split = false;
   hipGraphExec_t gexec = nullptr;
   bool graph_ok = false;
+  uint64_t graph_gen = 0;  // arena generation the graph was captured with
   std::vector<unsigned long long> hring;
   // per-phase timing (HIP events between the kernels of each sweep)
   bool profiling = false;
@@ -208,16 +301,9 @@ struct Engine {
     flags.release(mem);
     ring_ctr.release(mem);
     ring.release(mem);
-    opstart.release(mem);
-    kflat.release(mem);
-    parent.release(mem);
-    optime.release(mem);
-    optype.release(mem);
-    flipb.release(mem);
-    acc.release(mem);
-    bacc.release(mem);
-    rcnt.release(mem);
     loop_bases.release(mem);
+    arena_put(ar);
+    ar = nullptr;
   }
 };
 
@@ -291,18 +377,30 @@ int64_t ops_estimate(const lc_chain* c) {
                                         static_cast<double>(c->L), c->two_s, c->beta));
 }
 
-// Loop records (accumulators, flip bits) for cap loops.
-int ensure_roots(Engine& E, int64_t cap) {
-  if (E.root_cap >= cap) return LC_OK;
-  E.flipb.release(E.mem);
-  E.acc.release(E.mem);
-  if (!(E.flipb.ensure(E.mem, cap) && E.acc.ensure(E.mem, kAccWords * static_cast<size_t>(cap)))) {
-    E.root_cap = 0;
-    E.dirty = true;
-    return LC_ENOMEM;
+// Arena capacity for ops operators, nodes loop-graph nodes, roots loops.
+int ensure_scratch(Arena& A, int64_t ops, int64_t nodes, int64_t roots) {
+  // a buffer that has to grow gets 1/16 headroom, so slowly rising demand
+  // (a chain still equilibrating) does not reallocate on every call
+  if (A.op_cap < ops) {
+    ops += ops / 16;
+    A.op_cap = 0;
+    if (!(A.grow(A.optime, ops) && A.grow(A.optype, ops))) return LC_ENOMEM;
+    A.op_cap = ops;
   }
-  E.root_cap = cap;
-  E.drop_graph();
+  if (A.node_cap < nodes) {
+    nodes += nodes / 16;
+    A.node_cap = 0;
+    if (!(A.grow(A.parent, nodes) && A.grow(A.rcnt, static_cast<size_t>(nodes / 4096 + 2))))
+      return LC_ENOMEM;
+    A.node_cap = nodes;
+  }
+  if (A.root_cap < roots) {
+    roots += roots / 16;
+    A.root_cap = 0;
+    if (!(A.grow(A.flipb, roots) && A.grow(A.acc, kAccWords * static_cast<size_t>(roots))))
+      return LC_ENOMEM;
+    A.root_cap = roots;
+  }
   return LC_OK;
 }
 
@@ -333,26 +431,14 @@ int layout(Engine& E) {
             E.dyn.ensure(m, nc) && E.totals.ensure(m, 2) && E.scan_tmp.ensure(m, LC_SCAN_BLOCKS + 1) &&
             E.stats.ensure(m, nc * lc::ST_WORDS) && E.flags.ensure(m, 2) && E.ring_ctr.ensure(m, 2) &&
             E.ring.ensure(m, static_cast<size_t>(kRing) * (nc * lc::ST_WORDS + 1)) &&
-            E.opstart.ensure(m, static_cast<size_t>(nwin) + 1) &&
-            E.kflat.ensure(m, static_cast<size_t>(nwin) + 1) && E.loop_bases.ensure(m, nc) &&
-            E.bacc.ensure(m, static_cast<size_t>(std::max<int64_t>(nsites, 1)));
+            E.loop_bases.ensure(m, nc);
   if (!ok) return LC_ENOMEM;
-  if (E.op_cap < ops) {
-    const int64_t nc2 = nbn + 2 * ops;
-    E.optime.release(m);
-    E.optype.release(m);
-    E.parent.release(m);
-    ok = E.optime.ensure(m, ops) && E.optype.ensure(m, ops) && E.parent.ensure(m, nc2);
-    if (!ok) {
-      E.op_cap = E.node_cap = 0;
-      return LC_ENOMEM;
-    }
-    E.op_cap = ops;
-    E.node_cap = nc2;
-  }
-  if (!E.rcnt.ensure(m, static_cast<size_t>(E.node_cap / 4096 + 2)) ||
-      ensure_roots(E, loops_estimate(nbn, E.op_cap)) != LC_OK)
-    return LC_ENOMEM;
+  Arena& A = *E.ar;
+  ok = A.grow(A.opstart, static_cast<size_t>(nwin) + 1) && A.grow(A.kflat, static_cast<size_t>(nwin) + 1) &&
+       A.grow(A.bacc, static_cast<size_t>(std::max<int64_t>(nsites, 1)));
+  if (!ok) return LC_ENOMEM;
+  int rc = ensure_scratch(A, ops, nbn + 2 * ops, loops_estimate(nbn, ops));
+  if (rc != LC_OK) return rc;
   E.nwin = nwin;
   E.nsites = nsites;
   E.nspins = nspins;
@@ -376,6 +462,15 @@ int layout(Engine& E) {
   return LC_OK;
 }
 
+// Grow the arena, if needed, to the engine's current per-sweep bound
+// (kept + candidates per chain, from the host mirror of the kept counts).
+int ensure_capacity(Engine& E, int64_t at_least_ops) {
+  int64_t ops = 0;
+  for (lc_chain* c : E.chains) ops += ops_estimate(c);
+  ops = std::max(ops, at_least_ops);
+  return ensure_scratch(*E.ar, ops, E.sum_nbn + 2 * ops, loops_estimate(E.sum_nbn, ops));
+}
+
 LcSweepArgs sweep_args(Engine& E) {
   LcSweepArgs A;
   A.descs = E.descs.p;
@@ -388,19 +483,20 @@ LcSweepArgs sweep_args(Engine& E) {
   A.nsites = E.nsites;
   A.nspins = E.nspins;
   A.grid_blocks = E.grid;
-  A.opstart = E.opstart.p;
-  A.kflat = E.kflat.p;
-  A.optime = E.optime.p;
-  A.optype = E.optype.p;
-  A.parent = E.parent.p;
-  A.flipb = E.flipb.p;
-  A.acc = E.acc.p;
-  A.bacc = E.bacc.p;
+  const Arena& R = *E.ar;
+  A.opstart = R.opstart.p;
+  A.kflat = R.kflat.p;
+  A.optime = R.optime.p;
+  A.optype = R.optype.p;
+  A.parent = R.parent.p;
+  A.flipb = R.flipb.p;
+  A.acc = R.acc.p;
+  A.bacc = R.bacc.p;
   A.loop_bases = E.loop_bases.p;
-  A.root_cap = E.root_cap;
-  A.rcnt = E.rcnt.p;
-  A.op_cap = E.op_cap;
-  A.node_cap = E.node_cap;
+  A.root_cap = R.root_cap;
+  A.rcnt = R.rcnt.p;
+  A.op_cap = R.op_cap;
+  A.node_cap = R.node_cap;
   A.dyn = E.dyn.p;
   A.op_bases = E.op_bases.p;
   A.node_bases = E.node_bases.p;
@@ -425,6 +521,7 @@ int launch_one(Engine& E) {
     return hip_err(lc_launch_sweep(sweep_args(E), E.stream));
   }
   if (E.use_graph) {
+    if (E.graph_ok && E.graph_gen != E.ar->gen) E.drop_graph();
     if (!E.graph_ok) {
       hipGraph_t g = nullptr;
       if (hipStreamBeginCapture(E.stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
@@ -439,6 +536,7 @@ int launch_one(Engine& E) {
       (void)hipGraphDestroy(g);
       if (ie != hipSuccess) return LC_EDEVICE;
       E.graph_ok = true;
+      E.graph_gen = E.ar->gen;
     }
     return hip_err(hipGraphLaunch(E.gexec, E.stream));
   }
@@ -493,8 +591,11 @@ int grow_kept(lc_chain* c, int64_t need) {
 int run_engine(Engine& E, int64_t n_sweeps, int accumulate) {
   if (n_sweeps < 0) return LC_EINVAL;
   if (E.chains.empty() || n_sweeps == 0) return LC_OK;
+  std::lock_guard<std::mutex> hold(E.ar->mu);
+  Arena& R = *E.ar;
   int rc;
   if (E.dirty && (rc = layout(E)) != LC_OK) return rc;
+  if ((rc = ensure_capacity(E, 0)) != LC_OK) return rc;
   const int nch = static_cast<int>(E.chains.size());
   const int64_t rec = static_cast<int64_t>(nch) * lc::ST_WORDS + 1;
   int64_t done = 0;
@@ -518,6 +619,7 @@ int run_engine(Engine& E, int64_t n_sweeps, int accumulate) {
       for (int i = 0; i < nch; ++i) apply_record(E.chains[i], r + i * lc::ST_WORDS, accumulate != 0);
     }
     done += ok;
+    ++R.runs;
     if (E.profiling && ok) {
       if (E.ph_ms.size() != LC_PH_COUNT) E.ph_ms.assign(LC_PH_COUNT, 0.0);
       for (int p = 0; p < LC_PH_COUNT; ++p) {
@@ -531,6 +633,7 @@ int run_engine(Engine& E, int64_t n_sweeps, int accumulate) {
       lc_chain* c = E.chains[i];
       c->last_engine = &E;
       c->last_index = i;
+      c->last_run = R.runs;
       // descriptors held by the chain's other engine are now stale
       if (ok && c->own && c->own != &E) c->own->dirty = true;
     }
@@ -547,28 +650,18 @@ int run_engine(Engine& E, int64_t n_sweeps, int accumulate) {
       int64_t tot[2] = {0, 0};
       if (hipMemcpy(tot, E.totals.p, sizeof(tot), hipMemcpyDeviceToHost) != hipSuccess)
         return LC_EDEVICE;
-      const int64_t ops = std::max<int64_t>(tot[0] + tot[0] / 8 + 4096, E.op_cap + E.op_cap / 4);
-      const int64_t nodes = E.sum_nbn + 2 * ops;
-      E.optime.release(E.mem);
-      E.optype.release(E.mem);
-      E.parent.release(E.mem);
-      if (!(E.optime.ensure(E.mem, ops) && E.optype.ensure(E.mem, ops) &&
-            E.parent.ensure(E.mem, nodes))) {
-        E.op_cap = E.node_cap = 0;
-        E.dirty = true;
-        return LC_ENOMEM;
-      }
-      E.op_cap = ops;
-      E.node_cap = nodes;
+      // the totals are exact; grow to them plus a margin, or to the
+      // per-sweep bound of the current kept counts (the arena may already
+      // be larger, sized by another engine)
+      if ((rc = ensure_capacity(E, tot[0] + tot[0] / 8 + 4096)) != LC_OK) return rc;
     }
     if (bad & LC_FLAG_ROOTS) {
       int64_t cnt = 0;
-      const int64_t nch = (E.node_cap + 4095) / 4096;
-      if (hipMemcpy(&cnt, E.rcnt.p + nch, sizeof(cnt), hipMemcpyDeviceToHost) != hipSuccess)
+      const int64_t nch = (R.node_cap + 4095) / 4096;
+      if (hipMemcpy(&cnt, R.rcnt.p + nch, sizeof(cnt), hipMemcpyDeviceToHost) != hipSuccess)
         return LC_EDEVICE;
       const int64_t need = static_cast<int64_t>(cnt);
-      if ((rc = ensure_roots(E, std::max<int64_t>(need + need / 4 + 65536, 2 * E.root_cap))) != LC_OK)
-        return rc;
+      if ((rc = ensure_scratch(R, 0, 0, need + need / 4 + 65536)) != LC_OK) return rc;
     }
     if (bad & LC_FLAG_KEPT) {
       for (int i = 0; i < nch; ++i) {
@@ -593,8 +686,8 @@ int validate(int64_t L, double S, double beta, int* two_s) {
   return LC_OK;
 }
 
-// Bytes of one chain alone: state + its engine's scratch.
-size_t footprint_bytes(int64_t L, int two_s, double beta) {
+// Bytes of one chain alone: its state and the scratch it needs of an arena.
+void footprint_parts(int64_t L, int two_s, double beta, double* state_b, double* scratch_b) {
   int w, K;
   double mu;
   uint64_t T[lc::kMaxTable];
@@ -607,12 +700,18 @@ size_t footprint_bytes(int64_t L, int two_s, double beta) {
   const double ops = ops_bound(kept, n_bonds, static_cast<double>(L), two_s, beta);
   const double nodes = nbn + 2 * ops;
   const double loops = static_cast<double>(loops_estimate(static_cast<int64_t>(nbn), static_cast<int64_t>(ops)));
-  const double state = 2 * n_sites + 2 * 8 * (nwin + 1) + 2 * 8 * kept + 8 * n_sites;
+  // spins, kept-operator window scans and times (both halves), permutation
+  *state_b = 2 * n_sites + 2 * 8 * (nwin + 1) + 2 * 8 * kept + 8 * n_sites + 65536;
   // window scans, operators (time + type), parent words, loop records
   // (24 B accumulators + flip byte), boundary records
-  const double scratch =
-      2 * 8 * (nwin + 1) + 9 * ops + nodes * 8 + loops * (8 * kAccWords + 1) + 8 * n_sites;
-  return static_cast<size_t>(state + scratch + (1 << 20));
+  *scratch_b = 2 * 8 * (nwin + 1) + 9 * ops + nodes * 8 + loops * (8 * kAccWords + 1) +
+               8 * n_sites + (1 << 20);
+}
+
+size_t footprint_bytes(int64_t L, int two_s, double beta) {
+  double st, sc;
+  footprint_parts(L, two_s, beta, &st, &sc);
+  return static_cast<size_t>(st + sc);
 }
 
 }  // namespace
@@ -654,6 +753,18 @@ int lc_footprint(int64_t L, double S, double beta, size_t* bytes) {
   const int rc = validate(L, S, beta, &two_s);
   if (rc != LC_OK) return rc;
   *bytes = footprint_bytes(L, two_s, beta);
+  return LC_OK;
+}
+
+int lc_footprint_parts(int64_t L, double S, double beta, size_t* state, size_t* scratch) {
+  int two_s;
+  if (!state || !scratch) return LC_EINVAL;
+  const int rc = validate(L, S, beta, &two_s);
+  if (rc != LC_OK) return rc;
+  double st, sc;
+  footprint_parts(L, two_s, beta, &st, &sc);
+  *state = static_cast<size_t>(st);
+  *scratch = static_cast<size_t>(sc);
   return LC_OK;
 }
 
@@ -723,6 +834,12 @@ static Engine* own_engine(lc_chain* c) {
     if (!c->own) return nullptr;
     c->own->mem = c->mem;
     c->own->stream = c->stream;
+    c->own->ar = arena_get(c->mem);
+    if (!c->own->ar) {
+      delete c->own;
+      c->own = nullptr;
+      return nullptr;
+    }
     c->own->chains.push_back(c);
     // graph capture needs a stream other than the legacy null stream
     c->own->use_graph = c->stream != nullptr;
@@ -738,6 +855,53 @@ int lc_set_schedule(lc_chain* c, int grid_blocks, int use_graph) {
   E->use_graph = use_graph && c->stream != nullptr;
   E->drop_graph();
   return LC_OK;
+}
+
+// Time trial sweeps per candidate grid (graph replay when the stream allows
+// capture), keep the fastest.
+static int autotune(Engine& E, const int* grids, int n, int trials, int* best, double* ms) {
+  if (!grids || n < 1 || trials < 1) return LC_EINVAL;
+  for (int i = 0; i < n; ++i)
+    if (grids[i] <= 0) return LC_EINVAL;
+  const bool graph = E.stream != nullptr;
+  double best_ms = 0.0;
+  int bg = E.grid, rc;
+  for (int i = 0; i < n; ++i) {
+    E.grid = grids[i];
+    E.use_graph = graph;
+    E.drop_graph();
+    if ((rc = run_engine(E, 1, 0)) != LC_OK) return rc;  // warm-up, capture
+    const auto t0 = std::chrono::steady_clock::now();
+    if ((rc = run_engine(E, trials, 0)) != LC_OK) return rc;
+    const auto t1 = std::chrono::steady_clock::now();
+    const double per = std::chrono::duration<double, std::milli>(t1 - t0).count() / trials;
+    if (i == 0 || per < best_ms) {
+      best_ms = per;
+      bg = grids[i];
+    }
+  }
+  E.grid = bg;
+  E.drop_graph();
+  if (best) *best = bg;
+  if (ms) *ms = best_ms;
+  return LC_OK;
+}
+
+int lc_autotune(lc_chain* c, const int* grids, int n_grids, int trial_sweeps, int* best_grid,
+                double* ms_per_sweep) {
+  if (!c) return LC_EINVAL;
+  if (c->batch) return LC_ESTATE;
+  Engine* E = own_engine(c);
+  if (!E) return LC_ENOMEM;
+  return autotune(*E, grids, n_grids, trial_sweeps, best_grid, ms_per_sweep);
+}
+
+int lc_batch_autotune(lc_batch* b, const int* grids, int n_grids, int trial_sweeps, int* best_grid,
+                      double* ms_per_sweep) {
+  if (!b) return LC_EINVAL;
+  for (lc_chain* c : b->eng.chains)
+    if (c->stream != b->eng.stream && hipStreamSynchronize(c->stream) != hipSuccess) return LC_EDEVICE;
+  return autotune(b->eng, grids, n_grids, trial_sweeps, best_grid, ms_per_sweep);
 }
 
 int lc_update(lc_chain* c, int64_t n_sweeps, int accumulate) {
@@ -846,10 +1010,11 @@ int lc_import_state(lc_chain* c, const uint8_t* s0, const int64_t* bond_off, con
   return LC_OK;
 }
 
-// Operator and node ranges of a chain's most recent sweep.
+// Operator and node ranges of a chain's most recent sweep, still held in the
+// arena only if no other sweep has run there since (caller holds the lock).
 static int last_ranges(const lc_chain* c, ChainDyn* d, int64_t* win_base) {
   const Engine* E = c->last_engine;
-  if (!E || !c->has_last) return LC_ESTATE;
+  if (!E || !c->has_last || E->ar->runs != c->last_run) return LC_ESTATE;
   if (hipMemcpy(d, E->dyn.p + c->last_index, sizeof(ChainDyn), hipMemcpyDeviceToHost) != hipSuccess)
     return LC_EDEVICE;
   int64_t wb = 0;
@@ -861,6 +1026,8 @@ static int last_ranges(const lc_chain* c, ChainDyn* d, int64_t* win_base) {
 int lc_export_ops(const lc_chain* c, int64_t* op_bond, uint64_t* op_time, uint8_t* op_type0,
                   uint8_t* op_type1, int64_t* n_ops) {
   if (!c || !n_ops) return LC_EINVAL;
+  if (!c->last_engine) return LC_ESTATE;
+  std::lock_guard<std::mutex> hold(c->last_engine->ar->mu);
   ChainDyn d;
   int64_t wb;
   int rc = last_ranges(c, &d, &wb);
@@ -869,7 +1036,7 @@ int lc_export_ops(const lc_chain* c, int64_t* op_bond, uint64_t* op_time, uint8_
   *n_ops = d.n_ops;
   if (!op_bond && !op_time && !op_type0 && !op_type1) return LC_OK;
   if (have < d.n_ops) return LC_ECAPACITY;
-  const Engine* E = c->last_engine;
+  const Arena* E = c->last_engine->ar;
   std::vector<uint8_t> ty(static_cast<size_t>(std::max<int64_t>(d.n_ops, 1)));
   if (op_time && d.n_ops &&
       hipMemcpy(op_time, E->optime.p + d.op_base, d.n_ops * sizeof(uint64_t), hipMemcpyDeviceToHost) !=
@@ -897,6 +1064,8 @@ int lc_export_ops(const lc_chain* c, int64_t* op_bond, uint64_t* op_time, uint8_
 
 int lc_export_labels(const lc_chain* c, int64_t* labels, int64_t* n_nodes) {
   if (!c || !n_nodes) return LC_EINVAL;
+  if (!c->last_engine) return LC_ESTATE;
+  std::lock_guard<std::mutex> hold(c->last_engine->ar->mu);
   ChainDyn d;
   int64_t wb;
   int rc = last_ranges(c, &d, &wb);
@@ -905,7 +1074,7 @@ int lc_export_labels(const lc_chain* c, int64_t* labels, int64_t* n_nodes) {
   *n_nodes = d.n_nodes;
   if (!labels) return LC_OK;
   if (have < d.n_nodes) return LC_ECAPACITY;
-  if (hipMemcpy(labels, c->last_engine->parent.p + d.node_base, d.n_nodes * sizeof(int64_t),
+  if (hipMemcpy(labels, c->last_engine->ar->parent.p + d.node_base, d.n_nodes * sizeof(int64_t),
                 hipMemcpyDeviceToHost) != hipSuccess)
     return LC_EDEVICE;
   // parent words: a root holds a negative code, every other node its root
@@ -958,6 +1127,12 @@ int lc_batch_create(const lc_alloc* alloc, void* hip_stream, lc_batch** out) {
   if (alloc) {
     b->eng.mem.a = *alloc;
     b->eng.mem.user = true;
+  }
+  b->eng.ar = arena_get(b->eng.mem);
+  if (!b->eng.ar) {
+    if (b->owns_stream) (void)hipStreamDestroy(s);
+    delete b;
+    return LC_ENOMEM;
   }
   *out = b;
   return LC_OK;

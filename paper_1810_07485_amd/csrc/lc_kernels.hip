@@ -591,28 +591,44 @@ __device__ inline int64_t loop_index(const int64_t* __restrict__ parent, int64_t
 
 // Roots get compact loop indices in node order: roots are counted per chunk
 // of kRootChunk nodes, the counts are scanned, and each chunk numbers its
-// roots from its offset (no shared counter).
+// roots from its offset (no shared counter).  A chunk is kRootPer steps of
+// kBlock consecutive nodes (coalesced loads, all issued before use); a
+// root's rank in its chunk is the roots of earlier steps, of earlier waves
+// in its step, and of lower lanes in its wave's ballot.
 constexpr int kAccWords = LC_ACC_WORDS;
-constexpr int kRootPer = 16;                      // nodes per thread
+constexpr int kRootPer = 16;                      // steps per chunk
 constexpr int kRootChunk = kBlock * kRootPer;     // nodes per chunk
+constexpr int kWaves = kBlock / 64;
 
 __global__ __launch_bounds__(kBlock) void k_root_count(const int64_t* __restrict__ totals,
                                                         const int64_t* __restrict__ parent,
                                                         int64_t nchunks, int64_t* __restrict__ rcnt,
                                                         const uint32_t* __restrict__ flags) {
-  __shared__ int64_t sh[kBlock / 64 + 1];
+  __shared__ int wsum[kWaves];
   if (*flags) return;
   const int64_t n = totals[1];
+  const int lane = lane_id(), wv = threadIdx.x >> 6;
   for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
-    const int64_t g0 = ch * kRootChunk + static_cast<int64_t>(threadIdx.x) * kRootPer;
-    int64_t cnt = 0;
+    int64_t pv[kRootPer];
+#pragma unroll
     for (int s = 0; s < kRootPer; ++s) {
-      const int64_t g = g0 + s;
-      if (g < n && parent[g] == g) ++cnt;
+      const int64_t g = ch * kRootChunk + s * kBlock + threadIdx.x;
+      pv[s] = g < n ? parent[g] : -1;
     }
-    int64_t total;
-    block_exclusive_scan(cnt, sh, total);
-    if (threadIdx.x == 0) rcnt[ch] = total;
+    int cnt = 0;
+#pragma unroll
+    for (int s = 0; s < kRootPer; ++s)
+      cnt += pv[s] == ch * kRootChunk + s * kBlock + threadIdx.x ? 1 : 0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
+    if (lane == 0) wsum[wv] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int t = 0;
+      for (int q = 0; q < kWaves; ++q) t += wsum[q];
+      rcnt[ch] = t;
+    }
+    __syncthreads();
   }
 }
 
@@ -627,42 +643,61 @@ __global__ __launch_bounds__(kBlock) void k_roots(
     unsigned long long* __restrict__ acc, unsigned long long* __restrict__ bacc, int64_t root_cap,
     int64_t nchunks, const int64_t* __restrict__ rbase, unsigned long long* __restrict__ stats,
     uint32_t* __restrict__ flags) {
-  __shared__ int64_t sh[kBlock / 64 + 1];
+  __shared__ int wsum[kRootPer][kWaves];
   if (*flags) return;
   if (rbase[nchunks] > root_cap) {
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flags, LC_FLAG_ROOTS);
     return;
   }
   const int64_t n = totals[1];
+  const int lane = lane_id(), wv = threadIdx.x >> 6;
+  const unsigned long long below = (1ull << lane) - 1ull;
   constexpr int kIdx[1] = {ST_CLUSTERS};
   Partial<1> part;
   for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
-    const int64_t g0 = ch * kRootChunk + static_cast<int64_t>(threadIdx.x) * kRootPer;
-    int64_t cnt = 0;
+    const int64_t g0 = ch * kRootChunk + threadIdx.x;
+    int64_t pv[kRootPer];
+#pragma unroll
     for (int s = 0; s < kRootPer; ++s) {
-      const int64_t g = g0 + s;
-      if (g < n && parent[g] == g) ++cnt;
+      const int64_t g = g0 + s * kBlock;
+      pv[s] = g < n ? parent[g] : -1;
     }
-    int64_t total;
-    int64_t idx = rbase[ch] + block_exclusive_scan(cnt, sh, total);
-    for (int s = 0; s < kRootPer && cnt > 0; ++s) {
-      const int64_t g = g0 + s;
-      if (!(g < n && parent[g] == g)) continue;
-      const int c = chain_of(node_bases, nchain, g);
-      part.at(c, stats, kIdx);
-      part.v[0] += 1;
-      const ChainDesc& D = descs[c];
-      const int64_t v = g - node_bases[c];
-      parent[g] = -1 - idx;
-      flipb[idx] = static_cast<uint8_t>(flip_bit(D, v));
-      unsigned long long* a = acc + kAccWords * idx;
-      a[0] = 0;
-      a[1] = 0;
-      a[2] = 0;
-      if (v < D.n_sites) bacc[D.site_base + v] = 0;
-      ++idx;
-      --cnt;
+    unsigned long long m[kRootPer];
+#pragma unroll
+    for (int s = 0; s < kRootPer; ++s) {
+      m[s] = __ballot(pv[s] == g0 + s * kBlock);
+      if (lane == 0) wsum[s][wv] = __popcll(m[s]);
     }
+    __syncthreads();
+    int64_t idx = rbase[ch];
+#pragma unroll
+    for (int s = 0; s < kRootPer; ++s) {
+      int woff = 0, tot = 0;
+#pragma unroll
+      for (int q = 0; q < kWaves; ++q) {
+        const int x = wsum[s][q];
+        woff += q < wv ? x : 0;
+        tot += x;
+      }
+      const int64_t g = g0 + s * kBlock;
+      if (pv[s] == g) {
+        const int64_t i = idx + woff + __popcll(m[s] & below);
+        const int c = chain_of(node_bases, nchain, g);
+        part.at(c, stats, kIdx);
+        part.v[0] += 1;
+        const ChainDesc& D = descs[c];
+        const int64_t v = g - node_bases[c];
+        parent[g] = -1 - i;
+        flipb[i] = static_cast<uint8_t>(flip_bit(D, v));
+        unsigned long long* a = acc + kAccWords * i;
+        a[0] = 0;
+        a[1] = 0;
+        a[2] = 0;
+        if (v < D.n_sites) bacc[D.site_base + v] = 0;
+      }
+      idx += tot;
+    }
+    __syncthreads();  // wsum is rewritten for the next chunk
   }
   part.flush(stats, kIdx);
 }

@@ -118,3 +118,53 @@ def test_chain_alone_after_batch(lc):
     same_state(c.export_state(), ref[0])
     assert c.last_sweep() == ref[1][-1]
     b.close()
+
+
+def test_footprint_packed_runner_with_autotune_equals_alone(lc):
+    """Chains of the batching workload's distribution (smaller sizes): packed
+    into several groups under a small scratch budget, each group autotuned;
+    every chain ends where its alone-run does after the same sweep count."""
+    from paper_1810_07485_amd import batching, workloads
+    inst = workloads.batch_instances(24, L_min=16, L_max=512)
+    specs = [(i.L, i.S, i.beta, i.seed) for i in inst]
+    chains = [lc.Chain(*s) for s in specs]
+    parts = [lc.lc_footprint_parts(*s[:3])[1] for s in specs]
+    budget = max(parts) + sum(parts) // 5
+    r = batching.BatchRunner(chains, budget)
+    assert len(r.groups) >= 3 and sorted(sum(r.groups, [])) == list(range(24))
+    tune = r.autotune((256, 1024), trial_sweeps=1)
+    assert [g for g, _ in tune] == r.grids and set(r.grids) <= {256, 1024}
+    r.update(3)
+    n_sweeps = 2 * (1 + 1) + 3
+    for s, c in zip(specs, chains):
+        ref = lc.Chain(*s)
+        ref.update(n_sweeps)
+        same_state(c.export_state(), ref.export_state())
+        assert c.last_sweep() == ref.last_sweep(), s
+        ref.close()
+    r.close()
+
+
+def test_chain_autotune_keeps_results(lc):
+    a, b = lc.Chain(130, 0.5, 100.5, 3), lc.Chain(130, 0.5, 100.5, 3)
+    best, ms = a.autotune((128, 512), trial_sweeps=2)
+    assert best in (128, 512) and ms > 0
+    b.update(2 * 3)
+    same_state(a.export_state(), b.export_state())
+    assert a.last_sweep() == b.last_sweep()
+
+
+def test_exports_refuse_scratch_overwritten_by_another_engine(lc):
+    """Engines on one stream share the per-sweep scratch: a chain's operator
+    and label exports are refused once another engine has swept there."""
+    a, b = lc.Chain(64, 0.5, 16.0, 1), lc.Chain(64, 0.5, 16.0, 2)
+    a.update(1)
+    n = len(a.export_labels())
+    assert n == 64 + 2 * a.last_sweep()["n_ops"]
+    b.update(1)
+    with pytest.raises(lc.LcError):
+        a.export_labels()
+    with pytest.raises(lc.LcError):
+        a.export_ops()
+    a.update(1)
+    assert len(a.export_ops()[0]) == a.last_sweep()["n_ops"]
