@@ -57,18 +57,53 @@ def phase_bytes(n_ops, n_nodes, n_clusters, n_win, n_sites, kept_in, kept_out):
         "link_ops": 8 * W + 8 * N + 16 * V,
         "link_sites": 24 * S,
         "compress": 16 * V,
-        # roots: count roots per chunk (8V), assign loop index and flip bit,
-        # clear the three record words (8V + 8C + 1C + 24C)
-        "roots": 16 * V + 33 * Cl,
+        # roots: count roots per chunk (8V), assign loop index, clear the
+        # three record words (8V + 8C + 24C)
+        "roots": 16 * V + 32 * Cl,
         # accum: parent word per node, time per operator, bottom spins;
         # read-modify-write of 3 words per loop record
         "accum": 8 * V + 8 * N + S + 48 * Cl,
         "cluster_sums": 24 * Cl,
-        "flip": 8 * V + 2 * N + Cl + 8 * W + 2 * S,
+        # flip: parent word of both nodes of every operator (flip bit from
+        # the root id), type read and written, kept count per window
+        "flip": 8 * V + 2 * N + 8 * W + 2 * S,
         "scan_kept": 24 * W,
         "compact": 24 * W + 9 * N + 8 * kept_out,
         "setup": 0,
     }
+
+
+PHASE_KERNELS = {
+    "gen_count": ["k_gen<false>"], "gen_write": ["k_gen<true>"], "init_parent": ["k_init_parent"],
+    "link_ops": ["k_link_ops"], "compress": ["k_compress"], "roots": ["k_root_count", "k_roots"],
+    "accum": ["k_accum"], "cluster_sums": ["k_cluster_sums"], "flip": ["k_flip_ops", "k_flip_sites"],
+    "compact": ["k_compact"],
+}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_L65536_beta4096.txt")
+
+
+def measured_traffic(phase):
+    """HBM bytes per launch of a phase's kernels from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary of the medium workload (copy-calibrated),
+    or None when the kernel source has changed since the counters were taken."""
+    import hashlib
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return None
+    src = os.path.join(ROOT, "paper_1810_07485_amd", "csrc", "lc_kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    rec, ok = {}, False
+    for ln in lines:
+        f = ln.split()
+        if len(f) == 2 and f[0] == "kernel_source_sha256":
+            ok = f[1] == sha
+        elif len(f) == 6 and f[0] == "traffic":
+            rec[f[1]] = int(f[4]) + int(f[5])
+    ks = PHASE_KERNELS.get(phase, [])
+    if not ok or not ks or any(k not in rec for k in ks):
+        return None
+    return sum(rec[k] for k in ks)
 
 
 def cpu_baseline(lc, L, beta, seed=1, gpu_therm=30, budget_s=12.0):
@@ -139,12 +174,12 @@ def bench_batch(args, lc):
     sb = lc.Batch()
     for c in small:
         sb.add(c)
-    sgrid, _ = sb.autotune((256, 512, 1024, 2048), 1)
+    sgrid, _ = sb.autotune((512, 2048, 8192), 1)
     el_sb, ops_sb = _timed_passes(lambda: sb.update(1), small, args.steps)
     sb.close()
 
     runner = batching.BatchRunner(chains, budget)
-    tune = runner.autotune((1024, 2048, 4096), 1)
+    tune = runner.autotune((2048, 8192, 16384), 1)
     runner.update(1, accumulate=False)
     el_b, ops_b = _timed_passes(lambda: runner.update(1), chains, args.steps)
     n_groups = len(runner.groups)
@@ -247,6 +282,9 @@ def main():
     ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["batch", "serve"], default="medium",
                     help="medium: L=65536 beta=4096 (default); largest: L=262144 beta=16384; "
                          "batch: 512 chains; serve: request loop")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy 2 GiB device to device three times (reference kernel for "
+                         "the HBM byte counters) and exit")
     ap.add_argument("--serve-jobs", type=int, default=24)
     ap.add_argument("--serve-sweep-scale", type=float, default=0.1)
     args = ap.parse_args()
@@ -264,6 +302,14 @@ def main():
     import paper_1810_07485_amd as lc
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        x = torch.ones(1 << 28, dtype=torch.int64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": x.numel() * 8, "launches": 3}), flush=True)
+        return
     if args.workload == "batch":
         bench_batch(args, lc)
         return
@@ -295,6 +341,7 @@ def main():
     dom = max(phase_ms, key=phase_ms.get)
     achieved = pb[dom] / (phase_ms[dom] * 1e-3) / 1e9
     total_bytes = sum(pb.values())
+    traffic = measured_traffic(dom) if args.workload == "medium" else None
     out = {
         "metric": METRIC,
         "value": ops_total / el,
@@ -313,7 +360,8 @@ def main():
         "fragments_per_s": frag_total / el,
         "hbm_gbs_algorithmic": total_bytes * args.steps / el / 1e9,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_gbs": (traffic / (phase_ms[dom] * 1e-3) / 1e9) if traffic else None,
                      "bytes_per_launch": pb[dom], "avg_ms": phase_ms[dom]},
         "phase_ms": phase_ms,
         "observables": {"e": m["e"], "ops_per_L_beta": m["mean_ops"] / (w["L"] * w["beta"]),

@@ -162,7 +162,7 @@ def _autotune(fn, h, grids, trial_sweeps):
     return best.value, ms.value
 
 
-DEFAULT_GRIDS = (512, 1024, 2048, 4096, 8192)
+DEFAULT_GRIDS = (2048, 4096, 8192, 16384)
 
 
 def lc_debug_philox(seed: int, ctr) -> tuple:

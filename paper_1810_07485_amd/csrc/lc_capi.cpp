@@ -35,7 +35,7 @@ typedef unsigned __int128 u128;
 
 namespace {
 
-constexpr int kDefaultGrid = 2048;  // 256 CUs x 8 workgroups
+constexpr int kDefaultGrid = 8192;  // 256 CUs x 32 workgroups: latency-bound loops
 constexpr int kRing = 64;           // sweeps per host synchronisation
 constexpr int kAccWords = LC_ACC_WORDS;
 
@@ -151,7 +151,8 @@ struct Arena {
   std::mutex mu;      // one engine at a time
   DBuf<int64_t> opstart, kflat, parent, rcnt;
   DBuf<uint64_t> optime;
-  DBuf<uint8_t> optype, flipb;
+  DBuf<uint8_t> optype;
+  DBuf<uint32_t> accmask;
   DBuf<unsigned long long> acc, bacc;
   int64_t op_cap = 0, node_cap = 0, root_cap = 0;
 
@@ -162,7 +163,7 @@ struct Arena {
     rcnt.release(mem);
     optime.release(mem);
     optype.release(mem);
-    flipb.release(mem);
+    accmask.release(mem);
     acc.release(mem);
     bacc.release(mem);
     op_cap = node_cap = root_cap = 0;
@@ -181,7 +182,7 @@ struct Arena {
   }
   double bytes() const {
     return 8.0 * (opstart.n + kflat.n + parent.n + rcnt.n + optime.n + acc.n + bacc.n) +
-           static_cast<double>(optype.n + flipb.n);
+           static_cast<double>(optype.n) + 4.0 * accmask.n;
   }
 };
 
@@ -397,7 +398,7 @@ int ensure_scratch(Arena& A, int64_t ops, int64_t nodes, int64_t roots) {
   if (A.root_cap < roots) {
     roots += roots / 16;
     A.root_cap = 0;
-    if (!(A.grow(A.flipb, roots) && A.grow(A.acc, kAccWords * static_cast<size_t>(roots))))
+    if (!A.grow(A.acc, kAccWords * static_cast<size_t>(roots)))
       return LC_ENOMEM;
     A.root_cap = roots;
   }
@@ -435,6 +436,7 @@ int layout(Engine& E) {
   if (!ok) return LC_ENOMEM;
   Arena& A = *E.ar;
   ok = A.grow(A.opstart, static_cast<size_t>(nwin) + 1) && A.grow(A.kflat, static_cast<size_t>(nwin) + 1) &&
+       A.grow(A.accmask, static_cast<size_t>(std::max<int64_t>(nwin, 1))) &&
        A.grow(A.bacc, static_cast<size_t>(std::max<int64_t>(nsites, 1)));
   if (!ok) return LC_ENOMEM;
   int rc = ensure_scratch(A, ops, nbn + 2 * ops, loops_estimate(nbn, ops));
@@ -485,11 +487,11 @@ LcSweepArgs sweep_args(Engine& E) {
   A.grid_blocks = E.grid;
   const Arena& R = *E.ar;
   A.opstart = R.opstart.p;
+  A.accmask = R.accmask.p;
   A.kflat = R.kflat.p;
   A.optime = R.optime.p;
   A.optype = R.optype.p;
   A.parent = R.parent.p;
-  A.flipb = R.flipb.p;
   A.acc = R.acc.p;
   A.bacc = R.bacc.p;
   A.loop_bases = E.loop_bases.p;
@@ -703,8 +705,8 @@ void footprint_parts(int64_t L, int two_s, double beta, double* state_b, double*
   // spins, kept-operator window scans and times (both halves), permutation
   *state_b = 2 * n_sites + 2 * 8 * (nwin + 1) + 2 * 8 * kept + 8 * n_sites + 65536;
   // window scans, operators (time + type), parent words, loop records
-  // (24 B accumulators + flip byte), boundary records
-  *scratch_b = 2 * 8 * (nwin + 1) + 9 * ops + nodes * 8 + loops * (8 * kAccWords + 1) +
+  // (24 B accumulators), boundary records
+  *scratch_b = 2 * 8 * (nwin + 1) + 4 * nwin + 9 * ops + nodes * 8 + loops * (8 * kAccWords) +
                8 * n_sites + (1 << 20);
 }
 

@@ -21,11 +21,11 @@ struct LcSweepArgs {
   int grid_blocks;            // persistent grid size of the node/window loops
   // flat per-sweep scratch
   int64_t* opstart;           // nwin + 1
+  uint32_t* accmask;          // nwin: acceptance mask of each window (<= 32 candidates)
   int64_t* kflat;             // nwin + 1
   uint64_t* optime;           // op_cap
   uint8_t* optype;            // op_cap
   int64_t* parent;            // node_cap
-  uint8_t* flipb;             // root_cap: flip bit of each loop
   unsigned long long* acc;    // 3 root_cap: loop accumulators
   unsigned long long* bacc;   // nsites: boundary sums of loops rooted at each bottom node
   int64_t* loop_bases;        // nchain: first loop index of each chain

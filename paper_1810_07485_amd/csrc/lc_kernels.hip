@@ -26,6 +26,17 @@ constexpr int kCap = 24;  // candidates per window held in LDS; more are redrawn
 
 __device__ inline int lane_id() { return __lane_id(); }
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  Renumbering them so that every XCD takes a contiguous range of the
+// work keeps neighbouring windows and nodes (the other bond of a site, the
+// next operator of a loop) in one L2.  Identity unless the grid size is a
+// multiple of 8.  Only the assignment of work changes, never a result.
+__device__ inline int64_t xcd_block() {
+  const int64_t p = blockIdx.x, G = gridDim.x;
+  if (G & 7) return p;
+  return (p & 7) * (G >> 3) + (p >> 3);
+}
+
 // Add v to *dst once per wave when all lanes agree on dst, else per lane.
 __device__ inline void wave_add_u64(unsigned long long* dst, uint64_t v) {
   const unsigned long long d0 = __shfl(reinterpret_cast<unsigned long long>(dst), 0);
@@ -176,11 +187,14 @@ __device__ inline uint64_t cand_time(const ChainDesc& D, int64_t b, uint64_t k, 
 // Insertion of diagonal operators and removal of old ones (steps 2-6):
 // per (bond, window) the Poisson count from one 64-bit draw against the
 // threshold table, the candidate times, the antiparallel test, then (WRITE)
-// the merge with the kept operators into the operator list.
+// the merge with the kept operators into the operator list.  The counting
+// pass leaves the acceptance mask of windows with at most 32 candidates in
+// accmask, so the writing pass redraws only the times.
 template <bool WRITE>
 __global__ __launch_bounds__(kBlock) void k_gen(const ChainDesc* __restrict__ descs,
                                                 const int64_t* __restrict__ win_bases, int nchain,
                                                 int64_t nwin, int64_t* __restrict__ opstart,
+                                                uint32_t* __restrict__ accmask,
                                                 uint64_t* __restrict__ optime,
                                                 uint8_t* __restrict__ optype, int64_t op_cap,
                                                 unsigned long long* __restrict__ stats,
@@ -188,7 +202,7 @@ __global__ __launch_bounds__(kBlock) void k_gen(const ChainDesc* __restrict__ de
   __shared__ uint64_t slot[kCap * kBlock];
   const int tid = threadIdx.x;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
-  const int64_t start = static_cast<int64_t>(blockIdx.x) * kBlock + tid;
+  const int64_t start = xcd_block() * kBlock + tid;
   constexpr int kIdx[2] = {ST_CAND, ST_ACC};
   Partial<2> part;
   for (int64_t i = start; i < nwin; i += stride) {
@@ -210,16 +224,18 @@ __global__ __launch_bounds__(kBlock) void k_gen(const ChainDesc* __restrict__ de
       while (n < D.K && u >= D.T[n]) ++n;
       ncand = static_cast<uint32_t>(n);
       const bool inlds = n <= kCap;
-      uint64_t accm = 0;
+      const bool known = WRITE && n <= 32;
+      uint64_t accm = known ? accmask[i] : 0;
       for (int j = 0; j < n; ++j) {
         const uint64_t t = cand_time(D, b, k, j, v0);
         if (inlds) slot[j * kBlock + tid] = t;
-        if (antiparallel_before(D, s0, kstart, ktime, b, k, t)) accm |= (uint64_t(1) << j);
+        if (!known && antiparallel_before(D, s0, kstart, ktime, b, k, t)) accm |= (uint64_t(1) << j);
       }
       nacc = static_cast<uint32_t>(__popcll(accm));
       const int64_t kb = kstart[li], ke = kstart[li + 1];
       if (!WRITE) {
         opstart[i] = (ke - kb) + nacc;
+        accmask[i] = static_cast<uint32_t>(accm);
       } else {
         const int64_t base = opstart[i];
         if (opstart[i + 1] > op_cap) {
@@ -294,7 +310,7 @@ __global__ __launch_bounds__(kBlock) void k_init_parent(const int64_t* __restric
                                                          int64_t node_cap,
                                                          int64_t* __restrict__ parent) {
   const int64_t n = min(totals[1], node_cap);
-  for (int64_t g = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; g < n;
+  for (int64_t g = xcd_block() * kBlock + threadIdx.x; g < n;
        g += static_cast<int64_t>(gridDim.x) * kBlock)
     parent[g] = g;
 }
@@ -377,7 +393,7 @@ __global__ __launch_bounds__(kBlock) void k_link_ops(
     const uint64_t* __restrict__ optime, int64_t* __restrict__ parent,
     const uint32_t* __restrict__ flags) {
   if (*flags) return;
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < nwin;
+  for (int64_t i = xcd_block() * kBlock + threadIdx.x; i < nwin;
        i += static_cast<int64_t>(gridDim.x) * kBlock) {
     const int c = chain_of(win_bases, nchain, i);
     const ChainDesc& D = descs[c];
@@ -526,7 +542,7 @@ __global__ __launch_bounds__(kBlock) void k_compress(const int64_t* __restrict__
                                                       const uint32_t* __restrict__ flags) {
   if (*flags) return;
   const int64_t n = totals[1];
-  for (int64_t g = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; g < n;
+  for (int64_t g = xcd_block() * kBlock + threadIdx.x; g < n;
        g += static_cast<int64_t>(gridDim.x) * kBlock) {
     int64_t r = g, p = parent[g];
     while (p != r) {
@@ -580,15 +596,6 @@ __device__ inline int64_t block_exclusive_scan(int64_t v, int64_t* sh, int64_t& 
   return r;
 }
 
-// After compression the parent word of every node names its loop: a root
-// (the loop's smallest node) holds -1 - i, i the loop's compact index, and
-// every other node holds its root.
-__device__ inline int64_t loop_index(const int64_t* __restrict__ parent, int64_t g) {
-  int64_t p = parent[g];
-  if (p >= 0) p = parent[p];
-  return -1 - p;
-}
-
 // Roots get compact loop indices in node order: roots are counted per chunk
 // of kRootChunk nodes, the counts are scanned, and each chunk numbers its
 // roots from its offset (no shared counter).  A chunk is kRootPer steps of
@@ -608,7 +615,7 @@ __global__ __launch_bounds__(kBlock) void k_root_count(const int64_t* __restrict
   if (*flags) return;
   const int64_t n = totals[1];
   const int lane = lane_id(), wv = threadIdx.x >> 6;
-  for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+  for (int64_t ch = xcd_block(); ch < nchunks; ch += gridDim.x) {
     int64_t pv[kRootPer];
 #pragma unroll
     for (int s = 0; s < kRootPer; ++s) {
@@ -633,13 +640,13 @@ __global__ __launch_bounds__(kBlock) void k_root_count(const int64_t* __restrict
 }
 
 // Roots: compact index (stored as the code -1 - index in the root's parent
-// word), flip bit of the loop, cleared accumulators, loop count.  A loop
+// word), cleared accumulators, loop count.  A loop
 // through a boundary node has a bottom boundary node as its smallest node
 // (boundary ids come first, and every top node is joined to a bottom one),
 // so its boundary sums live in a per-subspin record bacc[site], cleared here.
 __global__ __launch_bounds__(kBlock) void k_roots(
     const ChainDesc* __restrict__ descs, const int64_t* __restrict__ node_bases, int nchain,
-    const int64_t* __restrict__ totals, int64_t* __restrict__ parent, uint8_t* __restrict__ flipb,
+    const int64_t* __restrict__ totals, int64_t* __restrict__ parent,
     unsigned long long* __restrict__ acc, unsigned long long* __restrict__ bacc, int64_t root_cap,
     int64_t nchunks, const int64_t* __restrict__ rbase, unsigned long long* __restrict__ stats,
     uint32_t* __restrict__ flags) {
@@ -654,7 +661,7 @@ __global__ __launch_bounds__(kBlock) void k_roots(
   const unsigned long long below = (1ull << lane) - 1ull;
   constexpr int kIdx[1] = {ST_CLUSTERS};
   Partial<1> part;
-  for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+  for (int64_t ch = xcd_block(); ch < nchunks; ch += gridDim.x) {
     const int64_t g0 = ch * kRootChunk + threadIdx.x;
     int64_t pv[kRootPer];
 #pragma unroll
@@ -688,7 +695,6 @@ __global__ __launch_bounds__(kBlock) void k_roots(
         const ChainDesc& D = descs[c];
         const int64_t v = g - node_bases[c];
         parent[g] = -1 - i;
-        flipb[i] = static_cast<uint8_t>(flip_bit(D, v));
         unsigned long long* a = acc + kAccWords * i;
         a[0] = 0;
         a[1] = 0;
@@ -721,7 +727,7 @@ __global__ __launch_bounds__(kBlock) void k_accum(
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
   const int64_t iters = (n + stride - 1) / stride;
   for (int64_t it = 0; it < iters; ++it) {
-    const int64_t g = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x + it * stride;
+    const int64_t g = xcd_block() * kBlock + threadIdx.x + it * stride;
     bool active = g < n;
     int64_t r = -1;
     uint64_t w0 = 0, w1 = 0, w2 = 0;
@@ -824,7 +830,7 @@ __global__ __launch_bounds__(kBlock) void k_cluster_sums(
     if (mx) atomicMax(st + ST_MAXSIZE, mx);
     s2lo = s2hi = l2lo = l2hi = mx = 0;
   };
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+  for (int64_t i = xcd_block() * kBlock + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * kBlock) {
     if (cc < 0 || i >= cend) {
       if (cc >= 0) flush_lane();
@@ -864,18 +870,25 @@ __global__ __launch_bounds__(kBlock) void k_cluster_sums(
   }
 }
 
+// Flip bit of the loop through node g, from its root (the loop's smallest
+// node): after compression a non-root holds its root, a root a negative code.
+__device__ inline uint32_t node_flip(const ChainDesc& D, int64_t node_base,
+                                     const int64_t* __restrict__ parent, int64_t g) {
+  const int64_t p = parent[g];
+  return flip_bit(D, (p >= 0 ? p : g) - node_base);
+}
+
 // Cluster flip (step 7): the type of an operator changes when exactly one of
 // its two loops flips; kept (off-diagonal) operators are counted per window.
 __global__ __launch_bounds__(kBlock) void k_flip_ops(
     const ChainDesc* __restrict__ descs, const int64_t* __restrict__ win_bases, int nchain,
     int64_t nwin, const ChainDyn* __restrict__ dyn, const int64_t* __restrict__ opstart,
-    const int64_t* __restrict__ parent, const uint8_t* __restrict__ flipb,
-    uint8_t* __restrict__ optype, int64_t* __restrict__ kcnt, unsigned long long* __restrict__ stats,
+    const int64_t* __restrict__ parent, uint8_t* __restrict__ optype, int64_t* __restrict__ kcnt, unsigned long long* __restrict__ stats,
     const uint32_t* __restrict__ flags) {
   if (*flags) return;
   constexpr int kIdx[1] = {ST_KEPT_OUT};
   Partial<1> part;
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < nwin;
+  for (int64_t i = xcd_block() * kBlock + threadIdx.x; i < nwin;
        i += static_cast<int64_t>(gridDim.x) * kBlock) {
     const int c = chain_of(win_bases, nchain, i);
     part.at(c, stats, kIdx);
@@ -885,8 +898,8 @@ __global__ __launch_bounds__(kBlock) void k_flip_ops(
     for (int64_t q = opstart[i]; q < opstart[i + 1]; ++q) {
       const int64_t lo = dy.node_base + D.nbn + 2 * (q - dy.op_base);
       const uint8_t v = optype[q];
-      const uint8_t ty =
-          (v & 1) ^ flipb[loop_index(parent, lo)] ^ flipb[loop_index(parent, lo + 1)];
+      const uint8_t ty = static_cast<uint8_t>((v & 1) ^ node_flip(D, dy.node_base, parent, lo) ^
+                                              node_flip(D, dy.node_base, parent, lo + 1));
       optype[q] = static_cast<uint8_t>(ty | (v & 2));
       kept += ty;
     }
@@ -902,7 +915,7 @@ __global__ __launch_bounds__(kBlock) void k_flip_ops(
 __global__ __launch_bounds__(kBlock) void k_flip_sites(
     const ChainDesc* __restrict__ descs, const int64_t* __restrict__ site_bases, int nchain,
     int64_t nsites, const ChainDyn* __restrict__ dyn, const int64_t* __restrict__ parent,
-    const uint8_t* __restrict__ flipb, const unsigned long long* __restrict__ bacc,
+    const unsigned long long* __restrict__ bacc,
     unsigned long long* __restrict__ stats, const uint32_t* __restrict__ flags) {
   if (*flags) return;
   constexpr int kIdx[3] = {ST_MAFTER, ST_M2, ST_N0SQ};
@@ -914,7 +927,7 @@ __global__ __launch_bounds__(kBlock) void k_flip_sites(
     const ChainDesc& D = descs[c];
     const int64_t x = gi - D.site_base;
     const int64_t p = parent[dyn[c].node_base + x];
-    const uint8_t s = D.s0[D.cur][x] ^ flipb[-1 - (p >= 0 ? parent[p] : p)];
+    const uint8_t s = D.s0[D.cur][x] ^ static_cast<uint8_t>(flip_bit(D, p >= 0 ? p - dyn[c].node_base : x));
     D.s0[D.cur ^ 1][x] = s;
     part.v[0] += static_cast<uint64_t>(2 * static_cast<int64_t>(s) - 1);
     if (p < 0) {  // root of its loop
@@ -939,7 +952,7 @@ __global__ __launch_bounds__(kBlock) void k_compact(const ChainDesc* __restrict_
                                                      uint32_t* __restrict__ flags) {
   // a sweep with any overflow or error is discarded: kflat may be stale
   if (*flags) return;
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < nwin;
+  for (int64_t i = xcd_block() * kBlock + threadIdx.x; i < nwin;
        i += static_cast<int64_t>(gridDim.x) * kBlock) {
     const int c = chain_of(win_bases, nchain, i);
     const ChainDesc& D = descs[c];
@@ -1099,8 +1112,8 @@ hipError_t lc_launch_sweep(const LcSweepArgs& A, hipStream_t s) {
   // 1. count operators per window, 2. scan
   mark(LC_PH_GEN_COUNT);
   hipLaunchKernelGGL((k_gen<false>), dim3(grid_for(A.nwin, G)), dim3(kBlock), 0, s, A.descs,
-                     A.win_bases, A.nchain, A.nwin, A.opstart, A.optime, A.optype, A.op_cap, st,
-                     A.flags);
+                     A.win_bases, A.nchain, A.nwin, A.opstart, A.accmask, A.optime, A.optype,
+                     A.op_cap, st, A.flags);
   mark(LC_PH_SCAN_OPS);
   (void)lc_launch_scan(A.opstart, A.nwin, A.scan_tmp, s);
   hipLaunchKernelGGL(k_chain_bases, dim3(grid_for(A.nchain, 64)), dim3(kBlock), 0, s, A.descs,
@@ -1109,8 +1122,8 @@ hipError_t lc_launch_sweep(const LcSweepArgs& A, hipStream_t s) {
   // 3. write operators
   mark(LC_PH_GEN_WRITE);
   hipLaunchKernelGGL((k_gen<true>), dim3(grid_for(A.nwin, G)), dim3(kBlock), 0, s, A.descs,
-                     A.win_bases, A.nchain, A.nwin, A.opstart, A.optime, A.optype, A.op_cap, st,
-                     A.flags);
+                     A.win_bases, A.nchain, A.nwin, A.opstart, A.accmask, A.optime, A.optype,
+                     A.op_cap, st, A.flags);
   // 4. loop graph and union-find
   mark(LC_PH_INIT_PARENT);
   hipLaunchKernelGGL(k_init_parent, dim3(G), dim3(kBlock), 0, s, A.totals, A.node_cap, A.parent);
@@ -1134,7 +1147,7 @@ hipError_t lc_launch_sweep(const LcSweepArgs& A, hipStream_t s) {
                        A.parent, nch, A.rcnt, A.flags);
     (void)lc_launch_scan(A.rcnt, nch, A.scan_tmp, s);
     hipLaunchKernelGGL(k_roots, dim3(grid_for(nch, G)), dim3(kBlock), 0, s, A.descs, A.node_bases,
-                       A.nchain, A.totals, A.parent, A.flipb, A.acc, A.bacc, A.root_cap, nch,
+                       A.nchain, A.totals, A.parent, A.acc, A.bacc, A.root_cap, nch,
                        A.rcnt, st, A.flags);
     hipLaunchKernelGGL(k_loop_bases, dim3(grid_for(A.nchain, 64)), dim3(kBlock), 0, s,
                        A.node_bases, A.nchain, A.parent, A.loop_bases, A.flags);
@@ -1143,16 +1156,16 @@ hipError_t lc_launch_sweep(const LcSweepArgs& A, hipStream_t s) {
   hipLaunchKernelGGL(k_accum, dim3(G), dim3(kBlock), 0, s, A.descs, A.node_bases, A.nchain, A.dyn,
                      A.totals, A.parent, A.optime, A.acc, A.bacc, A.flags);
   mark(LC_PH_CLUSTER_SUMS);
-  hipLaunchKernelGGL(k_cluster_sums, dim3(G), dim3(kBlock), 0, s, A.loop_bases, A.nchain,
+  // few resident threads: each flushes its partial sums with atomics
+  hipLaunchKernelGGL(k_cluster_sums, dim3(G < 2048 ? G : 2048), dim3(kBlock), 0, s, A.loop_bases, A.nchain,
                      A.rcnt + (A.node_cap + kRootChunk - 1) / kRootChunk, A.root_cap, A.acc, st,
                      A.flags);
   mark(LC_PH_FLIP);
   hipLaunchKernelGGL(k_flip_ops, dim3(grid_for(A.nwin, G)), dim3(kBlock), 0, s, A.descs,
-                     A.win_bases, A.nchain, A.nwin, A.dyn, A.opstart, A.parent, A.flipb,
-                     A.optype, A.kflat, st, A.flags);
+                     A.win_bases, A.nchain, A.nwin, A.dyn, A.opstart, A.parent, A.optype,
+                     A.kflat, st, A.flags);
   hipLaunchKernelGGL(k_flip_sites, dim3(grid_for(A.nsites, G)), dim3(kBlock), 0, s, A.descs,
-                     A.site_bases, A.nchain, A.nsites, A.dyn, A.parent, A.flipb, A.bacc, st,
-                     A.flags);
+                     A.site_bases, A.nchain, A.nsites, A.dyn, A.parent, A.bacc, st, A.flags);
   // 6. next world lines
   mark(LC_PH_SCAN_KEPT);
   (void)lc_launch_scan(A.kflat, A.nwin, A.scan_tmp, s);
