@@ -9,9 +9,11 @@ checked), but creating a chain needs the compiled library and a device.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
 import sys
+import weakref
 
 import numpy as np
 
@@ -213,6 +215,14 @@ class _TorchMemory:
 
 _MEMORIES = {}
 _STREAMS = {}
+_LIVE = weakref.WeakSet()  # chains and batches to release before interpreter teardown
+
+
+@atexit.register
+def _close_all():
+    # batches first: they hold chains
+    for o in sorted(list(_LIVE), key=lambda o: not isinstance(o, Batch)):
+        o.close()
 
 
 def library_stream(device=None):
@@ -256,13 +266,15 @@ class Chain:
         _check(lib.lc_init_lattice(self.L, self.S, self.beta, C.c_uint64(self.seed), alloc, strm,
                                    C.byref(h)), "lc_init_lattice")
         self._h = h
+        self._lib = lib
         self.n_sites = self.two_s * self.L
         self.n_bonds = self.two_s * self.two_s * self.L
+        _LIVE.add(self)
 
     def close(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            load().lc_free(h)
+            self._lib.lc_free(h)
         self._h = None
 
     __del__ = close
@@ -366,12 +378,14 @@ class Batch:
         strm = self._mem.handle if self._mem else None
         _check(lib.lc_batch_create(alloc, strm, C.byref(h)), "lc_batch_create")
         self._h = h
+        self._lib = lib
         self.members = []
+        _LIVE.add(self)
 
     def close(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            load().lc_batch_free(h)
+            self._lib.lc_batch_free(h)
         self._h = None
         self.members = []
 

@@ -384,9 +384,24 @@ __device__ inline int64_t next_event(const ChainDesc& D, const int64_t* __restri
   return best;
 }
 
+// Earlier of two candidate events (index, time, bond) in (time, bond,
+// index) order; -1 marks no candidate.
+__device__ inline int64_t earlier(int64_t c1, uint64_t t1, int64_t b1, int64_t c2, uint64_t t2,
+                                  int64_t b2) {
+  if (c1 < 0) return c2;
+  if (c2 < 0) return c1;
+  if (t1 != t2) return t1 < t2 ? c1 : c2;
+  if (b1 != b2) return b1 < b2 ? c1 : c2;
+  return c1 < c2 ? c1 : c2;
+}
+
 // Leg linking (Sec. 2, loops as trees of world-line fragments): the upper
 // node of every operator joins, on each of its two subspins, the lower node
 // of the next event there, or the top node of that subspin after the last.
+// For S = 1/2 the next event on a site is the bond's own next operator or
+// the first operator of the neighbouring bond after it: one forward pointer
+// per neighbour walks that bond's operators as the window's operators
+// advance in time (a merge of three sorted lists).
 __global__ __launch_bounds__(kBlock) void k_link_ops(
     const ChainDesc* __restrict__ descs, const int64_t* __restrict__ win_bases, int nchain,
     int64_t nwin, const ChainDyn* __restrict__ dyn, const int64_t* __restrict__ opstart,
@@ -402,6 +417,36 @@ __global__ __launch_bounds__(kBlock) void k_link_ops(
     const int64_t b = li >> D.w;
     const uint64_t k = static_cast<uint64_t>(li & ((int64_t(1) << D.w) - 1));
     const int64_t xs[2] = {bond_x(D, b), bond_y(D, b)};
+    if (D.two_s == 1) {
+      const int64_t W = int64_t(1) << D.w;
+      const int64_t bl = b == 0 ? D.L - 1 : b - 1, br = b + 1 == D.L ? 0 : b + 1;
+      const int64_t il = D.win_base + bl * W, ir = D.win_base + br * W;
+      const int64_t el = opstart[il + k + 1], er = opstart[ir + k + 1];  // window ends
+      const int64_t lend = opstart[il + W], rend = opstart[ir + W];      // bond ends
+      const int64_t bend = opstart[D.win_base + b * W + W];
+      int64_t pl = opstart[il + k], pr = opstart[ir + k];
+      uint64_t tl = pl < lend ? optime[pl] : 0, tr = pr < rend ? optime[pr] : 0;
+      const int64_t qe = opstart[i + 1];
+      for (int64_t q = opstart[i]; q < qe; ++q) {
+        const uint64_t t = optime[q];
+        while (pl < el && precedes(tl, bl, t, b)) {
+          ++pl;
+          tl = pl < lend ? optime[pl] : 0;
+        }
+        while (pr < er && precedes(tr, br, t, b)) {
+          ++pr;
+          tr = pr < rend ? optime[pr] : 0;
+        }
+        const int64_t own = q + 1 < bend ? q + 1 : -1;
+        const uint64_t tn = own >= 0 ? optime[own] : 0;
+        const int64_t nx = earlier(own, tn, b, pl < lend ? pl : -1, tl, bl);
+        const int64_t ny = earlier(own, tn, b, pr < rend ? pr : -1, tr, br);
+        const int64_t up = dy.node_base + D.nbn + 2 * (q - dy.op_base) + 1;
+        uf_union(parent, up, nx >= 0 ? dy.node_base + D.nbn + 2 * (nx - dy.op_base) : dy.node_base + xs[0]);
+        uf_union(parent, up, ny >= 0 ? dy.node_base + D.nbn + 2 * (ny - dy.op_base) : dy.node_base + xs[1]);
+      }
+      continue;
+    }
     for (int64_t q = opstart[i]; q < opstart[i + 1]; ++q) {
       const uint64_t t = optime[q];
       const int64_t up = dy.node_base + D.nbn + 2 * (q - dy.op_base) + 1;
