@@ -346,11 +346,15 @@ ChainDesc make_desc(const lc_chain* c, int64_t win_base, int64_t site_base, int6
   return d;
 }
 
-// Loops: every boundary node may be alone; operator nodes form loops of at
-// least two nodes, about 0.29 loops per node at low temperature (0.398 loops
-// and 0.693 operators per unit L beta for S=1/2).  Grown on overflow.
-int64_t loops_estimate(int64_t nbn, int64_t ops) {
-  return nbn + static_cast<int64_t>(0.32 * 2.0 * static_cast<double>(ops)) + 65536;
+// Loop records needed by a chain: every boundary node may be alone; operator
+// nodes form loops of at least two nodes.  For S = 1/2 the closed two-node
+// loops (nine in ten at low temperature) are finished while linking and take
+// no record: about 0.04 recorded loops per unit L beta remain against 0.69
+// operators.  Split spins keep a record per loop (about 0.29 per node).
+// Grown on overflow.
+int64_t loops_estimate(int64_t nbn, int two_s, int64_t ops) {
+  const double per_op_node = two_s == 1 ? 0.08 : 0.32;
+  return nbn + static_cast<int64_t>(per_op_node * 2.0 * static_cast<double>(ops));
 }
 
 // Initial kept-operator capacity per buffer: about 0.3 off-diagonal
@@ -406,6 +410,18 @@ int ensure_scratch(Arena& A, int64_t ops, int64_t nodes, int64_t roots) {
 }
 
 // (Re)build the flat layout of an engine's chains and upload descriptors.
+// Loop records for an engine whose chains need ops operators in all: each
+// chain's share of ops by its own estimate.
+int64_t loops_needed(const Engine& E, int64_t ops) {
+  int64_t est = 0, sum = 0;
+  for (const lc_chain* c : E.chains) est += ops_estimate(c);
+  for (const lc_chain* c : E.chains) {
+    const double share = est > 0 ? static_cast<double>(ops_estimate(c)) / static_cast<double>(est) : 0.0;
+    sum += loops_estimate(c->nbn, c->two_s, static_cast<int64_t>(share * static_cast<double>(ops)));
+  }
+  return sum + 65536;
+}
+
 int layout(Engine& E) {
   const int n = static_cast<int>(E.chains.size());
   std::vector<ChainDesc> h(n);
@@ -439,7 +455,7 @@ int layout(Engine& E) {
        A.grow(A.accmask, static_cast<size_t>(std::max<int64_t>(nwin, 1))) &&
        A.grow(A.bacc, static_cast<size_t>(std::max<int64_t>(nsites, 1)));
   if (!ok) return LC_ENOMEM;
-  int rc = ensure_scratch(A, ops, nbn + 2 * ops, loops_estimate(nbn, ops));
+  int rc = ensure_scratch(A, ops, nbn + 2 * ops, loops_needed(E, ops));
   if (rc != LC_OK) return rc;
   E.nwin = nwin;
   E.nsites = nsites;
@@ -470,7 +486,7 @@ int ensure_capacity(Engine& E, int64_t at_least_ops) {
   int64_t ops = 0;
   for (lc_chain* c : E.chains) ops += ops_estimate(c);
   ops = std::max(ops, at_least_ops);
-  return ensure_scratch(*E.ar, ops, E.sum_nbn + 2 * ops, loops_estimate(E.sum_nbn, ops));
+  return ensure_scratch(*E.ar, ops, E.sum_nbn + 2 * ops, loops_needed(E, ops));
 }
 
 LcSweepArgs sweep_args(Engine& E) {
@@ -701,7 +717,8 @@ void footprint_parts(int64_t L, int two_s, double beta, double* state_b, double*
   const double kept = static_cast<double>(kept_initial(static_cast<int64_t>(n_bonds), beta));
   const double ops = ops_bound(kept, n_bonds, static_cast<double>(L), two_s, beta);
   const double nodes = nbn + 2 * ops;
-  const double loops = static_cast<double>(loops_estimate(static_cast<int64_t>(nbn), static_cast<int64_t>(ops)));
+  const double loops =
+      static_cast<double>(loops_estimate(static_cast<int64_t>(nbn), two_s, static_cast<int64_t>(ops)) + 65536);
   // spins, kept-operator window scans and times (both halves), permutation
   *state_b = 2 * n_sites + 2 * 8 * (nwin + 1) + 2 * 8 * kept + 8 * n_sites + 65536;
   // window scans, operators (time + type), parent words, loop records

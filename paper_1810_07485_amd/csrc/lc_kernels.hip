@@ -24,6 +24,10 @@ namespace lc {
 constexpr int kBlock = 256;
 constexpr int kCap = 24;  // candidates per window held in LDS; more are redrawn
 
+// Parent word of the upper node of a closed two-node loop (see k_link_ops):
+// below every root code -1 - index, so no kernel takes it for a loop index.
+constexpr int64_t kPairRoot = INT64_MIN;
+
 __device__ inline int lane_id() { return __lane_id(); }
 
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
@@ -37,51 +41,83 @@ __device__ inline int64_t xcd_block() {
   return (p & 7) * (G >> 3) + (p >> 3);
 }
 
-// Add v to *dst once per wave when all lanes agree on dst, else per lane.
-__device__ inline void wave_add_u64(unsigned long long* dst, uint64_t v) {
-  const unsigned long long d0 = __shfl(reinterpret_cast<unsigned long long>(dst), 0);
-  if (__all(reinterpret_cast<unsigned long long>(dst) == d0)) {
-    uint64_t s = v;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if (lane_id() == 0 && s) atomicAdd(dst, static_cast<unsigned long long>(s));
-  } else if (v) {
-    atomicAdd(dst, static_cast<unsigned long long>(v));
-  }
-}
+// Block-level flushes of per-thread statistics.  Every thread holds a
+// chain c (-1: none) and a value for one statistics word of that chain; the
+// values are summed over the wave with shuffles and over the block's waves
+// through LDS, and one atomic per block and word reaches the counter when
+// the whole block names one chain (per wave, or per lane, otherwise).  The
+// statistics words are few, so the number of same-address atomics, not
+// their total, is what costs.  Convergent: every thread of the block calls.
+constexpr int kWaves = kBlock / 64;
 
-__device__ inline void wave_add_u128(unsigned long long* lo, unsigned long long* hi, uint64_t xlo,
-                                     uint64_t xhi) {
-  const unsigned long long d0 = __shfl(reinterpret_cast<unsigned long long>(lo), 0);
-  if (__all(reinterpret_cast<unsigned long long>(lo) == d0)) {
-    // reduce 128-bit values across the wave
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const uint64_t ol = __shfl_xor(xlo, o), oh = __shfl_xor(xhi, o);
-      const uint64_t s = xlo + ol;
-      xhi = xhi + oh + (s < xlo ? 1u : 0u);
-      xlo = s;
-    }
-    if (lane_id() == 0 && (xlo | xhi)) atomic_add_u128(lo, hi, xlo, xhi);
+enum FlushOp { FLUSH_ADD, FLUSH_MAX };
+
+// (lo, hi) += (xlo, xhi) as a 128-bit sum; hi < 0: a single 64-bit word;
+// FLUSH_MAX: lo = max(lo, xlo).
+__device__ inline void stat_apply(unsigned long long* stats, int c, int ilo, int ihi, FlushOp op,
+                                  uint64_t xlo, uint64_t xhi) {
+  unsigned long long* st = stats + static_cast<int64_t>(c) * ST_WORDS;
+  if (op == FLUSH_MAX) {
+    if (xlo) atomicMax(st + ilo, static_cast<unsigned long long>(xlo));
+  } else if (ihi < 0) {
+    if (xlo) atomicAdd(st + ilo, static_cast<unsigned long long>(xlo));
   } else if (xlo | xhi) {
-    atomic_add_u128(lo, hi, xlo, xhi);
+    atomic_add_u128(st + ilo, st + ihi, xlo, xhi);
   }
 }
 
-__device__ inline uint64_t wave_max_u64(uint64_t v) {
+__device__ inline void stat_combine(FlushOp op, uint64_t& alo, uint64_t& ahi, uint64_t blo,
+                                    uint64_t bhi) {
+  if (op == FLUSH_MAX) {
+    alo = blo > alo ? blo : alo;
+  } else {
+    const uint64_t s = alo + blo;
+    ahi = ahi + bhi + (s < alo ? 1u : 0u);
+    alo = s;
+  }
+}
+
+__device__ inline void block_flush(unsigned long long* stats, int c, int ilo, int ihi, FlushOp op,
+                                   uint64_t xlo, uint64_t xhi) {
+  __shared__ uint64_t slo[kWaves], shi[kWaves];
+  __shared__ int sc[kWaves];
+  const int lane = lane_id(), wv = threadIdx.x >> 6;
+  const int c0 = __shfl(c, 0);
+  const bool uni = __all(c == c0);
+  if (!uni) {  // the wave spans chains: per lane
+    if (c >= 0) stat_apply(stats, c, ilo, ihi, op, xlo, xhi);
+    xlo = xhi = 0;
+  }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
-    const uint64_t w = __shfl_xor(v, o);
-    v = w > v ? w : v;
+    const uint64_t ol = __shfl_xor(xlo, o), oh = __shfl_xor(xhi, o);
+    stat_combine(op, xlo, xhi, ol, oh);
   }
-  return v;
+  if (lane == 0) {
+    slo[wv] = xlo;
+    shi[wv] = xhi;
+    sc[wv] = uni ? c0 : -1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    bool same = sc[0] >= 0;
+    for (int w = 1; w < kWaves; ++w) same = same && sc[w] == sc[0];
+    if (same) {
+      uint64_t tlo = slo[0], thi = shi[0];
+      for (int w = 1; w < kWaves; ++w) stat_combine(op, tlo, thi, slo[w], shi[w]);
+      stat_apply(stats, sc[0], ilo, ihi, op, tlo, thi);
+    } else {
+      for (int w = 0; w < kWaves; ++w)
+        if (sc[w] >= 0) stat_apply(stats, sc[w], ilo, ihi, op, slo[w], shi[w]);
+    }
+  }
+  __syncthreads();  // the LDS slots are reused by the next flush
 }
 
 // Per-thread partial sums of one chain's statistics.  A thread walks its
 // items in increasing flat index, so it meets each chain in one stretch: the
 // sums go to the chain's counters when the thread moves on to another chain
-// (per lane, rare) and once at the end (one atomic per wave when the wave
-// agrees on the chain).
+// (per lane, rare) and once at the end (block_flush).
 template <int N>
 struct Partial {
   int c;
@@ -101,11 +137,10 @@ struct Partial {
     for (int i = 0; i < N; ++i) v[i] = 0;
     c = cn;
   }
-  // convergent: every lane of the wave must call it
+  // convergent: every thread of the block must call it
   __device__ void flush(unsigned long long* stats, const int (&idx)[N]) {
-    const int cf = c < 0 ? 0 : c;
 #pragma unroll
-    for (int i = 0; i < N; ++i) wave_add_u64(stats + static_cast<int64_t>(cf) * ST_WORDS + idx[i], v[i]);
+    for (int i = 0; i < N; ++i) block_flush(stats, c, idx[i], -1, FLUSH_ADD, v[i], 0);
   }
 };
 
@@ -402,12 +437,54 @@ __device__ inline int64_t earlier(int64_t c1, uint64_t t1, int64_t b1, int64_t c
 // the first operator of the neighbouring bond after it: one forward pointer
 // per neighbour walks that bond's operators as the window's operators
 // advance in time (a merge of three sorted lists).
+//
+// When the next event on both sites of operator q is the bond's own next
+// operator q+1, upper(q) and lower(q+1) are joined by both of their edges
+// and by nothing else: a closed loop of two nodes (nine loops in ten at low
+// temperature).  It is finished here without union-find: plain stores mark
+// it (kPairRoot at its smallest node upper(q), lower(q+1) -> upper(q)), and
+// its estimators (size 2, no boundary node, length 2 (t_{q+1} - t_q)) go to
+// the chain statistics; the root and accumulation kernels skip it.
+struct PairSums {
+  int c = -1;
+  uint64_t n = 0, l2lo = 0, l2hi = 0;
+  __device__ void flush_lane(unsigned long long* stats) {
+    if (c < 0 || n == 0) return;
+    unsigned long long* st = stats + static_cast<int64_t>(c) * ST_WORDS;
+    atomicAdd(st + ST_CLUSTERS, n);
+    atomic_add_u128(st + ST_SIZE2_LO, st + ST_SIZE2_HI, 4 * n, 0);
+    if (l2lo | l2hi) atomic_add_u128(st + ST_LEN2_LO, st + ST_LEN2_HI, l2lo, l2hi);
+    atomicMax(st + ST_MAXSIZE, 2ull);
+    n = l2lo = l2hi = 0;
+  }
+  __device__ void at(int cn, unsigned long long* stats) {
+    if (cn == c) return;
+    flush_lane(stats);
+    c = cn;
+  }
+  __device__ void add(uint64_t dt) {
+    n += 1;
+    const uint64_t l32 = dt >> 31;  // (2 dt) >> 32
+    const u128p q = mul64x64(l32, l32);
+    l2lo += q.lo;
+    l2hi += q.hi + (l2lo < q.lo ? 1u : 0u);
+  }
+  // convergent: every thread of the block must call it
+  __device__ void flush(unsigned long long* stats) {
+    block_flush(stats, c, ST_CLUSTERS, -1, FLUSH_ADD, n, 0);
+    block_flush(stats, c, ST_SIZE2_LO, ST_SIZE2_HI, FLUSH_ADD, 4 * n, 0);
+    block_flush(stats, c, ST_LEN2_LO, ST_LEN2_HI, FLUSH_ADD, l2lo, l2hi);
+    block_flush(stats, c, ST_MAXSIZE, -1, FLUSH_MAX, n ? 2 : 0, 0);
+  }
+};
+
 __global__ __launch_bounds__(kBlock) void k_link_ops(
     const ChainDesc* __restrict__ descs, const int64_t* __restrict__ win_bases, int nchain,
     int64_t nwin, const ChainDyn* __restrict__ dyn, const int64_t* __restrict__ opstart,
     const uint64_t* __restrict__ optime, int64_t* __restrict__ parent,
-    const uint32_t* __restrict__ flags) {
+    unsigned long long* __restrict__ stats, const uint32_t* __restrict__ flags) {
   if (*flags) return;
+  PairSums pairs;
   for (int64_t i = xcd_block() * kBlock + threadIdx.x; i < nwin;
        i += static_cast<int64_t>(gridDim.x) * kBlock) {
     const int c = chain_of(win_bases, nchain, i);
@@ -442,6 +519,13 @@ __global__ __launch_bounds__(kBlock) void k_link_ops(
         const int64_t nx = earlier(own, tn, b, pl < lend ? pl : -1, tl, bl);
         const int64_t ny = earlier(own, tn, b, pr < rend ? pr : -1, tr, br);
         const int64_t up = dy.node_base + D.nbn + 2 * (q - dy.op_base) + 1;
+        if (own >= 0 && nx == own && ny == own) {  // closed two-node loop
+          parent[up] = kPairRoot;
+          parent[up + 1] = up;
+          pairs.at(c, stats);
+          pairs.add(tn - t);
+          continue;
+        }
         uf_union(parent, up, nx >= 0 ? dy.node_base + D.nbn + 2 * (nx - dy.op_base) : dy.node_base + xs[0]);
         uf_union(parent, up, ny >= 0 ? dy.node_base + D.nbn + 2 * (ny - dy.op_base) : dy.node_base + xs[1]);
       }
@@ -459,6 +543,7 @@ __global__ __launch_bounds__(kBlock) void k_link_ops(
       }
     }
   }
+  pairs.flush(stats);
 }
 
 // Boundary nodes: bottom(x) joins the lower node of the first event on x;
@@ -590,11 +675,11 @@ __global__ __launch_bounds__(kBlock) void k_compress(const int64_t* __restrict__
   for (int64_t g = xcd_block() * kBlock + threadIdx.x; g < n;
        g += static_cast<int64_t>(gridDim.x) * kBlock) {
     int64_t r = g, p = parent[g];
-    while (p != r) {
+    while (p != r && p >= 0) {  // a negative word marks a finished two-node loop
       r = p;
       p = parent[r];
     }
-    parent[g] = r;
+    if (r != g) parent[g] = r;
   }
 }
 
@@ -650,7 +735,6 @@ __device__ inline int64_t block_exclusive_scan(int64_t v, int64_t* sh, int64_t& 
 constexpr int kAccWords = LC_ACC_WORDS;
 constexpr int kRootPer = 16;                      // steps per chunk
 constexpr int kRootChunk = kBlock * kRootPer;     // nodes per chunk
-constexpr int kWaves = kBlock / 64;
 
 __global__ __launch_bounds__(kBlock) void k_root_count(const int64_t* __restrict__ totals,
                                                         const int64_t* __restrict__ parent,
@@ -782,25 +866,29 @@ __global__ __launch_bounds__(kBlock) void k_accum(
       const ChainDyn dy = dyn[c];
       const int64_t v = g - dy.node_base;
       const int64_t p = parent[g];
-      r = -1 - (p >= 0 ? parent[p] : p);
-      w0 = 1;
-      if (v < D.nbn) {
-        const bool bottom = v < D.n_sites;
-        if ((D.two_s == 1) || !bottom) w0 += 1ull << 40;  // top node: + 2^64
-        const int64_t root = (p >= 0 ? p : g) - dy.node_base;
-        if (bottom && root < D.n_sites)  // always true: the root is a bottom node
-          atomicAdd(bacc + D.site_base + root,
-                    1ull + (static_cast<uint64_t>(2 * static_cast<int64_t>(D.s0[D.cur][v]) - 1) << 32));
-      } else {
-        const int64_t q = (v - D.nbn) >> 1;
-        const uint64_t t = optime[dy.op_base + q];
-        const uint64_t th = t >> 32, tl = t & 0xFFFFFFFFull;
-        if (((v - D.nbn) & 1) == 0) {
-          w1 = th;
-          w2 = tl;
+      const int64_t code = p >= 0 ? parent[p] : p;
+      active = code != kPairRoot;  // two-node loops were finished while linking
+      if (active) {
+        r = -1 - code;
+        w0 = 1;
+        if (v < D.nbn) {
+          const bool bottom = v < D.n_sites;
+          if ((D.two_s == 1) || !bottom) w0 += 1ull << 40;  // top node: + 2^64
+          const int64_t root = (p >= 0 ? p : g) - dy.node_base;
+          if (bottom && root < D.n_sites)  // always true: the root is a bottom node
+            atomicAdd(bacc + D.site_base + root,
+                      1ull + (static_cast<uint64_t>(2 * static_cast<int64_t>(D.s0[D.cur][v]) - 1) << 32));
         } else {
-          w1 = 0 - th;
-          w2 = 0 - tl;
+          const int64_t q = (v - D.nbn) >> 1;
+          const uint64_t t = optime[dy.op_base + q];
+          const uint64_t th = t >> 32, tl = t & 0xFFFFFFFFull;
+          if (((v - D.nbn) & 1) == 0) {
+            w1 = th;
+            w2 = tl;
+          } else {
+            w1 = 0 - th;
+            w2 = 0 - tl;
+          }
         }
       }
     }
@@ -902,17 +990,9 @@ __global__ __launch_bounds__(kBlock) void k_cluster_sums(
     l2hi += l2.hi + (l2lo < l2.lo ? 1u : 0u);
     mx = sz > mx ? sz : mx;
   }
-  const int cf = cc < 0 ? 0 : cc;
-  unsigned long long* st = stats + static_cast<int64_t>(cf) * ST_WORDS;
-  wave_add_u128(st + ST_SIZE2_LO, st + ST_SIZE2_HI, s2lo, s2hi);
-  wave_add_u128(st + ST_LEN2_LO, st + ST_LEN2_HI, l2lo, l2hi);
-  const unsigned long long d0 = __shfl(reinterpret_cast<unsigned long long>(st), 0);
-  if (__all(reinterpret_cast<unsigned long long>(st) == d0)) {
-    const uint64_t wm = wave_max_u64(mx);
-    if (lane_id() == 0 && wm) atomicMax(st + ST_MAXSIZE, wm);
-  } else if (mx) {
-    atomicMax(st + ST_MAXSIZE, mx);
-  }
+  block_flush(stats, cc, ST_SIZE2_LO, ST_SIZE2_HI, FLUSH_ADD, s2lo, s2hi);
+  block_flush(stats, cc, ST_LEN2_LO, ST_LEN2_HI, FLUSH_ADD, l2lo, l2hi);
+  block_flush(stats, cc, ST_MAXSIZE, -1, FLUSH_MAX, mx, 0);
 }
 
 // Flip bit of the loop through node g, from its root (the loop's smallest
@@ -1174,7 +1254,8 @@ hipError_t lc_launch_sweep(const LcSweepArgs& A, hipStream_t s) {
   hipLaunchKernelGGL(k_init_parent, dim3(G), dim3(kBlock), 0, s, A.totals, A.node_cap, A.parent);
   mark(LC_PH_LINK_OPS);
   hipLaunchKernelGGL(k_link_ops, dim3(grid_for(A.nwin, G)), dim3(kBlock), 0, s, A.descs,
-                     A.win_bases, A.nchain, A.nwin, A.dyn, A.opstart, A.optime, A.parent, A.flags);
+                     A.win_bases, A.nchain, A.nwin, A.dyn, A.opstart, A.optime, A.parent, st,
+                     A.flags);
   mark(LC_PH_LINK_SITES);
   hipLaunchKernelGGL(k_link_sites, dim3(grid_for(A.nsites, G)), dim3(kBlock), 0, s, A.descs,
                      A.site_bases, A.nchain, A.nsites, A.dyn, A.opstart, A.optime, A.parent,
