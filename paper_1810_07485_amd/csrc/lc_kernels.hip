@@ -22,7 +22,7 @@
 namespace lc {
 
 constexpr int kBlock = 256;
-constexpr int kCap = 24;  // candidates per window held in LDS; more are redrawn
+constexpr int kCap = 12;  // candidate times per window kept in LDS while writing; more are redrawn
 
 // Parent word of the upper node of a closed two-node loop (see k_link_ops):
 // below every root code -1 - index, so no kernel takes it for a loop index.
@@ -234,7 +234,8 @@ __global__ __launch_bounds__(kBlock) void k_gen(const ChainDesc* __restrict__ de
                                                 uint8_t* __restrict__ optype, int64_t op_cap,
                                                 unsigned long long* __restrict__ stats,
                                                 uint32_t* __restrict__ flags) {
-  __shared__ uint64_t slot[kCap * kBlock];
+  // only the writing pass keeps candidate times (LDS bounds its occupancy)
+  __shared__ uint64_t slot[WRITE ? kCap * kBlock : 1];
   const int tid = threadIdx.x;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
   const int64_t start = xcd_block() * kBlock + tid;
@@ -258,7 +259,7 @@ __global__ __launch_bounds__(kBlock) void k_gen(const ChainDesc* __restrict__ de
       int n = 0;
       while (n < D.K && u >= D.T[n]) ++n;
       ncand = static_cast<uint32_t>(n);
-      const bool inlds = n <= kCap;
+      const bool inlds = WRITE && n <= kCap;
       const bool known = WRITE && n <= 32;
       uint64_t accm = known ? accmask[i] : 0;
       for (int j = 0; j < n; ++j) {
@@ -892,43 +893,49 @@ __global__ __launch_bounds__(kBlock) void k_accum(
         }
       }
     }
-    // Reduce by loop within the wave: bitonic sort of (loop, sums) over the
-    // 64 lanes, segmented sums, then one set of atomics per distinct loop
-    // (about 27 distinct loops per 64 consecutive nodes at low temperature).
+    // Reduce by loop within the wave: bitonic sort of one packed word per
+    // lane, (loop << 6) | lane (loop indices are below 2^40), so only the key
+    // moves through the 21 exchange stages; each lane then fetches the sums
+    // of the element it ended up with, a segmented scan adds equal loops, and
+    // the last lane of each run issues one set of atomics per distinct loop.
     const int lane = lane_id();
-    int64_t key = active ? r : INT64_MAX;
+    uint64_t sk = active ? ((static_cast<uint64_t>(r) << 6) | static_cast<uint64_t>(lane)) : ~0ull;
 #pragma unroll
     for (int k = 2; k <= 64; k <<= 1) {
 #pragma unroll
       for (int j = k >> 1; j > 0; j >>= 1) {
-        const int64_t pk = __shfl_xor(key, j);
-        const uint64_t p0 = __shfl_xor(w0, j), p1 = __shfl_xor(w1, j);
-        const uint64_t p2 = __shfl_xor(w2, j);
+        const uint64_t pk = __shfl_xor(sk, j);
         const bool ascending = (lane & k) == 0, lower = (lane & j) == 0;
-        const bool take = (lower == ascending) ? (pk < key) : (pk > key);
-        if (take) {
-          key = pk;
-          w0 = p0;
-          w1 = p1;
-          w2 = p2;
-        }
+        const bool take = (lower == ascending) ? (pk < sk) : (pk > sk);
+        sk = take ? pk : sk;
       }
     }
+    const int src = static_cast<int>(sk & 63ull);
+    const int64_t key = sk == ~0ull ? INT64_MAX : static_cast<int64_t>(sk >> 6);
+    // per-wave node and top counts fit 16 bits each
+    uint32_t c0 = static_cast<uint32_t>(__shfl(static_cast<uint32_t>((w0 & 0xFFFFull) | ((w0 >> 40) << 16)), src));
+    w1 = __shfl(w1, src);
+    w2 = __shfl(w2, src);
+    // runs of equal loops: head lanes from one ballot, segment id = heads so far
+    const int64_t pkey = __shfl_up(key, 1);
+    const unsigned long long heads = __ballot(lane == 0 || pkey != key);
+    const int seg = __popcll(heads & ((lane == 63) ? ~0ull : ((2ull << lane) - 1ull)));
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
-      const int64_t qk = __shfl_up(key, d);
-      const uint64_t q0 = __shfl_up(w0, d), q1 = __shfl_up(w1, d);
-      const uint64_t q2 = __shfl_up(w2, d);
-      if (lane >= d && qk == key) {
-        w0 += q0;
+      const int qs = __shfl_up(seg, d);
+      const uint32_t q0 = __shfl_up(c0, d);
+      const uint64_t q1 = __shfl_up(w1, d), q2 = __shfl_up(w2, d);
+      if (lane >= d && qs == seg) {
+        c0 += q0;
         w1 += q1;
         w2 += q2;
       }
     }
-    const int64_t nk = __shfl_down(key, 1);
-    if (key != INT64_MAX && (lane == 63 || nk != key)) {
+    const bool last = lane == 63 || ((heads >> (lane + 1)) & 1ull);
+    if (key != INT64_MAX && last) {
       unsigned long long* a = acc + kAccWords * key;
-      atomicAdd(a + 0, static_cast<unsigned long long>(w0));
+      const uint64_t v0 = static_cast<uint64_t>(c0 & 0xFFFFu) + (static_cast<uint64_t>(c0 >> 16) << 40);
+      atomicAdd(a + 0, static_cast<unsigned long long>(v0));
       if (w1) atomicAdd(a + 1, static_cast<unsigned long long>(w1));
       if (w2) atomicAdd(a + 2, static_cast<unsigned long long>(w2));
     }
