@@ -668,14 +668,25 @@ __global__ __launch_bounds__(kBlock) void k_symmetrize(
 }
 
 // Full path compression: parent[g] = root = smallest node of g's loop.
+// Roots (parent[g] == g) are counted per chunk of 4,096 nodes on the way
+// (each wave covers 64 consecutive nodes of one chunk): rcnt feeds the
+// numbering of the loops.
 __global__ __launch_bounds__(kBlock) void k_compress(const int64_t* __restrict__ totals,
                                                       int64_t* __restrict__ parent,
+                                                      unsigned long long* __restrict__ rcnt,
                                                       const uint32_t* __restrict__ flags) {
   if (*flags) return;
   const int64_t n = totals[1];
-  for (int64_t g = xcd_block() * kBlock + threadIdx.x; g < n;
-       g += static_cast<int64_t>(gridDim.x) * kBlock) {
-    int64_t r = g, p = parent[g];
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+  const int64_t iters = (n + stride - 1) / stride;
+  for (int64_t it = 0; it < iters; ++it) {
+    const int64_t g = xcd_block() * kBlock + threadIdx.x + it * stride;
+    const int64_t p0 = g < n ? parent[g] : -1;
+    const unsigned long long roots = __ballot(p0 == g);
+    if (lane_id() == 0 && roots)
+      atomicAdd(rcnt + (g >> 12), static_cast<unsigned long long>(__popcll(roots)));
+    if (g >= n) continue;
+    int64_t r = g, p = p0;
     while (p != r && p >= 0) {  // a negative word marks a finished two-node loop
       r = p;
       p = parent[r];
@@ -735,39 +746,8 @@ __device__ inline int64_t block_exclusive_scan(int64_t v, int64_t* sh, int64_t& 
 // in its step, and of lower lanes in its wave's ballot.
 constexpr int kAccWords = LC_ACC_WORDS;
 constexpr int kRootPer = 16;                      // steps per chunk
-constexpr int kRootChunk = kBlock * kRootPer;     // nodes per chunk
-
-__global__ __launch_bounds__(kBlock) void k_root_count(const int64_t* __restrict__ totals,
-                                                        const int64_t* __restrict__ parent,
-                                                        int64_t nchunks, int64_t* __restrict__ rcnt,
-                                                        const uint32_t* __restrict__ flags) {
-  __shared__ int wsum[kWaves];
-  if (*flags) return;
-  const int64_t n = totals[1];
-  const int lane = lane_id(), wv = threadIdx.x >> 6;
-  for (int64_t ch = xcd_block(); ch < nchunks; ch += gridDim.x) {
-    int64_t pv[kRootPer];
-#pragma unroll
-    for (int s = 0; s < kRootPer; ++s) {
-      const int64_t g = ch * kRootChunk + s * kBlock + threadIdx.x;
-      pv[s] = g < n ? parent[g] : -1;
-    }
-    int cnt = 0;
-#pragma unroll
-    for (int s = 0; s < kRootPer; ++s)
-      cnt += pv[s] == ch * kRootChunk + s * kBlock + threadIdx.x ? 1 : 0;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
-    if (lane == 0) wsum[wv] = cnt;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      int t = 0;
-      for (int q = 0; q < kWaves; ++q) t += wsum[q];
-      rcnt[ch] = t;
-    }
-    __syncthreads();
-  }
-}
+constexpr int kRootChunk = kBlock * kRootPer;     // nodes per chunk (2^12, counted in k_compress)
+static_assert(kRootChunk == 4096, "k_compress counts roots per 4,096 nodes");
 
 // Roots: compact index (stored as the code -1 - index in the root's parent
 // word), cleared accumulators, loop count.  A loop
@@ -856,34 +836,49 @@ __global__ __launch_bounds__(kBlock) void k_accum(
   const int64_t n = totals[1];
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
   const int64_t iters = (n + stride - 1) / stride;
+  // fields of the chain of the current node, reloaded only when the node
+  // leaves the chain's range [cbeg, cend)
+  int64_t cbeg = 0, cend = -1, op_base = 0, nbn = 0, n_sites = 0, site_base = 0;
+  int two_s = 1;
+  const uint8_t* s0p = nullptr;
   for (int64_t it = 0; it < iters; ++it) {
     const int64_t g = xcd_block() * kBlock + threadIdx.x + it * stride;
     bool active = g < n;
     int64_t r = -1;
     uint64_t w0 = 0, w1 = 0, w2 = 0;
     if (active) {
-      const int c = chain_of(node_bases, nchain, g);
-      const ChainDesc& D = descs[c];
-      const ChainDyn dy = dyn[c];
-      const int64_t v = g - dy.node_base;
+      if (g < cbeg || g >= cend) {
+        const int c = chain_of(node_bases, nchain, g);
+        const ChainDesc& D = descs[c];
+        const ChainDyn dy = dyn[c];
+        cbeg = dy.node_base;
+        cend = dy.node_base + dy.n_nodes;
+        op_base = dy.op_base;
+        nbn = D.nbn;
+        n_sites = D.n_sites;
+        site_base = D.site_base;
+        two_s = D.two_s;
+        s0p = D.s0[D.cur];
+      }
+      const int64_t v = g - cbeg;
       const int64_t p = parent[g];
       const int64_t code = p >= 0 ? parent[p] : p;
       active = code != kPairRoot;  // two-node loops were finished while linking
       if (active) {
         r = -1 - code;
         w0 = 1;
-        if (v < D.nbn) {
-          const bool bottom = v < D.n_sites;
-          if ((D.two_s == 1) || !bottom) w0 += 1ull << 40;  // top node: + 2^64
-          const int64_t root = (p >= 0 ? p : g) - dy.node_base;
-          if (bottom && root < D.n_sites)  // always true: the root is a bottom node
-            atomicAdd(bacc + D.site_base + root,
-                      1ull + (static_cast<uint64_t>(2 * static_cast<int64_t>(D.s0[D.cur][v]) - 1) << 32));
+        if (v < nbn) {
+          const bool bottom = v < n_sites;
+          if ((two_s == 1) || !bottom) w0 += 1ull << 40;  // top node: + 2^64
+          const int64_t root = (p >= 0 ? p : g) - cbeg;
+          if (bottom && root < n_sites)  // always true: the root is a bottom node
+            atomicAdd(bacc + site_base + root,
+                      1ull + (static_cast<uint64_t>(2 * static_cast<int64_t>(s0p[v]) - 1) << 32));
         } else {
-          const int64_t q = (v - D.nbn) >> 1;
-          const uint64_t t = optime[dy.op_base + q];
+          const int64_t q = (v - nbn) >> 1;
+          const uint64_t t = optime[op_base + q];
           const uint64_t th = t >> 32, tl = t & 0xFFFFFFFFull;
-          if (((v - D.nbn) & 1) == 0) {
+          if (((v - nbn) & 1) == 0) {
             w1 = th;
             w2 = tl;
           } else {
@@ -1271,13 +1266,15 @@ hipError_t lc_launch_sweep(const LcSweepArgs& A, hipStream_t s) {
     hipLaunchKernelGGL(k_symmetrize, dim3(grid_for(A.nspins, G)), dim3(kBlock), 0, s, A.descs,
                        A.spin_bases, A.nchain, A.nspins, A.dyn, A.parent, A.flags);
   mark(LC_PH_COMPRESS);
-  hipLaunchKernelGGL(k_compress, dim3(G), dim3(kBlock), 0, s, A.totals, A.parent, A.flags);
+  const int64_t nroot_chunks = (A.node_cap + kRootChunk - 1) / kRootChunk;
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(nroot_chunks + 1, 1024)), dim3(kBlock), 0, s,
+                     reinterpret_cast<unsigned long long*>(A.rcnt), nroot_chunks + 1, 0ull);
+  hipLaunchKernelGGL(k_compress, dim3(G), dim3(kBlock), 0, s, A.totals, A.parent,
+                     reinterpret_cast<unsigned long long*>(A.rcnt), A.flags);
   // 5. flips and estimators
   mark(LC_PH_ROOTS);
   {
-    const int64_t nch = (A.node_cap + kRootChunk - 1) / kRootChunk;
-    hipLaunchKernelGGL(k_root_count, dim3(grid_for(nch, G)), dim3(kBlock), 0, s, A.totals,
-                       A.parent, nch, A.rcnt, A.flags);
+    const int64_t nch = nroot_chunks;
     (void)lc_launch_scan(A.rcnt, nch, A.scan_tmp, s);
     hipLaunchKernelGGL(k_roots, dim3(grid_for(nch, G)), dim3(kBlock), 0, s, A.descs, A.node_bases,
                        A.nchain, A.totals, A.parent, A.acc, A.bacc, A.root_cap, nch,
