@@ -818,6 +818,23 @@ __global__ __launch_bounds__(kBlock) void k_roots(
   part.flush(stats, kIdx);
 }
 
+__device__ inline uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint32_t w = __shfl_xor(v, o);
+    v = w > v ? w : v;
+  }
+  return v;
+}
+
+__device__ inline void flush_carry(unsigned long long* acc, int64_t key, uint64_t v0, uint64_t v1,
+                                   uint64_t v2) {
+  unsigned long long* a = acc + kAccWords * key;
+  atomicAdd(a + 0, static_cast<unsigned long long>(v0));
+  if (v1) atomicAdd(a + 1, static_cast<unsigned long long>(v1));
+  if (v2) atomicAdd(a + 2, static_cast<unsigned long long>(v2));
+}
+
 // Per-loop accumulators (before the flip), three 64-bit words per loop:
 //   [0] nodes + (top nodes << 40)
 //   [1] sum of +-hi32(t), [2] sum of +-lo32(t)  over operator nodes: lower
@@ -841,6 +858,9 @@ __global__ __launch_bounds__(kBlock) void k_accum(
   int64_t cbeg = 0, cend = -1, op_base = 0, nbn = 0, n_sites = 0, site_base = 0;
   int two_s = 1;
   const uint8_t* s0p = nullptr;
+  // wave carry: sums of one hot loop (wave-uniform), flushed once
+  int64_t ck = -1;
+  uint64_t cv0 = 0, cv1 = 0, cv2 = 0;
   for (int64_t it = 0; it < iters; ++it) {
     const int64_t g = xcd_block() * kBlock + threadIdx.x + it * stride;
     bool active = g < n;
@@ -893,6 +913,9 @@ __global__ __launch_bounds__(kBlock) void k_accum(
     // moves through the 21 exchange stages; each lane then fetches the sums
     // of the element it ended up with, a segmented scan adds equal loops, and
     // the last lane of each run issues one set of atomics per distinct loop.
+    // Very large loops (high spin, low temperature) meet nearly every wave:
+    // the wave carries the sums of one such loop across its steps instead of
+    // adding them to the same record from every wave and step.
     const int lane = lane_id();
     uint64_t sk = active ? ((static_cast<uint64_t>(r) << 6) | static_cast<uint64_t>(lane)) : ~0ull;
 #pragma unroll
@@ -927,14 +950,38 @@ __global__ __launch_bounds__(kBlock) void k_accum(
       }
     }
     const bool last = lane == 63 || ((heads >> (lane + 1)) & 1ull);
-    if (key != INT64_MAX && last) {
+    const bool seg_end = key != INT64_MAX && last;
+    const uint64_t v0 = static_cast<uint64_t>(c0 & 0xFFFFu) + (static_cast<uint64_t>(c0 >> 16) << 40);
+    // the carried loop absorbs its segment without atomics
+    bool absorbed = seg_end && key == ck;
+    unsigned long long m = __ballot(absorbed);
+    if (!m) {
+      // the carried loop is absent: a segment of at least 16 nodes takes over
+      // the carry (the old carry is flushed); the largest such segment wins
+      const uint32_t cnt = seg_end ? (c0 & 0xFFFFu) : 0u;
+      const uint32_t best = wave_max_u32((cnt << 6) | static_cast<uint32_t>(lane));
+      if ((best >> 6) >= 16) {
+        if (ck >= 0 && lane == 0) flush_carry(acc, ck, cv0, cv1, cv2);
+        ck = __shfl(key, static_cast<int>(best & 63u));
+        cv0 = cv1 = cv2 = 0;
+        absorbed = lane == static_cast<int>(best & 63u);
+        m = __ballot(absorbed);
+      }
+    }
+    if (m) {
+      const int src = __ffsll(static_cast<long long>(m)) - 1;
+      cv0 += __shfl(v0, src);
+      cv1 += __shfl(w1, src);
+      cv2 += __shfl(w2, src);
+    }
+    if (seg_end && !absorbed) {
       unsigned long long* a = acc + kAccWords * key;
-      const uint64_t v0 = static_cast<uint64_t>(c0 & 0xFFFFu) + (static_cast<uint64_t>(c0 >> 16) << 40);
       atomicAdd(a + 0, static_cast<unsigned long long>(v0));
       if (w1) atomicAdd(a + 1, static_cast<unsigned long long>(w1));
       if (w2) atomicAdd(a + 2, static_cast<unsigned long long>(w2));
     }
   }
+  if (ck >= 0 && lane_id() == 0) flush_carry(acc, ck, cv0, cv1, cv2);
 }
 
 // First loop index of each chain: a chain's node 0 is always a root (the
