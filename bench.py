@@ -57,9 +57,10 @@ def phase_bytes(n_ops, n_nodes, n_clusters, n_win, n_sites, kept_in, kept_out):
         "link_ops": 8 * W + 8 * N + 16 * V,
         "link_sites": 24 * S,
         "compress": 16 * V,
-        # roots: count roots per chunk (8V), assign loop index, clear the
-        # three record words (8V + 8C + 24C)
-        "roots": 16 * V + 32 * Cl,
+        # roots: read parent words to find the roots (8V), assign loop
+        # indices, clear the three record words (8C + 24C); the counts per
+        # chunk are taken inside compression
+        "roots": 8 * V + 32 * Cl,
         # accum: parent word per node, time per operator, bottom spins;
         # read-modify-write of 3 words per loop record
         "accum": 8 * V + 8 * N + S + 48 * Cl,
@@ -75,7 +76,7 @@ def phase_bytes(n_ops, n_nodes, n_clusters, n_win, n_sites, kept_in, kept_out):
 
 PHASE_KERNELS = {
     "gen_count": ["k_gen<false>"], "gen_write": ["k_gen<true>"], "init_parent": ["k_init_parent"],
-    "link_ops": ["k_link_ops"], "compress": ["k_compress"], "roots": ["k_root_count", "k_roots"],
+    "link_ops": ["k_link_ops"], "compress": ["k_compress"], "roots": ["k_roots", "k_loop_bases"],
     "accum": ["k_accum"], "cluster_sums": ["k_cluster_sums"], "flip": ["k_flip_ops", "k_flip_sites"],
     "compact": ["k_compact"],
 }
