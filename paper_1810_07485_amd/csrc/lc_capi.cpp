@@ -384,26 +384,28 @@ int64_t ops_estimate(const lc_chain* c) {
 
 // Arena capacity for ops operators, nodes loop-graph nodes, roots loops.
 int ensure_scratch(Arena& A, int64_t ops, int64_t nodes, int64_t roots) {
-  // a buffer that has to grow gets 1/16 headroom, so slowly rising demand
-  // (a chain still equilibrating) does not reallocate on every call
+  // A buffer that has to grow takes the need plus 1/16, and at least a
+  // quarter more than it had: every move invalidates the graphs of all
+  // engines sharing the arena, so slowly rising demand (chains still
+  // equilibrating) must not move it on every call.
+  auto target = [](int64_t need, int64_t cap) { return std::max(need + need / 16, cap + cap / 4); };
   if (A.op_cap < ops) {
-    ops += ops / 16;
+    ops = target(ops, A.op_cap);
     A.op_cap = 0;
     if (!(A.grow(A.optime, ops) && A.grow(A.optype, ops))) return LC_ENOMEM;
     A.op_cap = ops;
   }
   if (A.node_cap < nodes) {
-    nodes += nodes / 16;
+    nodes = target(nodes, A.node_cap);
     A.node_cap = 0;
     if (!(A.grow(A.parent, nodes) && A.grow(A.rcnt, static_cast<size_t>(nodes / 4096 + 2))))
       return LC_ENOMEM;
     A.node_cap = nodes;
   }
   if (A.root_cap < roots) {
-    roots += roots / 16;
+    roots = target(roots, A.root_cap);
     A.root_cap = 0;
-    if (!A.grow(A.acc, kAccWords * static_cast<size_t>(roots)))
-      return LC_ENOMEM;
+    if (!A.grow(A.acc, kAccWords * static_cast<size_t>(roots))) return LC_ENOMEM;
     A.root_cap = roots;
   }
   return LC_OK;
