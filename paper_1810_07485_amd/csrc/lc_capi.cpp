@@ -448,7 +448,7 @@ int layout(Engine& E) {
   bool ok = E.descs.ensure(m, nc) && E.win_bases.ensure(m, nc) && E.site_bases.ensure(m, nc) &&
             E.spin_bases.ensure(m, nc) && E.op_bases.ensure(m, nc) && E.node_bases.ensure(m, nc) &&
             E.dyn.ensure(m, nc) && E.totals.ensure(m, 2) && E.scan_tmp.ensure(m, LC_SCAN_BLOCKS + 1) &&
-            E.stats.ensure(m, nc * lc::ST_WORDS) && E.flags.ensure(m, 2) && E.ring_ctr.ensure(m, 2) &&
+            E.stats.ensure(m, nc * lc::ST_WORDS * (1 + LC_STAT_STRIPES)) && E.flags.ensure(m, 2) && E.ring_ctr.ensure(m, 2) &&
             E.ring.ensure(m, static_cast<size_t>(kRing) * (nc * lc::ST_WORDS + 1)) &&
             E.loop_bases.ensure(m, nc);
   if (!ok) return LC_ENOMEM;

@@ -9,6 +9,7 @@
 
 #define LC_SCAN_BLOCKS 1024
 #define LC_ACC_WORDS 3  // accumulator words per loop record
+#define LC_STAT_STRIPES 256  // striped copies of each statistics word (after the words)
 
 struct LcSweepArgs {
   lc::ChainDesc* descs;       // nchain descriptors
@@ -36,7 +37,7 @@ struct LcSweepArgs {
   int64_t* node_bases;        // nchain
   int64_t* totals;            // 2: operators, nodes over all chains
   int64_t* scan_tmp;          // LC_SCAN_BLOCKS + 1
-  uint64_t* stats;            // nchain * ST_WORDS
+  uint64_t* stats;            // nchain * ST_WORDS, then nchain * ST_WORDS * LC_STAT_STRIPES stripes
   uint32_t* flags;            // overflow / error bits
   unsigned long long* ring;   // ring_cap records of nchain * ST_WORDS + 1 words
   uint32_t* ring_ctr;         // next record slot

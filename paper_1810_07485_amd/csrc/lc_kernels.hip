@@ -44,25 +44,34 @@ __device__ inline int64_t xcd_block() {
 // Block-level flushes of per-thread statistics.  Every thread holds a
 // chain c (-1: none) and a value for one statistics word of that chain; the
 // values are summed over the wave with shuffles and over the block's waves
-// through LDS, and one atomic per block and word reaches the counter when
-// the whole block names one chain (per wave, or per lane, otherwise).  The
-// statistics words are few, so the number of same-address atomics, not
-// their total, is what costs.  Convergent: every thread of the block calls.
+// through LDS, and one atomic per block and word reaches a striped copy of
+// the counter when the whole block names one chain (per wave, or per lane,
+// otherwise).  Blocks that finish together would otherwise queue thousands
+// of atomics on the same few words; with kStripes copies (stripe = block
+// mod kStripes, so one XCD per stripe) they spread, and k_stats_reduce folds
+// the stripes into the statistics at the end of the sweep.  The stripes sit
+// after the nchain * ST_WORDS statistics words.  Convergent: every thread of
+// the block calls.
 constexpr int kWaves = kBlock / 64;
+constexpr int kStripes = LC_STAT_STRIPES;
 
 enum FlushOp { FLUSH_ADD, FLUSH_MAX };
 
+__device__ inline unsigned long long* stripe_word(unsigned long long* stats, int nchain, int c, int w) {
+  return stats + static_cast<int64_t>(nchain) * ST_WORDS +
+         (static_cast<int64_t>(c) * ST_WORDS + w) * kStripes + (blockIdx.x % kStripes);
+}
+
 // (lo, hi) += (xlo, xhi) as a 128-bit sum; hi < 0: a single 64-bit word;
-// FLUSH_MAX: lo = max(lo, xlo).
-__device__ inline void stat_apply(unsigned long long* stats, int c, int ilo, int ihi, FlushOp op,
-                                  uint64_t xlo, uint64_t xhi) {
-  unsigned long long* st = stats + static_cast<int64_t>(c) * ST_WORDS;
+// FLUSH_MAX: lo = max(lo, xlo).  Into this block's stripe.
+__device__ inline void stat_apply(unsigned long long* stats, int nchain, int c, int ilo, int ihi,
+                                  FlushOp op, uint64_t xlo, uint64_t xhi) {
   if (op == FLUSH_MAX) {
-    if (xlo) atomicMax(st + ilo, static_cast<unsigned long long>(xlo));
+    if (xlo) atomicMax(stripe_word(stats, nchain, c, ilo), static_cast<unsigned long long>(xlo));
   } else if (ihi < 0) {
-    if (xlo) atomicAdd(st + ilo, static_cast<unsigned long long>(xlo));
+    if (xlo) atomicAdd(stripe_word(stats, nchain, c, ilo), static_cast<unsigned long long>(xlo));
   } else if (xlo | xhi) {
-    atomic_add_u128(st + ilo, st + ihi, xlo, xhi);
+    atomic_add_u128(stripe_word(stats, nchain, c, ilo), stripe_word(stats, nchain, c, ihi), xlo, xhi);
   }
 }
 
@@ -77,15 +86,15 @@ __device__ inline void stat_combine(FlushOp op, uint64_t& alo, uint64_t& ahi, ui
   }
 }
 
-__device__ inline void block_flush(unsigned long long* stats, int c, int ilo, int ihi, FlushOp op,
-                                   uint64_t xlo, uint64_t xhi) {
+__device__ inline void block_flush(unsigned long long* stats, int nchain, int c, int ilo, int ihi,
+                                   FlushOp op, uint64_t xlo, uint64_t xhi) {
   __shared__ uint64_t slo[kWaves], shi[kWaves];
   __shared__ int sc[kWaves];
   const int lane = lane_id(), wv = threadIdx.x >> 6;
   const int c0 = __shfl(c, 0);
   const bool uni = __all(c == c0);
   if (!uni) {  // the wave spans chains: per lane
-    if (c >= 0) stat_apply(stats, c, ilo, ihi, op, xlo, xhi);
+    if (c >= 0) stat_apply(stats, nchain, c, ilo, ihi, op, xlo, xhi);
     xlo = xhi = 0;
   }
 #pragma unroll
@@ -105,10 +114,10 @@ __device__ inline void block_flush(unsigned long long* stats, int c, int ilo, in
     if (same) {
       uint64_t tlo = slo[0], thi = shi[0];
       for (int w = 1; w < kWaves; ++w) stat_combine(op, tlo, thi, slo[w], shi[w]);
-      stat_apply(stats, sc[0], ilo, ihi, op, tlo, thi);
+      stat_apply(stats, nchain, sc[0], ilo, ihi, op, tlo, thi);
     } else {
       for (int w = 0; w < kWaves; ++w)
-        if (sc[w] >= 0) stat_apply(stats, sc[w], ilo, ihi, op, slo[w], shi[w]);
+        if (sc[w] >= 0) stat_apply(stats, nchain, sc[w], ilo, ihi, op, slo[w], shi[w]);
     }
   }
   __syncthreads();  // the LDS slots are reused by the next flush
@@ -138,9 +147,9 @@ struct Partial {
     c = cn;
   }
   // convergent: every thread of the block must call it
-  __device__ void flush(unsigned long long* stats, const int (&idx)[N]) {
+  __device__ void flush(unsigned long long* stats, int nchain, const int (&idx)[N]) {
 #pragma unroll
-    for (int i = 0; i < N; ++i) block_flush(stats, c, idx[i], -1, FLUSH_ADD, v[i], 0);
+    for (int i = 0; i < N; ++i) block_flush(stats, nchain, c, idx[i], -1, FLUSH_ADD, v[i], 0);
   }
 };
 
@@ -309,7 +318,7 @@ __global__ __launch_bounds__(kBlock) void k_gen(const ChainDesc* __restrict__ de
     part.v[0] += ncand;
     part.v[1] += nacc;
   }
-  if (!WRITE) part.flush(stats, kIdx);
+  if (!WRITE) part.flush(stats, nchain, kIdx);
 }
 
 // Per-chain operator and node bases after the operator scan.
@@ -471,11 +480,11 @@ struct PairSums {
     l2hi += q.hi + (l2lo < q.lo ? 1u : 0u);
   }
   // convergent: every thread of the block must call it
-  __device__ void flush(unsigned long long* stats) {
-    block_flush(stats, c, ST_CLUSTERS, -1, FLUSH_ADD, n, 0);
-    block_flush(stats, c, ST_SIZE2_LO, ST_SIZE2_HI, FLUSH_ADD, 4 * n, 0);
-    block_flush(stats, c, ST_LEN2_LO, ST_LEN2_HI, FLUSH_ADD, l2lo, l2hi);
-    block_flush(stats, c, ST_MAXSIZE, -1, FLUSH_MAX, n ? 2 : 0, 0);
+  __device__ void flush(unsigned long long* stats, int nchain) {
+    block_flush(stats, nchain, c, ST_CLUSTERS, -1, FLUSH_ADD, n, 0);
+    block_flush(stats, nchain, c, ST_SIZE2_LO, ST_SIZE2_HI, FLUSH_ADD, 4 * n, 0);
+    block_flush(stats, nchain, c, ST_LEN2_LO, ST_LEN2_HI, FLUSH_ADD, l2lo, l2hi);
+    block_flush(stats, nchain, c, ST_MAXSIZE, -1, FLUSH_MAX, n ? 2 : 0, 0);
   }
 };
 
@@ -544,7 +553,7 @@ __global__ __launch_bounds__(kBlock) void k_link_ops(
       }
     }
   }
-  pairs.flush(stats);
+  pairs.flush(stats, nchain);
 }
 
 // Boundary nodes: bottom(x) joins the lower node of the first event on x;
@@ -815,7 +824,7 @@ __global__ __launch_bounds__(kBlock) void k_roots(
     }
     __syncthreads();  // wsum is rewritten for the next chunk
   }
-  part.flush(stats, kIdx);
+  part.flush(stats, nchain, kIdx);
 }
 
 __device__ inline uint32_t wave_max_u32(uint32_t v) {
@@ -1039,9 +1048,9 @@ __global__ __launch_bounds__(kBlock) void k_cluster_sums(
     l2hi += l2.hi + (l2lo < l2.lo ? 1u : 0u);
     mx = sz > mx ? sz : mx;
   }
-  block_flush(stats, cc, ST_SIZE2_LO, ST_SIZE2_HI, FLUSH_ADD, s2lo, s2hi);
-  block_flush(stats, cc, ST_LEN2_LO, ST_LEN2_HI, FLUSH_ADD, l2lo, l2hi);
-  block_flush(stats, cc, ST_MAXSIZE, -1, FLUSH_MAX, mx, 0);
+  block_flush(stats, nchain, cc, ST_SIZE2_LO, ST_SIZE2_HI, FLUSH_ADD, s2lo, s2hi);
+  block_flush(stats, nchain, cc, ST_LEN2_LO, ST_LEN2_HI, FLUSH_ADD, l2lo, l2hi);
+  block_flush(stats, nchain, cc, ST_MAXSIZE, -1, FLUSH_MAX, mx, 0);
 }
 
 // Flip bit of the loop through node g, from its root (the loop's smallest
@@ -1080,7 +1089,7 @@ __global__ __launch_bounds__(kBlock) void k_flip_ops(
     kcnt[i] = static_cast<int64_t>(kept);
     part.v[0] += kept;
   }
-  part.flush(stats, kIdx);
+  part.flush(stats, nchain, kIdx);
 }
 
 // New spins at tau = 0; the boundary estimators of every loop whose root is
@@ -1112,7 +1121,7 @@ __global__ __launch_bounds__(kBlock) void k_flip_sites(
       part.v[2] += static_cast<uint64_t>(n0 * n0);
     }
   }
-  part.flush(stats, kIdx);
+  part.flush(stats, nchain, kIdx);
 }
 
 // The off-diagonal operators become the next sweep's world lines.
@@ -1144,6 +1153,37 @@ __global__ __launch_bounds__(kBlock) void k_compact(const ChainDesc* __restrict_
     if (li == nw - 1) ks[nw] = kflat[i + 1] - kb;
     for (int64_t q = opstart[i]; q < opstart[i + 1]; ++q)
       if (optype[q] & 1) kt[o++] = optime[q];
+  }
+}
+
+// Fold the striped statistics into the counters (one thread per chain and
+// word; a 128-bit pair is summed with carries by the thread of its low word).
+__global__ void k_stats_reduce(unsigned long long* __restrict__ stats, int nchain) {
+  const int64_t nw = static_cast<int64_t>(nchain) * ST_WORDS;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < nw;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int w = static_cast<int>(i % ST_WORDS);
+    const unsigned long long* sp = stats + nw + i * kStripes;
+    if (w == ST_SIZE2_HI || w == ST_LEN2_HI) continue;
+    if (w == ST_MAXSIZE) {
+      unsigned long long m = stats[i];
+      for (int k = 0; k < kStripes; ++k) m = sp[k] > m ? sp[k] : m;
+      stats[i] = m;
+    } else if (w == ST_SIZE2_LO || w == ST_LEN2_LO) {
+      const unsigned long long* sh = sp + kStripes;  // stripes of the high word
+      uint64_t lo = stats[i], hi = stats[i + 1];
+      for (int k = 0; k < kStripes; ++k) {
+        const uint64_t t = lo + sp[k];
+        hi += sh[k] + (t < lo ? 1u : 0u);
+        lo = t;
+      }
+      stats[i] = lo;
+      stats[i + 1] = hi;
+    } else {
+      uint64_t sum = stats[i];
+      for (int k = 0; k < kStripes; ++k) sum += sp[k];
+      stats[i] = sum;
+    }
   }
 }
 
@@ -1279,8 +1319,8 @@ hipError_t lc_launch_sweep(const LcSweepArgs& A, hipStream_t s) {
     if (A.events) (void)hipEventRecord(static_cast<hipEvent_t>(A.events[ph]), s);
   };
   mark(LC_PH_SETUP);
-  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(A.nchain * ST_WORDS, 64)), dim3(kBlock), 0, s, st,
-                     static_cast<int64_t>(A.nchain) * ST_WORDS, 0ull);
+  const int64_t stat_words = static_cast<int64_t>(A.nchain) * ST_WORDS * (1 + kStripes);
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(stat_words, 1024)), dim3(kBlock), 0, s, st, stat_words, 0ull);
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s,
                      reinterpret_cast<unsigned long long*>(A.flags), 1, 0ull);
   // 1. count operators per window, 2. scan
@@ -1350,6 +1390,8 @@ hipError_t lc_launch_sweep(const LcSweepArgs& A, hipStream_t s) {
   hipLaunchKernelGGL(k_compact, dim3(grid_for(A.nwin, G)), dim3(kBlock), 0, s, A.descs,
                      A.win_bases, A.nchain, A.nwin, A.opstart, A.optime, A.optype, A.kflat,
                      A.flags);
+  hipLaunchKernelGGL(k_stats_reduce, dim3(grid_for(static_cast<int64_t>(A.nchain) * ST_WORDS, 64)),
+                     dim3(kBlock), 0, s, st, A.nchain);
   hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, A.descs, A.nchain, A.flags);
   hipLaunchKernelGGL(k_record, dim3(1), dim3(kBlock), 0, s, st,
                      static_cast<int64_t>(A.nchain) * ST_WORDS, A.flags, A.ring, A.ring_ctr,
