@@ -125,8 +125,9 @@ __device__ inline void block_flush(unsigned long long* stats, int nchain, int c,
 
 // Per-thread partial sums of one chain's statistics.  A thread walks its
 // items in increasing flat index, so it meets each chain in one stretch: the
-// sums go to the chain's counters when the thread moves on to another chain
-// (per lane, rare) and once at the end (block_flush).
+// sums go to the chain's counters (striped copies) when the thread moves on
+// to another chain (per lane; frequent in a batch of many small chains) and
+// once at the end (block_flush).
 template <int N>
 struct Partial {
   int c;
@@ -135,12 +136,11 @@ struct Partial {
 #pragma unroll
     for (int i = 0; i < N; ++i) v[i] = 0;
   }
-  __device__ void at(int cn, unsigned long long* stats, const int (&idx)[N]) {
+  __device__ void at(int cn, unsigned long long* stats, int nchain, const int (&idx)[N]) {
     if (cn == c) return;
     if (c >= 0) {
 #pragma unroll
-      for (int i = 0; i < N; ++i)
-        if (v[i]) atomicAdd(stats + static_cast<int64_t>(c) * ST_WORDS + idx[i], v[i]);
+      for (int i = 0; i < N; ++i) stat_apply(stats, nchain, c, idx[i], -1, FLUSH_ADD, v[i], 0);
     }
 #pragma unroll
     for (int i = 0; i < N; ++i) v[i] = 0;
@@ -254,7 +254,7 @@ __global__ __launch_bounds__(kBlock) void k_gen(const ChainDesc* __restrict__ de
     uint32_t ncand = 0, nacc = 0;
     {
       const int c = chain_of(win_bases, nchain, i);
-      if (!WRITE) part.at(c, stats, kIdx);
+      if (!WRITE) part.at(c, stats, nchain, kIdx);
       const ChainDesc& D = descs[c];
       const uint8_t* __restrict__ s0 = D.s0[D.cur];
       const int64_t* __restrict__ kstart = D.kstart[D.cur];
@@ -458,18 +458,17 @@ __device__ inline int64_t earlier(int64_t c1, uint64_t t1, int64_t b1, int64_t c
 struct PairSums {
   int c = -1;
   uint64_t n = 0, l2lo = 0, l2hi = 0;
-  __device__ void flush_lane(unsigned long long* stats) {
+  __device__ void flush_lane(unsigned long long* stats, int nchain) {
     if (c < 0 || n == 0) return;
-    unsigned long long* st = stats + static_cast<int64_t>(c) * ST_WORDS;
-    atomicAdd(st + ST_CLUSTERS, n);
-    atomic_add_u128(st + ST_SIZE2_LO, st + ST_SIZE2_HI, 4 * n, 0);
-    if (l2lo | l2hi) atomic_add_u128(st + ST_LEN2_LO, st + ST_LEN2_HI, l2lo, l2hi);
-    atomicMax(st + ST_MAXSIZE, 2ull);
+    stat_apply(stats, nchain, c, ST_CLUSTERS, -1, FLUSH_ADD, n, 0);
+    stat_apply(stats, nchain, c, ST_SIZE2_LO, ST_SIZE2_HI, FLUSH_ADD, 4 * n, 0);
+    stat_apply(stats, nchain, c, ST_LEN2_LO, ST_LEN2_HI, FLUSH_ADD, l2lo, l2hi);
+    stat_apply(stats, nchain, c, ST_MAXSIZE, -1, FLUSH_MAX, 2, 0);
     n = l2lo = l2hi = 0;
   }
-  __device__ void at(int cn, unsigned long long* stats) {
+  __device__ void at(int cn, unsigned long long* stats, int nchain) {
     if (cn == c) return;
-    flush_lane(stats);
+    flush_lane(stats, nchain);
     c = cn;
   }
   __device__ void add(uint64_t dt) {
@@ -532,7 +531,7 @@ __global__ __launch_bounds__(kBlock) void k_link_ops(
         if (own >= 0 && nx == own && ny == own) {  // closed two-node loop
           parent[up] = kPairRoot;
           parent[up + 1] = up;
-          pairs.at(c, stats);
+          pairs.at(c, stats, nchain);
           pairs.add(tn - t);
           continue;
         }
@@ -809,7 +808,7 @@ __global__ __launch_bounds__(kBlock) void k_roots(
       if (pv[s] == g) {
         const int64_t i = idx + woff + __popcll(m[s] & below);
         const int c = chain_of(node_bases, nchain, g);
-        part.at(c, stats, kIdx);
+        part.at(c, stats, nchain, kIdx);
         part.v[0] += 1;
         const ChainDesc& D = descs[c];
         const int64_t v = g - node_bases[c];
@@ -1014,11 +1013,10 @@ __global__ __launch_bounds__(kBlock) void k_cluster_sums(
   int cc = -1;
   int64_t cend = 0;  // first loop index past chain cc
   uint64_t s2lo = 0, s2hi = 0, l2lo = 0, l2hi = 0, mx = 0;
-  auto flush_lane = [&]() {
-    unsigned long long* st = stats + static_cast<int64_t>(cc) * ST_WORDS;
-    if (s2lo | s2hi) atomic_add_u128(st + ST_SIZE2_LO, st + ST_SIZE2_HI, s2lo, s2hi);
-    if (l2lo | l2hi) atomic_add_u128(st + ST_LEN2_LO, st + ST_LEN2_HI, l2lo, l2hi);
-    if (mx) atomicMax(st + ST_MAXSIZE, mx);
+  auto flush_lane = [&]() {  // into this block's stripes
+    stat_apply(stats, nchain, cc, ST_SIZE2_LO, ST_SIZE2_HI, FLUSH_ADD, s2lo, s2hi);
+    stat_apply(stats, nchain, cc, ST_LEN2_LO, ST_LEN2_HI, FLUSH_ADD, l2lo, l2hi);
+    stat_apply(stats, nchain, cc, ST_MAXSIZE, -1, FLUSH_MAX, mx, 0);
     s2lo = s2hi = l2lo = l2hi = mx = 0;
   };
   for (int64_t i = xcd_block() * kBlock + threadIdx.x; i < n;
@@ -1074,7 +1072,7 @@ __global__ __launch_bounds__(kBlock) void k_flip_ops(
   for (int64_t i = xcd_block() * kBlock + threadIdx.x; i < nwin;
        i += static_cast<int64_t>(gridDim.x) * kBlock) {
     const int c = chain_of(win_bases, nchain, i);
-    part.at(c, stats, kIdx);
+    part.at(c, stats, nchain, kIdx);
     const ChainDesc& D = descs[c];
     const ChainDyn dy = dyn[c];
     uint64_t kept = 0;
@@ -1106,7 +1104,7 @@ __global__ __launch_bounds__(kBlock) void k_flip_sites(
   for (int64_t gi = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; gi < nsites;
        gi += static_cast<int64_t>(gridDim.x) * kBlock) {
     const int c = chain_of(site_bases, nchain, gi);
-    part.at(c, stats, kIdx);
+    part.at(c, stats, nchain, kIdx);
     const ChainDesc& D = descs[c];
     const int64_t x = gi - D.site_base;
     const int64_t p = parent[dyn[c].node_base + x];
