@@ -970,6 +970,7 @@ int lc_export_state(const lc_chain* c, uint8_t* s0, int64_t* bond_off, uint64_t*
   const int64_t have = *n_kept;
   *n_kept = c->n_kept;
   if (sweep) *sweep = c->sweep;
+  if (times && have < c->n_kept) return LC_ECAPACITY;  // before any copy starts
   hipStream_t s = c->stream;
   if (s0 && hipMemcpyAsync(s0, c->s0[c->cur].p, c->n_sites, hipMemcpyDeviceToHost, s) != hipSuccess)
     return LC_EDEVICE;
@@ -982,7 +983,6 @@ int lc_export_state(const lc_chain* c, uint8_t* s0, int64_t* bond_off, uint64_t*
     for (int64_t b = 0; b <= c->n_bonds; ++b) bond_off[b] = ks[b << c->w];
   }
   if (times) {
-    if (have < c->n_kept) return LC_ECAPACITY;
     if (c->n_kept && hipMemcpyAsync(times, c->ktime[c->cur].p, c->n_kept * sizeof(uint64_t),
                                     hipMemcpyDeviceToHost, s) != hipSuccess)
       return LC_EDEVICE;
@@ -994,15 +994,15 @@ int lc_import_state(lc_chain* c, const uint8_t* s0, const int64_t* bond_off, con
                     int64_t sweep) {
   if (!c || !s0 || !bond_off || sweep < 0 || sweep > 0xFFFFFFFFll) return LC_EINVAL;
   if (bond_off[0] != 0) return LC_EINVAL;
-  for (int64_t b = 0; b < c->n_bonds; ++b) {
+  for (int64_t b = 0; b < c->n_bonds; ++b)
     if (bond_off[b + 1] < bond_off[b]) return LC_EINVAL;
-    for (int64_t i = bond_off[b] + 1; i < bond_off[b + 1]; ++i)
-      if (times[i] < times[i - 1]) return LC_EINVAL;
-  }
-  for (int64_t x = 0; x < c->n_sites; ++x)
-    if (s0[x] > 1) return LC_EINVAL;
   const int64_t n = bond_off[c->n_bonds];
   if (n > 0 && !times) return LC_EINVAL;
+  for (int64_t b = 0; b < c->n_bonds; ++b)
+    for (int64_t i = bond_off[b] + 1; i < bond_off[b + 1]; ++i)
+      if (times[i] < times[i - 1]) return LC_EINVAL;
+  for (int64_t x = 0; x < c->n_sites; ++x)
+    if (s0[x] > 1) return LC_EINVAL;
   int rc;
   if (n > c->kept_cap && (rc = grow_kept(c, n)) != LC_OK) return rc;
   // kept operators per window, exclusive scan
