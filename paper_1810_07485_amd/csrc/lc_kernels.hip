@@ -179,38 +179,41 @@ __device__ inline bool precedes(uint64_t t1, int64_t b1, uint64_t t2, int64_t b2
   return t1 < t2 || (t1 == t2 && b1 < b2);
 }
 
-// Parity of the kept off-diagonal operators of bond bb that precede (t, b).
-__device__ inline uint32_t kept_parity_before(const int64_t* __restrict__ kstart,
-                                              const uint64_t* __restrict__ ktime, int w,
-                                              int64_t bb, uint64_t k, uint64_t t, int64_t b) {
-  const int64_t i0 = bb << w;
-  const int64_t s = kstart[i0 + static_cast<int64_t>(k)], e = kstart[i0 + static_cast<int64_t>(k) + 1];
-  int64_t n = s - kstart[i0];
-  for (int64_t q = s; q < e; ++q) {
-    if (!precedes(ktime[q], bb, t, b)) break;
-    ++n;
-  }
-  return static_cast<uint32_t>(n & 1);
-}
-
-// Spins of the two ends of bond b just before (t, b) differ?  Kept operators
-// on b itself flip both ends and cancel; the rest come from the other bonds
-// touching either end (labeling rules ii/iii: horizontal graph only when
-// antiparallel).
-__device__ inline bool antiparallel_before(const ChainDesc& D, const uint8_t* __restrict__ s0,
-                                           const int64_t* __restrict__ kstart,
-                                           const uint64_t* __restrict__ ktime, int64_t b,
-                                           uint64_t k, uint64_t t) {
-  const int64_t x = bond_x(D, b), y = bond_y(D, b);
-  uint32_t p = static_cast<uint32_t>(s0[x] ^ s0[y]);
+// Are the spins of the two ends of bond b antiparallel just before (tc[j], b)?
+// (labeling rules ii/iii: a horizontal graph only between antiparallel
+// spins.)  The spins at 0+ are flipped by every kept off-diagonal operator
+// that precedes (tc[j], b) in (time, bond) order on the other bonds touching
+// either end; kept operators on b itself flip both ends and cancel.  Answered
+// for m <= kChunk candidate times of one window (b, k) at once, as a bit
+// mask: each neighbouring bond's window bounds and kept times are read once
+// for all of them.
+constexpr int kChunk = 8;
+__device__ inline uint32_t antiparallel_mask(const ChainDesc& D, const uint8_t* __restrict__ s0,
+                                             const int64_t* __restrict__ kstart,
+                                             const uint64_t* __restrict__ ktime, int64_t b,
+                                             uint64_t k, const uint64_t (&tc)[kChunk], int m) {
+  const int64_t ends[2] = {bond_x(D, b), bond_y(D, b)};
+  uint32_t base = static_cast<uint32_t>(s0[ends[0]] ^ s0[ends[1]]);
+  uint32_t flips = 0;  // bit j: parity of in-window kept operators before tc[j]
   const int nt = 2 * D.two_s;
-  for (int q = 0; q < nt; ++q) {
-    const int64_t bx = bond_touching(D, x, q);
-    if (bx != b) p ^= kept_parity_before(kstart, ktime, D.w, bx, k, t, b);
-    const int64_t by = bond_touching(D, y, q);
-    if (by != b) p ^= kept_parity_before(kstart, ktime, D.w, by, k, t, b);
+  for (int e = 0; e < 2; ++e) {
+    for (int s = 0; s < nt; ++s) {
+      const int64_t bb = bond_touching(D, ends[e], s);
+      if (bb == b) continue;
+      const int64_t i0 = bb << D.w;
+      const int64_t ws = kstart[i0 + static_cast<int64_t>(k)];
+      const int64_t we = kstart[i0 + static_cast<int64_t>(k) + 1];
+      base ^= static_cast<uint32_t>((ws - kstart[i0]) & 1);
+      for (int64_t p = ws; p < we; ++p) {
+        const uint64_t tp = ktime[p];
+#pragma unroll
+        for (int j = 0; j < kChunk; ++j)
+          if (j < m && precedes(tp, bb, tc[j], b)) flips ^= 1u << j;
+      }
+    }
   }
-  return p & 1u;
+  const uint32_t live = (m >= 32) ? ~0u : ((1u << m) - 1u);
+  return ((base & 1u) ? ~flips : flips) & live;
 }
 
 // Candidate j of window (b, k): the j-th uniform 64-bit draw placed in the
@@ -271,10 +274,18 @@ __global__ __launch_bounds__(kBlock) void k_gen(const ChainDesc* __restrict__ de
       const bool inlds = WRITE && n <= kCap;
       const bool known = WRITE && n <= 32;
       uint64_t accm = known ? accmask[i] : 0;
-      for (int j = 0; j < n; ++j) {
-        const uint64_t t = cand_time(D, b, k, j, v0);
-        if (inlds) slot[j * kBlock + tid] = t;
-        if (!known && antiparallel_before(D, s0, kstart, ktime, b, k, t)) accm |= (uint64_t(1) << j);
+      if (known) {
+        if (inlds)
+          for (int j = 0; j < n; ++j) slot[j * kBlock + tid] = cand_time(D, b, k, j, v0);
+      } else {
+        // n > kCap here whenever WRITE, so no candidate goes to LDS
+        for (int j0 = 0; j0 < n; j0 += kChunk) {
+          const int m = (n - j0 < kChunk) ? n - j0 : kChunk;
+          uint64_t tc[kChunk];
+#pragma unroll
+          for (int j = 0; j < kChunk; ++j) tc[j] = (j < m) ? cand_time(D, b, k, j0 + j, v0) : 0;
+          accm |= static_cast<uint64_t>(antiparallel_mask(D, s0, kstart, ktime, b, k, tc, m)) << j0;
+        }
       }
       nacc = static_cast<uint32_t>(__popcll(accm));
       const int64_t kb = kstart[li], ke = kstart[li + 1];
