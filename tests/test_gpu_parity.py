@@ -73,6 +73,8 @@ def test_parity_spin_half(lc, orc, L, S, beta, seed, sweeps):
     (6, 1.5, 3.0, 9, 6),
     (4, 4.0, 1.0, 10, 6),
     (6, 4.0, 9.0, 11, 3),
+    (16, 1.0, 31.5, 12, 4),      # mean 3.9 candidates per window: some windows exceed 8
+    (12, 2.0, 15.5, 13, 3),
 ])
 def test_parity_split_spin(lc, orc, L, S, beta, seed, sweeps):
     lockstep(lc, orc, L, S, beta, seed, sweeps)
