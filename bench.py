@@ -295,8 +295,8 @@ def main():
     if args.warmup is None:
         args.warmup = dflt[1]
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the chain is not "
-              "sharded across GPUs in this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the library runs "
+              "each chain on a single GPU and has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import torch
