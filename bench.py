@@ -8,7 +8,9 @@ one full sweep of the hot path (insertion, operator merge, linking,
 union-find, flip, estimators, next world lines) on device-resident state.
 
 --workload largest runs the largest single-GPU chain instead (L=262,144,
-beta=16,384, about 3e9 operators per sweep).  --workload batch runs 512
+beta=16,384, about 3e9 operators per sweep).  --workload split runs an S=4
+chain (8 subspins per site, L=4,096, beta=2,048, about 2.8e8 operators per
+sweep; no roofline or oracle entries).  --workload batch runs 512
 independent chains (L log-uniform in [64, 16,384], beta uniform in [L/4, L]):
 one step is one sweep of every chain, timed as 512 sequential plain updates
 and as footprint-packed, autotuned batches.  --workload serve runs the
@@ -38,6 +40,8 @@ WORKLOADS = {
                    L=65536, S=0.5, beta=4096.0, seed=1),
     "largest": dict(workload="S=1/2 Heisenberg chain L=262144 beta=16384 seed 1, single chain",
                     L=262144, S=0.5, beta=16384.0, seed=1),
+    "split": dict(workload="S=4 Heisenberg chain (8 subspins per site) L=4096 beta=2048 seed 1, "
+                           "single chain", L=4096, S=4.0, beta=2048.0, seed=1),
 }
 HBM_PEAK_GBS = 8000.0
 
@@ -276,20 +280,21 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed steps (default 20; largest 5; batch 3)")
+                    help="timed steps (default 20; largest and split 5; batch 3)")
     ap.add_argument("--warmup", type=int, default=None,
-                    help="untimed steps first (default 10; largest 4; batch 2)")
+                    help="untimed steps first (default 10; largest and split 4; batch 2)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["batch", "serve"], default="medium",
                     help="medium: L=65536 beta=4096 (default); largest: L=262144 beta=16384; "
-                         "batch: 512 chains; serve: request loop")
+                         "split: S=4 L=4096 beta=2048; batch: 512 chains; serve: request loop")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 2 GiB device to device three times (reference kernel for "
                          "the HBM byte counters) and exit")
     ap.add_argument("--serve-jobs", type=int, default=24)
     ap.add_argument("--serve-sweep-scale", type=float, default=0.1)
     args = ap.parse_args()
-    dflt = {"medium": (20, 10), "largest": (5, 4), "batch": (3, 2), "serve": (0, 0)}[args.workload]
+    dflt = {"medium": (20, 10), "largest": (5, 4), "split": (5, 4), "batch": (3, 2),
+            "serve": (0, 0)}[args.workload]
     if args.steps is None:
         args.steps = dflt[0]
     if args.warmup is None:
@@ -333,10 +338,11 @@ def main():
     assert m["n_sweeps"] == args.steps == nsw
     ops_total = m["mean_ops"] * args.steps
     n_sites = chain.n_sites
-    frag_total = (2 * m["mean_ops"] + n_sites) * args.steps
+    nbn = n_sites if w["S"] == 0.5 else 2 * n_sites  # boundary nodes
+    frag_total = (2 * m["mean_ops"] + nbn) * args.steps
     wtab = lc.lc_debug_window_table(w["beta"])
     n_win = chain.n_bonds << wtab[0]
-    pb = phase_bytes(m["mean_ops"], 2 * m["mean_ops"] + n_sites, m["mean_clusters"], n_win,
+    pb = phase_bytes(m["mean_ops"], 2 * m["mean_ops"] + nbn, m["mean_clusters"], n_win,
                      n_sites, last["n_kept_in"], last["n_kept_out"])
     phase_ms = {k: v / nsw for k, v in prof.items()}
     dom = max(phase_ms, key=phase_ms.get)
@@ -369,7 +375,10 @@ def main():
                         "loops_per_L_beta": m["mean_clusters"] / (w["L"] * w["beta"])},
     }
     chain.close()
-    if not args.no_cpu_baseline:
+    if w["S"] != 0.5:
+        # the per-phase byte model and the oracle sample are those of S = 1/2 chains
+        out["roofline"] = None
+    elif not args.no_cpu_baseline:
         Ls = max(1024, int(2 ** 24 / w["beta"]) // 2 * 2)
         out["cpu_baseline"] = cpu_baseline(lc, Ls, w["beta"])
     print(json.dumps(out), flush=True)
