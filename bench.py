@@ -1,14 +1,17 @@
 #!/usr/bin/env python3
 """Throughput of the loop-cluster update on one MI355X.
 
-Workload: the medium single chain -- S=1/2 antiferromagnetic Heisenberg
-chain, J=1, L=65,536 spins, periodic, beta=4,096, Philox seed 1, random
-initial Neel world lines (about 1.86e8 operators per sweep).  One step is
-one full sweep of the hot path (insertion, operator merge, linking,
-union-find, flip, estimators, next world lines) on device-resident state.
+Workload: the largest single chain that fits one GPU -- S=1/2
+antiferromagnetic Heisenberg chain, J=1, L=262,144 spins, periodic,
+beta=16,384, Philox seed 1, random initial Neel world lines (about 3e9
+operators per sweep).  One step is one full sweep of the hot path
+(insertion, operator merge, linking, union-find, flip, estimators, next
+world lines) on device-resident state, launched as the library runs it
+(one captured HIP graph per sweep).  The per-phase times come from a
+separate pass of direct launches with HIP events between the phases.
 
---workload largest runs the largest single-GPU chain instead (L=262,144,
-beta=16,384, about 3e9 operators per sweep).  --workload split runs an S=4
+--workload medium runs the medium chain instead (L=65,536, beta=4,096,
+about 1.86e8 operators per sweep).  --workload split runs an S=4
 chain (8 subspins per site, L=4,096, beta=2,048, about 2.8e8 operators per
 sweep; no roofline or oracle entries).  --workload batch runs 512
 independent chains (L log-uniform in [64, 16,384], beta uniform in [L/4, L]):
@@ -19,9 +22,10 @@ request loop on a Poisson stream of jobs (S in {1/2, 4}, L in {1024, 4096,
 continuous batching, and reports p50/p99 per-sweep latency and throughput.
 
 Prints one JSON line: operators ("graph vertices") per second over exactly
---steps sweeps after --warmup untimed sweeps, with the per-phase HIP-event
-timing of those same sweeps, the roofline entry of the dominant kernel and
-the CPU oracle's rate on a bounded sample.
+--steps sweeps after --warmup untimed sweeps, the per-phase HIP-event timing
+of a separate profiled pass, the roofline entry of the dominant kernel, the
+measured random-CAS and copy ceilings of the device, and the CPU oracle's
+rate on a bounded sample.  --calibrate-atomics prints only the ceilings.
 """
 from __future__ import annotations
 
@@ -46,6 +50,38 @@ WORKLOADS = {
 HBM_PEAK_GBS = 8000.0
 
 
+def host_cpu():
+    """(model name, logical cores available to this process) of the host."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count()
+    return model, n
+
+
+def device_ceilings(lc):
+    """Measured ceilings: random 8-byte CAS on a 32 GiB word array (larger than
+    every cache, like the union-find parent words of the largest chain) and on
+    a 1 MiB one (L2-resident), and a streaming 4 GiB copy."""
+    hbm, f1 = lc.lc_probe_cas(32, 1 << 27, 3)
+    l2, f2 = lc.lc_probe_cas(17, 1 << 27, 3)
+    copy = lc.lc_probe_copy(4 << 30, 3)
+    assert f1 == 1.0 and f2 == 1.0
+    return {"cas_per_s_hbm": hbm, "cas_per_s_l2": l2, "copy_gbs": copy,
+            "how": "lc_probe_cas: random 8-byte CAS, 2^27 per launch, on 2^32 words (32 GiB) "
+                   "and on 2^17 words (1 MiB), best of 3; lc_probe_copy: 4 GiB device copy, "
+                   "read + written bytes per second, best of 3"}
+
+
 def phase_bytes(n_ops, n_nodes, n_clusters, n_win, n_sites, kept_in, kept_out):
     """Algorithmic HBM bytes of each phase for one sweep (compulsory traffic:
     every array element the phase must read or write, counted once).
@@ -58,7 +94,10 @@ def phase_bytes(n_ops, n_nodes, n_clusters, n_win, n_sites, kept_in, kept_out):
         "scan_ops": 24 * W,
         "gen_write": 8 * kept_in + 8 * W + 8 * W + 9 * N,
         "init_parent": 8 * V,
-        "link_ops": 8 * W + 8 * N + 16 * V,
+        # per-site time order read once, fused into linking (8 B per
+        # operator), and two edges per operator, each two finds and one
+        # CAS on 8-byte parent words (48 B per operator)
+        "link_ops": 56 * N,
         "link_sites": 24 * S,
         "compress": 16 * V,
         # roots: read parent words to find the roots (8V), assign loop
@@ -84,17 +123,19 @@ PHASE_KERNELS = {
     "accum": ["k_accum"], "cluster_sums": ["k_cluster_sums"], "flip": ["k_flip_ops", "k_flip_sites"],
     "compact": ["k_compact"],
 }
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_L65536_beta4096.txt")
+TRAFFIC_FILES = {"medium": os.path.join(ROOT, "profiles", "hbm_traffic_L65536_beta4096.txt"),
+                 "largest": os.path.join(ROOT, "profiles", "hbm_traffic_L262144_beta16384.txt")}
 
 
-def measured_traffic(phase):
+def measured_traffic(phase, workload):
     """HBM bytes per launch of a phase's kernels from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary of the medium workload (copy-calibrated),
-    or None when the kernel source has changed since the counters were taken."""
+    FETCH_SIZE / WRITE_SIZE summary of the workload (copy-calibrated), or None
+    when there is none or the kernel source has changed since the counters
+    were taken."""
     import hashlib
     try:
-        lines = open(TRAFFIC_FILE).read().splitlines()
-    except OSError:
+        lines = open(TRAFFIC_FILES[workload]).read().splitlines()
+    except (OSError, KeyError):
         return None
     src = os.path.join(ROOT, "paper_1810_07485_amd", "csrc", "lc_kernels.hip")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
@@ -111,28 +152,27 @@ def measured_traffic(phase):
     return sum(rec[k] for k in ks)
 
 
-def cpu_baseline(lc, L, beta, seed=1, gpu_therm=30, budget_s=12.0):
-    """The oracle's rate on a bounded sample: a chain with the workload's
-    beta and fewer spins (L beta = 2^24), thermalised on the GPU, imported
-    into the oracle, then timed for whole oracle sweeps (>= 1, up to about
-    budget_s seconds).  Single-threaded C."""
+def cpu_baseline(L, beta, seed=1, budget_s=12.0):
+    """The oracle's rate on a bounded sample: its own chain with the
+    workload's beta and fewer spins (L beta = 2^24), one untimed sweep from
+    the Neel state, then whole timed sweeps (>= 1, up to about budget_s
+    seconds).  Single-threaded C."""
     from oracle import oracle
 
-    g = lc.Chain(L, 0.5, beta, seed)
-    g.update(gpu_therm, accumulate=False)
-    st = g.export_state()
     o = oracle.Chain(L, 0.5, beta, seed)
-    o.import_state(*st)
+    o.sweep()
     ops, t0 = 0, time.perf_counter()
     while True:
         ops += o.sweep()["n_ops"]
         el = time.perf_counter() - t0
         if el >= budget_s:
             break
-    g.close()
+    model, ncpu = host_cpu()
     return {"value": ops / el, "unit": "vertices/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle sweeps of a thermalised S=1/2 chain L={L} beta={beta:g} "
-                      f"(same beta, fewer spins): {ops} operators in {el:.1f} s"}
+            "cpu_model": model, "host_cores": ncpu,
+            "sample": f"oracle sweeps 1.. of an S=1/2 chain L={L} beta={beta:g} from its Neel "
+                      f"start (same beta, fewer spins): {ops} operators in {el:.1f} s, "
+                      f"single-threaded C on one core of {ncpu} ({model})"}
 
 
 def _ops_since_reset(chains):
@@ -220,7 +260,7 @@ def bench_batch(args, lc):
         c.close()
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(lc, 4096, 4096.0)
+        out["cpu_baseline"] = cpu_baseline(4096, 4096.0)
     print(json.dumps(out), flush=True)
 
 
@@ -284,17 +324,25 @@ def main():
     ap.add_argument("--warmup", type=int, default=None,
                     help="untimed steps first (default 10; largest and split 4; batch 2)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["batch", "serve"], default="medium",
-                    help="medium: L=65536 beta=4096 (default); largest: L=262144 beta=16384; "
+    ap.add_argument("--no-ceilings", action="store_true",
+                    help="skip the random-CAS and copy probes")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["batch", "serve"], default="largest",
+                    help="largest: L=262144 beta=16384 (default); medium: L=65536 beta=4096; "
                          "split: S=4 L=4096 beta=2048; batch: 512 chains; serve: request loop")
+    ap.add_argument("--calibrate-atomics", action="store_true",
+                    help="only measure the random-CAS and copy ceilings and exit")
+    ap.add_argument("--profile-sweeps", type=int, default=None,
+                    help="sweeps of the separate per-phase timing pass (default 2, medium 10)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 2 GiB device to device three times (reference kernel for "
                          "the HBM byte counters) and exit")
     ap.add_argument("--serve-jobs", type=int, default=24)
     ap.add_argument("--serve-sweep-scale", type=float, default=0.1)
     args = ap.parse_args()
-    dflt = {"medium": (20, 10), "largest": (5, 4), "split": (5, 4), "batch": (3, 2),
+    dflt = {"medium": (20, 10), "largest": (10, 4), "split": (5, 4), "batch": (3, 2),
             "serve": (0, 0)}[args.workload]
+    if args.profile_sweeps is None:
+        args.profile_sweeps = 10 if args.workload == "medium" else 2
     if args.steps is None:
         args.steps = dflt[0]
     if args.warmup is None:
@@ -316,6 +364,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_per_launch": x.numel() * 8, "launches": 3}), flush=True)
         return
+    if args.calibrate_atomics:
+        print(json.dumps(device_ceilings(lc)), flush=True)
+        return
     if args.workload == "batch":
         bench_batch(args, lc)
         return
@@ -326,16 +377,19 @@ def main():
     chain = lc.Chain(w["L"], w["S"], w["beta"], w["seed"])
     chain.update(args.warmup, accumulate=False)
     chain.reset_measurements()
-    chain.set_profiling(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    chain.update(args.steps, accumulate=True)
+    chain.update(args.steps, accumulate=True)   # graph replay, as the library runs
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     m = chain.measure()
-    prof, nsw = chain.profile()
     last = chain.last_sweep()
-    assert m["n_sweeps"] == args.steps == nsw
+    assert m["n_sweeps"] == args.steps
+    # separate pass: direct launches with HIP events between the phases
+    chain.set_profiling(True)
+    chain.update(args.profile_sweeps, accumulate=False)
+    prof, nsw = chain.profile()
+    chain.set_profiling(False)
     ops_total = m["mean_ops"] * args.steps
     n_sites = chain.n_sites
     nbn = n_sites if w["S"] == 0.5 else 2 * n_sites  # boundary nodes
@@ -348,7 +402,7 @@ def main():
     dom = max(phase_ms, key=phase_ms.get)
     achieved = pb[dom] / (phase_ms[dom] * 1e-3) / 1e9
     total_bytes = sum(pb.values())
-    traffic = measured_traffic(dom) if args.workload == "medium" else None
+    traffic = measured_traffic(dom, args.workload)
     out = {
         "metric": METRIC,
         "value": ops_total / el,
@@ -369,18 +423,24 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_gbs": (traffic / (phase_ms[dom] * 1e-3) / 1e9) if traffic else None,
-                     "bytes_per_launch": pb[dom], "avg_ms": phase_ms[dom]},
+                     "bytes_per_launch": pb[dom], "avg_ms": phase_ms[dom],
+                     "timing": f"HIP events around each phase on the library stream, "
+                               f"{nsw} directly launched sweeps after the timed region"},
         "phase_ms": phase_ms,
+        "profiled_ms_per_sweep": sum(phase_ms.values()),
         "observables": {"e": m["e"], "ops_per_L_beta": m["mean_ops"] / (w["L"] * w["beta"]),
                         "loops_per_L_beta": m["mean_clusters"] / (w["L"] * w["beta"])},
     }
     chain.close()
+    torch.cuda.empty_cache()
+    if not args.no_ceilings:
+        out["ceilings"] = device_ceilings(lc)
     if w["S"] != 0.5:
         # the per-phase byte model and the oracle sample are those of S = 1/2 chains
         out["roofline"] = None
     elif not args.no_cpu_baseline:
         Ls = max(1024, int(2 ** 24 / w["beta"]) // 2 * 2)
-        out["cpu_baseline"] = cpu_baseline(lc, Ls, w["beta"])
+        out["cpu_baseline"] = cpu_baseline(Ls, w["beta"])
     print(json.dumps(out), flush=True)
 
 

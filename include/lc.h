@@ -17,7 +17,9 @@
  *    transactional (the world lines are double-buffered and only the last
  *    kernel of a successful sweep makes the new buffer current).
  *  - Spin S is passed as a double: 0.5, 1.0, 1.5, ... 4.0 (2S integer in 1..8).
- *    L must be even and >= 4; beta must be finite, > 0 and <= 8 * 2^32.
+ *    L must be even and >= 4, and the sub-bond count (2S)^2 L below 2^32
+ *    (bond indices are 32-bit Philox counter words); beta must be finite,
+ *    > 0 and <= 8 * 2^32.
  *  - Imaginary time is a 64-bit fixed-point fraction of beta:
  *    tau = beta * t / 2^64.
  *  - Subspin (j, a) of spin j has index 2S j + a; sub-bond
@@ -116,8 +118,15 @@ int lc_footprint_parts(int64_t L, double S, double beta, size_t *state, size_t *
 
 /* init_lattice: a chain of L spins S at inverse temperature beta with Philox
  * key `seed`, in the Neel state with a random phase and no operators.
- * alloc may be NULL (hipMalloc); hip_stream may be NULL.  *out receives the
- * handle, owned by the caller until lc_free. */
+ * The model is Sec. 2, Eq. (1): H = J sum_j S_j . S_{j+1}, J = 1, periodic;
+ * spin S > 1/2 is represented by 2S subspins per spin and (2S)^2 sub-bonds
+ * per bond (Sec. 5).  The paper leaves the starting configuration open; the
+ * Neel state with a Philox phase (bit 0 of the INIT block) is this library's
+ * reading, shared with the oracle.  Errors: LC_EINVAL for L odd, L < 4,
+ * L >= 2^32, (2S)^2 L >= 2^32, 2S not an integer in 1..8, beta not finite,
+ * <= 0 or > 8 2^32; LC_ETOOLARGE when the footprint exceeds the device;
+ * LC_ENOMEM, LC_EDEVICE.  alloc may be NULL (hipMalloc); hip_stream may be
+ * NULL.  *out receives the handle, owned by the caller until lc_free. */
 int lc_init_lattice(int64_t L, double S, double beta, uint64_t seed, const lc_alloc *alloc,
                     void *hip_stream, lc_chain **out);
 
@@ -126,7 +135,14 @@ int lc_init_lattice(int64_t L, double S, double beta, uint64_t seed, const lc_al
  * LC_ESTATE when the chain belongs to a batch. */
 int lc_update(lc_chain *c, int64_t n_sweeps, int accumulate);
 
-/* measure: FP64 observables from the accumulated sums into *out. */
+/* measure: FP64 observables from the accumulated sums into *out (Sec. 2,
+ * step 8, the measurement after each update; the paper prints no estimator
+ * formulas, so the definitions are those of lc_measurement above: the
+ * energy from the operator count, the susceptibilities and structure factor
+ * from per-loop sums -- the improved estimators of the loop algorithm).
+ * Every average is an exact integer sum divided in FP64 at the end.  With no
+ * accumulated sweep, n_sweeps = 0 and every other field is 0.  LC_EINVAL on
+ * NULL.  Host-only: no device work. */
 int lc_measure(const lc_chain *c, lc_measurement *out);
 
 /* Integers of the most recent sweep; LC_ESTATE before the first sweep. */
@@ -160,8 +176,11 @@ int lc_import_state(lc_chain *c, const uint8_t *s0, const int64_t *bond_off, con
 int lc_export_ops(const lc_chain *c, int64_t *op_bond, uint64_t *op_time, uint8_t *op_type0,
                   uint8_t *op_type1, int64_t *n_ops);
 
-/* Loop labels of the most recent sweep: labels[v] = smallest node id of the
- * loop through node v.  Nodes: boundary nodes first (S = 1/2: one per spin;
+/* Loop labels of the most recent sweep (Sec. 2: loops are the connected
+ * components of the graph of world-line fragments, identified by union-find;
+ * the label of a loop is its smallest node id, the canonical representative
+ * that makes the result independent of the order of the unions, Sec. 3.2):
+ * labels[v] = smallest node id of the loop through node v.  Nodes: boundary nodes first (S = 1/2: one per spin;
  * split spins: bottom(x) = x and top(x) = n_sites + x), then operator q has
  * lower node nbn + 2q and upper node nbn + 2q + 1.  *n_nodes: capacity in,
  * count out.  Same validity as lc_export_ops. */
@@ -191,6 +210,12 @@ int lc_batch_update(lc_batch *b, int64_t n_sweeps, int accumulate);
  * node and window loops, and graph capture on/off.  Schedule only: results
  * do not depend on it. */
 int lc_batch_set_schedule(lc_batch *b, int grid_blocks, int use_graph);
+/* Bytes of device memory held by the per-sweep scratch arena the batch uses
+ * (shared with every engine on its stream and allocator).  The arena grows
+ * with headroom when a sweep needs more and is released with the last
+ * engine that uses it; admission policies bound their budgets with it.
+ * Host-only; LC_EINVAL on NULL. */
+int lc_batch_scratch_bytes(const lc_batch *b, size_t *bytes);
 void lc_batch_free(lc_batch *b);
 
 /* Same launch configuration for a chain run alone. */
@@ -220,6 +245,21 @@ int lc_set_profiling(lc_chain *c, int on);
 int lc_profile(const lc_chain *c, double *ms, int n, int64_t *sweeps);
 int lc_batch_set_profiling(lc_batch *b, int on);
 int lc_batch_profile(const lc_batch *b, double *ms, int n, int64_t *sweeps);
+
+/* ---- measurement probes (ceilings of this device) -----------------------
+ * lc_probe_cas: random 8-byte compare-and-swap on an array of 2^log2_words
+ * words (10..34), the access of a lock-free union-find hook (Sec. 3.2); about
+ * n_cas operations per launch, best of `repeats` timed launches after one
+ * warm-up.  Every CAS succeeds and leaves the array unchanged.  *cas_per_s
+ * receives the rate and *success_frac (may be NULL) the fraction of CAS that
+ * found the expected word (1 by construction).  lc_probe_copy: a streaming
+ * device-to-device copy of `bytes` bytes; *gb_per_s counts bytes read plus
+ * bytes written per second.  Both allocate and free their own device
+ * buffers (hipMalloc), run on hip_stream (may be NULL) and return LC_EINVAL,
+ * LC_ENOMEM or LC_EDEVICE on failure. */
+int lc_probe_cas(int log2_words, int64_t n_cas, int repeats, void *hip_stream, double *cas_per_s,
+                 double *success_frac);
+int lc_probe_copy(int64_t bytes, int repeats, void *hip_stream, double *gb_per_s);
 
 /* ---- testing hooks (host code of the library, no GPU needed) ------------
  * The library's host twin of its Philox4x32-10 and its Poisson window rule:

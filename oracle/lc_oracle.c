@@ -159,6 +159,9 @@ int orc_create(int64_t L, int two_s, double beta, uint64_t seed, orc_chain **out
 {
     if (!out || L < 4 || (L & 1) || two_s < 1 || two_s > 8)
         return ORC_EINVAL;
+    /* bond indices are 32-bit Philox counter words */
+    if ((int64_t)two_s * two_s * L >= ((int64_t)1 << 32))
+        return ORC_EINVAL;
     orc_chain *c = (orc_chain *)calloc(1, sizeof(orc_chain));
     if (!c)
         return ORC_ENOMEM;

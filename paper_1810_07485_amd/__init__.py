@@ -108,6 +108,7 @@ def load():
         "lc_batch_size": ([vp, pi], C.c_int),
         "lc_batch_update": ([vp, C.c_int64, C.c_int], C.c_int),
         "lc_batch_set_schedule": ([vp, C.c_int, C.c_int], C.c_int),
+        "lc_batch_scratch_bytes": ([vp, C.POINTER(C.c_size_t)], C.c_int),
         "lc_batch_free": ([vp], None),
         "lc_set_schedule": ([vp, C.c_int, C.c_int], C.c_int),
         "lc_phase_count": ([], C.c_int),
@@ -116,6 +117,9 @@ def load():
         "lc_profile": ([vp, C.POINTER(C.c_double), C.c_int, p64], C.c_int),
         "lc_batch_set_profiling": ([vp, C.c_int], C.c_int),
         "lc_batch_profile": ([vp, C.POINTER(C.c_double), C.c_int, p64], C.c_int),
+        "lc_probe_cas": ([C.c_int, C.c_int64, C.c_int, vp, C.POINTER(C.c_double),
+                          C.POINTER(C.c_double)], C.c_int),
+        "lc_probe_copy": ([C.c_int64, C.c_int, vp, C.POINTER(C.c_double)], C.c_int),
         "lc_debug_philox": ([C.c_uint64, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)], C.c_int),
         "lc_debug_window_table": ([C.c_double, pi, C.POINTER(C.c_double), pu64, pi], C.c_int),
     }
@@ -180,6 +184,23 @@ def lc_debug_window_table(beta: float):
     _check(load().lc_debug_window_table(float(beta), C.byref(w), C.byref(mu), T, C.byref(K)),
            "lc_debug_window_table")
     return w.value, mu.value, [T[i] for i in range(K.value)]
+
+
+def lc_probe_cas(log2_words: int, n_cas: int = 1 << 26, repeats: int = 3, stream=None) -> tuple:
+    """(random 8-byte CAS per second, success fraction) on 2^log2_words words."""
+    r, f = C.c_double(), C.c_double()
+    h = C.c_void_p(stream.cuda_stream) if stream is not None else None
+    _check(load().lc_probe_cas(int(log2_words), int(n_cas), int(repeats), h, C.byref(r), C.byref(f)),
+           "lc_probe_cas")
+    return r.value, f.value
+
+
+def lc_probe_copy(nbytes: int, repeats: int = 3, stream=None) -> float:
+    """Device-to-device streaming copy: bytes read + written per second / 1e9."""
+    r = C.c_double()
+    h = C.c_void_p(stream.cuda_stream) if stream is not None else None
+    _check(load().lc_probe_copy(int(nbytes), int(repeats), h, C.byref(r)), "lc_probe_copy")
+    return r.value
 
 
 class _TorchMemory:
@@ -409,6 +430,12 @@ class Batch:
 
     def set_profiling(self, on: bool = True):
         _check(load().lc_batch_set_profiling(self._h, int(bool(on))), "lc_batch_set_profiling")
+
+    def scratch_bytes(self) -> int:
+        """Device bytes of the scratch arena this batch uses (lc_batch_scratch_bytes)."""
+        n = C.c_size_t()
+        _check(load().lc_batch_scratch_bytes(self._h, C.byref(n)), "lc_batch_scratch_bytes")
+        return n.value
 
     def autotune(self, grids=DEFAULT_GRIDS, trial_sweeps: int = 2) -> tuple:
         """Pick the fastest grid size (runs real, unaccumulated sweeps)."""

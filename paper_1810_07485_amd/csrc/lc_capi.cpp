@@ -149,24 +149,26 @@ struct Arena {
   uint64_t gen = 1;   // bumped whenever a buffer is reallocated
   uint64_t runs = 0;  // bumped by every group of sweeps (export validity)
   std::mutex mu;      // one engine at a time
-  DBuf<int64_t> opstart, kflat, parent, rcnt;
+  DBuf<int64_t> opstart, kflat, parent, rcnt, xedge, frag;
   DBuf<uint64_t> optime;
   DBuf<uint8_t> optype;
   DBuf<uint32_t> accmask;
   DBuf<unsigned long long> acc, bacc;
-  int64_t op_cap = 0, node_cap = 0, root_cap = 0;
+  int64_t op_cap = 0, node_cap = 0, root_cap = 0, xcap = 0, fcap = 0;
 
   void release_all() {
     opstart.release(mem);
     kflat.release(mem);
     parent.release(mem);
     rcnt.release(mem);
+    xedge.release(mem);
+    frag.release(mem);
     optime.release(mem);
     optype.release(mem);
     accmask.release(mem);
     acc.release(mem);
     bacc.release(mem);
-    op_cap = node_cap = root_cap = 0;
+    op_cap = node_cap = root_cap = xcap = fcap = 0;
     ++gen;
   }
   // grow b to hold want elements; a move bumps the generation
@@ -181,7 +183,8 @@ struct Arena {
     return b.ensure(mem, want);
   }
   double bytes() const {
-    return 8.0 * (opstart.n + kflat.n + parent.n + rcnt.n + optime.n + acc.n + bacc.n) +
+    return 8.0 * (opstart.n + kflat.n + parent.n + rcnt.n + xedge.n + frag.n + optime.n + acc.n +
+                  bacc.n) +
            static_cast<double>(optype.n) + 4.0 * accmask.n;
   }
 };
@@ -228,6 +231,8 @@ struct lc_chain {
   uint64_t T[lc::kMaxTable] = {};
   int K = 0;
   int64_t n_sites = 0, n_bonds = 0, nwin = 0, nbn = 0;
+  int tile_j = 1, tile_k = 1, tile_shrink = 0;  // linking tile (spins x windows)
+  int64_t ntj = 1, ntk = 1;
   Mem mem;
   hipStream_t stream = nullptr;
   DBuf<uint8_t> s0[2];
@@ -258,13 +263,16 @@ struct Engine {
   bool use_graph = true;
   // per-chain small arrays
   DBuf<ChainDesc> descs;
-  DBuf<int64_t> win_bases, site_bases, spin_bases, op_bases, node_bases, loop_bases;
+  DBuf<int64_t> win_bases, site_bases, spin_bases, op_bases, node_bases;
   DBuf<ChainDyn> dyn;
-  DBuf<int64_t> totals, scan_tmp;
+  DBuf<int64_t> totals, scan_tmp, bn_bases, grp_tile_base;
+  DBuf<int> grp_chain;
+  DBuf<unsigned long long> dyncnt;
+  std::vector<LcTileGroup> groups;
   DBuf<uint64_t> stats;
   DBuf<uint32_t> flags, ring_ctr;
   DBuf<unsigned long long> ring;
-  int64_t nwin = 0, nsites = 0, nspins = 0, sum_nbn = 0;
+  int64_t nwin = 0, nsites = 0, nspins = 0, sum_nbn = 0, sum_xe = 0, sum_fe = 0;
   bool any_split = false;
   hipGraphExec_t gexec = nullptr;
   bool graph_ok = false;
@@ -298,11 +306,14 @@ struct Engine {
     dyn.release(mem);
     totals.release(mem);
     scan_tmp.release(mem);
+    bn_bases.release(mem);
+    grp_tile_base.release(mem);
+    grp_chain.release(mem);
+    dyncnt.release(mem);
     stats.release(mem);
     flags.release(mem);
     ring_ctr.release(mem);
     ring.release(mem);
-    loop_bases.release(mem);
     arena_put(ar);
     ar = nullptr;
   }
@@ -342,20 +353,20 @@ ChainDesc make_desc(const lc_chain* c, int64_t win_base, int64_t site_base, int6
   d.K = c->K;
   d.sweep = c->sweep;
   d.cur = c->cur;
+  d.tile_j = c->tile_j;
+  d.tile_k = c->tile_k;
+  d.ntj = c->ntj;
   std::memcpy(d.T, c->T, sizeof(d.T));
   return d;
 }
 
-// Loop records needed by a chain: every boundary node may be alone; operator
-// nodes form loops of at least two nodes.  For S = 1/2 the closed two-node
-// loops (nine in ten at low temperature) are finished while linking and take
-// no record: about 0.04 recorded loops per unit L beta remain against 0.69
-// operators.  Split spins keep a record per loop (about 0.29 per node).
-// Grown on overflow.
-int64_t loops_estimate(int64_t nbn, int two_s, int64_t ops) {
-  const double per_op_node = two_s == 1 ? 0.08 : 0.32;
-  return nbn + static_cast<int64_t>(per_op_node * 2.0 * static_cast<double>(ops));
-}
+// Edges between linking tiles and open fragments per operator: with tiles of
+// 64 spins x 4 windows about one operator in twelve has an edge leaving its
+// tile at S = 1/2; split-spin tiles span few spins (2S bonds wide at each
+// side) and about half of their operators do.  Grown on overflow from the
+// exact counts of the sweep.
+double cross_per_op(int two_s) { return two_s == 1 ? 0.12 : 0.7; }
+double frags_per_op(int two_s) { return two_s == 1 ? 0.12 : 0.7; }
 
 // Initial kept-operator capacity per buffer: about 0.3 off-diagonal
 // operators per bond and unit beta at low temperature; grown on overflow.
@@ -382,8 +393,10 @@ int64_t ops_estimate(const lc_chain* c) {
                                         static_cast<double>(c->L), c->two_s, c->beta));
 }
 
-// Arena capacity for ops operators, nodes loop-graph nodes, roots loops.
-int ensure_scratch(Arena& A, int64_t ops, int64_t nodes, int64_t roots) {
+// Arena capacity for ops operators, nodes loop-graph nodes, xe edges between
+// tiles and fe fragments of an engine with nbn boundary nodes; loop records
+// and root counts follow the items (fragments and boundary nodes).
+int ensure_scratch(Arena& A, int64_t ops, int64_t nodes, int64_t xe, int64_t fe, int64_t nbn) {
   // A buffer that has to grow takes the need plus 1/16, and at least a
   // quarter more than it had: every move invalidates the graphs of all
   // engines sharing the arena, so slowly rising demand (chains still
@@ -398,71 +411,123 @@ int ensure_scratch(Arena& A, int64_t ops, int64_t nodes, int64_t roots) {
   if (A.node_cap < nodes) {
     nodes = target(nodes, A.node_cap);
     A.node_cap = 0;
-    if (!(A.grow(A.parent, nodes) && A.grow(A.rcnt, static_cast<size_t>(nodes / 4096 + 2))))
-      return LC_ENOMEM;
+    if (!A.grow(A.parent, nodes)) return LC_ENOMEM;
     A.node_cap = nodes;
   }
-  if (A.root_cap < roots) {
-    roots = target(roots, A.root_cap);
+  if (A.xcap < xe) {
+    xe = target(xe, A.xcap);
+    A.xcap = 0;
+    if (!A.grow(A.xedge, 2 * static_cast<size_t>(xe))) return LC_ENOMEM;
+    A.xcap = xe;
+  }
+  if (A.fcap < fe) {
+    fe = target(fe, A.fcap);
+    A.fcap = 0;
+    if (!A.grow(A.frag, 4 * static_cast<size_t>(fe))) return LC_ENOMEM;
+    A.fcap = fe;
+  }
+  const int64_t items = A.fcap + nbn;
+  if (A.root_cap < items) {
+    const int64_t roots = target(items, A.root_cap);
     A.root_cap = 0;
     if (!A.grow(A.acc, kAccWords * static_cast<size_t>(roots))) return LC_ENOMEM;
     A.root_cap = roots;
   }
+  if (!A.grow(A.rcnt, static_cast<size_t>(items / 4096 + 2))) return LC_ENOMEM;
   return LC_OK;
 }
 
-// (Re)build the flat layout of an engine's chains and upload descriptors.
-// Loop records for an engine whose chains need ops operators in all: each
-// chain's share of ops by its own estimate.
-int64_t loops_needed(const Engine& E, int64_t ops) {
-  int64_t est = 0, sum = 0;
-  for (const lc_chain* c : E.chains) est += ops_estimate(c);
-  for (const lc_chain* c : E.chains) {
-    const double share = est > 0 ? static_cast<double>(ops_estimate(c)) / static_cast<double>(est) : 0.0;
-    sum += loops_estimate(c->nbn, c->two_s, static_cast<int64_t>(share * static_cast<double>(ops)));
-  }
-  return sum + 65536;
+// Linking tile of a chain: spins x windows with at most LC_TILE_THREADS
+// (subspin, window) walkers and LC_TILE_BONDS owned bonds, sized for about
+// 1,500 operators (LC_TILE_OPS is the hard limit: a tile beyond it makes the
+// sweep replay with tiles half as large, tile_shrink).  S = 1/2 tiles are
+// 4 windows tall: a site crosses a window boundary once, a tile side on
+// about half of its events.  Split-spin tiles are one window tall: 2S bonds
+// wide at each side, they need all the spins they can get.
+void choose_tile(lc_chain* c) {
+  const int ts = c->two_s;
+  const int64_t W = int64_t(1) << c->w;
+  const double win_tau = c->beta / static_cast<double>(W);
+  // operators per sub-bond and unit imaginary time: about ln 2 for S = 1/2,
+  // the bound (N_b/4 + L S(S+1)) / N_b otherwise
+  const double rho = ts == 1 ? 0.72 : (ts + 1.0) / (2.0 * ts);
+  const double per_spin_window = std::max(rho * ts * ts * win_tau, 1e-9);
+  const double target = 1500.0 / static_cast<double>(int64_t(1) << c->tile_shrink);
+  int64_t tk = std::min<int64_t>(W, ts == 1 ? 4 : 1);
+  while (tk > 1 && per_spin_window * static_cast<double>(tk) > target) tk >>= 1;
+  int64_t tj = static_cast<int64_t>(target / (per_spin_window * static_cast<double>(tk)));
+  tj = std::min<int64_t>(tj, LC_TILE_THREADS / (ts * tk));
+  tj = std::min<int64_t>(tj, LC_TILE_BONDS / (ts * ts));
+  tj = std::min<int64_t>(tj, c->L);
+  tj = std::max<int64_t>(tj, 1);
+  c->tile_j = static_cast<int>(tj);
+  c->tile_k = static_cast<int>(tk);
+  c->ntj = (c->L + tj - 1) / tj;
+  c->ntk = (W + tk - 1) / tk;
 }
 
 int layout(Engine& E) {
   const int n = static_cast<int>(E.chains.size());
   std::vector<ChainDesc> h(n);
-  std::vector<int64_t> wb(n), sb(n), pb(n);
-  int64_t nwin = 0, nsites = 0, nspins = 0, nbn = 0, ops = 0;
+  std::vector<int64_t> wb(n), sb(n), pb(n), bb(n), tb;
+  std::vector<int> gc;
+  int64_t nwin = 0, nsites = 0, nspins = 0, nbn = 0, ops = 0, xe = 0, fe = 0;
   bool split = false;
   for (int i = 0; i < n; ++i) {
     lc_chain* c = E.chains[i];
+    choose_tile(c);
     h[i] = make_desc(c, nwin, nsites, nspins, nbn);
     wb[i] = nwin;
     sb[i] = nsites;
     pb[i] = nspins;
+    bb[i] = nbn;
     nwin += c->nwin;
     nsites += c->n_sites;
     nspins += c->L;
     nbn += c->nbn;
-    ops += ops_estimate(c);
+    const int64_t o = ops_estimate(c);
+    ops += o;
+    xe += static_cast<int64_t>(cross_per_op(c->two_s) * static_cast<double>(o)) + 4096;
+    fe += static_cast<int64_t>(frags_per_op(c->two_s) * static_cast<double>(o)) + 4096;
     split = split || c->two_s > 1;
+  }
+  // one tile group per spin length present
+  E.groups.clear();
+  for (int ts = 1; ts <= LC_MAX_TS; ++ts) {
+    LcTileGroup g{ts, 0, static_cast<int>(gc.size()), 0};
+    for (int i = 0; i < n; ++i) {
+      const lc_chain* c = E.chains[i];
+      if (c->two_s != ts) continue;
+      gc.push_back(i);
+      tb.push_back(g.ntiles);
+      g.ntiles += c->ntj * c->ntk;
+      g.nchain += 1;
+    }
+    if (g.nchain) E.groups.push_back(g);
   }
   const Mem& m = E.mem;
   const size_t nc = static_cast<size_t>(std::max(n, 1));
   bool ok = E.descs.ensure(m, nc) && E.win_bases.ensure(m, nc) && E.site_bases.ensure(m, nc) &&
             E.spin_bases.ensure(m, nc) && E.op_bases.ensure(m, nc) && E.node_bases.ensure(m, nc) &&
+            E.bn_bases.ensure(m, nc) && E.grp_chain.ensure(m, nc) && E.grp_tile_base.ensure(m, nc) &&
+            E.dyncnt.ensure(m, 4) &&
             E.dyn.ensure(m, nc) && E.totals.ensure(m, 2) && E.scan_tmp.ensure(m, LC_SCAN_BLOCKS + 1) &&
             E.stats.ensure(m, nc * lc::ST_WORDS * (1 + LC_STAT_STRIPES)) && E.flags.ensure(m, 2) && E.ring_ctr.ensure(m, 2) &&
-            E.ring.ensure(m, static_cast<size_t>(kRing) * (nc * lc::ST_WORDS + 1)) &&
-            E.loop_bases.ensure(m, nc);
+            E.ring.ensure(m, static_cast<size_t>(kRing) * (nc * lc::ST_WORDS + 1));
   if (!ok) return LC_ENOMEM;
   Arena& A = *E.ar;
   ok = A.grow(A.opstart, static_cast<size_t>(nwin) + 1) && A.grow(A.kflat, static_cast<size_t>(nwin) + 1) &&
        A.grow(A.accmask, static_cast<size_t>(std::max<int64_t>(nwin, 1))) &&
        A.grow(A.bacc, static_cast<size_t>(std::max<int64_t>(nsites, 1)));
   if (!ok) return LC_ENOMEM;
-  int rc = ensure_scratch(A, ops, nbn + 2 * ops, loops_needed(E, ops));
+  int rc = ensure_scratch(A, ops, nbn + 2 * ops, xe, fe, nbn);
   if (rc != LC_OK) return rc;
   E.nwin = nwin;
   E.nsites = nsites;
   E.nspins = nspins;
   E.sum_nbn = nbn;
+  E.sum_xe = xe;
+  E.sum_fe = fe;
   E.any_split = split;
   if (n > 0) {
     hipStream_t s = E.stream;
@@ -470,6 +535,9 @@ int layout(Engine& E) {
         hipMemcpyAsync(E.win_bases.p, wb.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, s) ||
         hipMemcpyAsync(E.site_bases.p, sb.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, s) ||
         hipMemcpyAsync(E.spin_bases.p, pb.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, s) ||
+        hipMemcpyAsync(E.bn_bases.p, bb.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, s) ||
+        hipMemcpyAsync(E.grp_chain.p, gc.data(), n * sizeof(int), hipMemcpyHostToDevice, s) ||
+        hipMemcpyAsync(E.grp_tile_base.p, tb.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, s) ||
         hipStreamSynchronize(s))
       return LC_EDEVICE;
   }
@@ -483,12 +551,20 @@ int layout(Engine& E) {
 }
 
 // Grow the arena, if needed, to the engine's current per-sweep bound
-// (kept + candidates per chain, from the host mirror of the kept counts).
-int ensure_capacity(Engine& E, int64_t at_least_ops) {
-  int64_t ops = 0;
-  for (lc_chain* c : E.chains) ops += ops_estimate(c);
+// (kept + candidates per chain, from the host mirror of the kept counts) and
+// to at least the given counts.
+int ensure_capacity(Engine& E, int64_t at_least_ops, int64_t at_least_xe = 0, int64_t at_least_fe = 0) {
+  int64_t ops = 0, xe = 0, fe = 0;
+  for (lc_chain* c : E.chains) {
+    const int64_t o = ops_estimate(c);
+    ops += o;
+    xe += static_cast<int64_t>(cross_per_op(c->two_s) * static_cast<double>(o)) + 4096;
+    fe += static_cast<int64_t>(frags_per_op(c->two_s) * static_cast<double>(o)) + 4096;
+  }
   ops = std::max(ops, at_least_ops);
-  return ensure_scratch(*E.ar, ops, E.sum_nbn + 2 * ops, loops_needed(E, ops));
+  xe = std::max(xe, at_least_xe);
+  fe = std::max(fe, at_least_fe);
+  return ensure_scratch(*E.ar, ops, E.sum_nbn + 2 * ops, xe, fe, E.sum_nbn);
 }
 
 LcSweepArgs sweep_args(Engine& E) {
@@ -499,9 +575,15 @@ LcSweepArgs sweep_args(Engine& E) {
   A.spin_bases = E.spin_bases.p;
   A.nchain = static_cast<int>(E.chains.size());
   A.any_split = E.any_split ? 1 : 0;
+  A.bn_bases = E.bn_bases.p;
   A.nwin = E.nwin;
   A.nsites = E.nsites;
   A.nspins = E.nspins;
+  A.nbn = E.sum_nbn;
+  A.ngroups = static_cast<int>(E.groups.size());
+  for (int g = 0; g < A.ngroups; ++g) A.groups[g] = E.groups[g];
+  A.grp_chain = E.grp_chain.p;
+  A.grp_tile_base = E.grp_tile_base.p;
   A.grid_blocks = E.grid;
   const Arena& R = *E.ar;
   A.opstart = R.opstart.p;
@@ -510,9 +592,13 @@ LcSweepArgs sweep_args(Engine& E) {
   A.optime = R.optime.p;
   A.optype = R.optype.p;
   A.parent = R.parent.p;
+  A.xedge = R.xedge.p;
+  A.frag = R.frag.p;
+  A.xcap = R.xcap;
+  A.fcap = R.fcap;
+  A.dyncnt = E.dyncnt.p;
   A.acc = R.acc.p;
   A.bacc = R.bacc.p;
-  A.loop_bases = E.loop_bases.p;
   A.root_cap = R.root_cap;
   A.rcnt = R.rcnt.p;
   A.op_cap = R.op_cap;
@@ -663,25 +749,34 @@ int run_engine(Engine& E, int64_t n_sweeps, int accumulate) {
     }
     // a sweep did not fit: grow and run it again
     if (bad & LC_FLAG_SYM) return LC_ESTATE;
-    if (++stuck > 8) return LC_ENOMEM;
+    if (bad & LC_FLAG_GRAPH) {
+      std::fprintf(stderr, "[lc] internal error: inconsistent loop graph (flags %#x)\n", bad);
+      return LC_EDEVICE;
+    }
+    if (++stuck > 16) return LC_ENOMEM;
     for (int i = 0; i < nch; ++i) E.chains[i]->last_engine = nullptr;
     const unsigned long long* r = E.hring.data() + ok * rec;
+    if (verbose()) std::fprintf(stderr, "[lc] sweep replayed: flags %#x\n", bad);
+    if (bad & LC_FLAG_TILE) {
+      for (lc_chain* c : E.chains) c->tile_shrink = std::min(c->tile_shrink + 1, 10);
+    }
+    int64_t tot[2] = {0, 0};
+    unsigned long long dc[2] = {0, 0};
     if (bad & (LC_FLAG_OPS | LC_FLAG_NODES)) {
-      int64_t tot[2] = {0, 0};
       if (hipMemcpy(tot, E.totals.p, sizeof(tot), hipMemcpyDeviceToHost) != hipSuccess)
         return LC_EDEVICE;
+    }
+    if (bad & (LC_FLAG_XEDGE | LC_FLAG_FRAG)) {
+      if (hipMemcpy(dc, E.dyncnt.p, sizeof(dc), hipMemcpyDeviceToHost) != hipSuccess)
+        return LC_EDEVICE;
+    }
+    if (bad & (LC_FLAG_OPS | LC_FLAG_NODES | LC_FLAG_XEDGE | LC_FLAG_FRAG | LC_FLAG_ROOTS)) {
       // the totals are exact; grow to them plus a margin, or to the
       // per-sweep bound of the current kept counts (the arena may already
       // be larger, sized by another engine)
-      if ((rc = ensure_capacity(E, tot[0] + tot[0] / 8 + 4096)) != LC_OK) return rc;
-    }
-    if (bad & LC_FLAG_ROOTS) {
-      int64_t cnt = 0;
-      const int64_t nch = (R.node_cap + 4095) / 4096;
-      if (hipMemcpy(&cnt, R.rcnt.p + nch, sizeof(cnt), hipMemcpyDeviceToHost) != hipSuccess)
-        return LC_EDEVICE;
-      const int64_t need = static_cast<int64_t>(cnt);
-      if ((rc = ensure_scratch(R, 0, 0, need + need / 4 + 65536)) != LC_OK) return rc;
+      const int64_t x = static_cast<int64_t>(dc[0]), f = static_cast<int64_t>(dc[1]);
+      if ((rc = ensure_capacity(E, tot[0] + tot[0] / 8 + 4096, x + x / 8 + 4096, f + f / 8 + 4096)) != LC_OK)
+        return rc;
     }
     if (bad & LC_FLAG_KEPT) {
       for (int i = 0; i < nch; ++i) {
@@ -696,11 +791,13 @@ int run_engine(Engine& E, int64_t n_sweeps, int accumulate) {
 }
 
 int validate(int64_t L, double S, double beta, int* two_s) {
-  if (L < 4 || (L & 1) || L > (int64_t(1) << 40)) return LC_EINVAL;
+  if (L < 4 || (L & 1) || L >= (int64_t(1) << 32)) return LC_EINVAL;
   if (!std::isfinite(S)) return LC_EINVAL;
   const double ts = 2.0 * S;
   const int t = static_cast<int>(std::lround(ts));
   if (std::fabs(ts - t) > 1e-12 || t < 1 || t > 8) return LC_EINVAL;
+  // bond and spin indices are 32-bit counter words of the Philox draws
+  if (static_cast<int64_t>(t) * t * L >= (int64_t(1) << 32)) return LC_EINVAL;
   if (!(beta > 0.0) || !std::isfinite(beta) || beta > 8.0 * 4294967296.0) return LC_EINVAL;
   *two_s = t;
   return LC_OK;
@@ -719,14 +816,14 @@ void footprint_parts(int64_t L, int two_s, double beta, double* state_b, double*
   const double kept = static_cast<double>(kept_initial(static_cast<int64_t>(n_bonds), beta));
   const double ops = ops_bound(kept, n_bonds, static_cast<double>(L), two_s, beta);
   const double nodes = nbn + 2 * ops;
-  const double loops =
-      static_cast<double>(loops_estimate(static_cast<int64_t>(nbn), two_s, static_cast<int64_t>(ops)) + 65536);
+  const double xe = cross_per_op(two_s) * ops + 4096, fe = frags_per_op(two_s) * ops + 4096;
   // spins, kept-operator window scans and times (both halves), permutation
   *state_b = 2 * n_sites + 2 * 8 * (nwin + 1) + 2 * 8 * kept + 8 * n_sites + 65536;
-  // window scans, operators (time + type), parent words, loop records
-  // (24 B accumulators), boundary records
-  *scratch_b = 2 * 8 * (nwin + 1) + 4 * nwin + 9 * ops + nodes * 8 + loops * (8 * kAccWords) +
-               8 * n_sites + (1 << 20);
+  // window scans, operators (time + type), parent words, edges between
+  // tiles (16 B), fragments (32 B), loop records (one per item), boundary
+  // records
+  *scratch_b = 2 * 8 * (nwin + 1) + 4 * nwin + 9 * ops + nodes * 8 + 16 * xe + 32 * fe +
+               (fe + nbn) * (8 * kAccWords) + 8 * n_sites + (1 << 20);
 }
 
 size_t footprint_bytes(int64_t L, int two_s, double beta) {
@@ -1098,8 +1195,23 @@ int lc_export_labels(const lc_chain* c, int64_t* labels, int64_t* n_nodes) {
   if (hipMemcpy(labels, c->last_engine->ar->parent.p + d.node_base, d.n_nodes * sizeof(int64_t),
                 hipMemcpyDeviceToHost) != hipSuccess)
     return LC_EDEVICE;
-  // parent words: a root holds a negative code, every other node its root
-  for (int64_t v = 0; v < d.n_nodes; ++v) labels[v] = labels[v] < 0 ? v : labels[v] - d.node_base;
+  // parent words after a sweep: a node holding a negative word is the
+  // smallest node of its loop (a loop code, or a loop finished inside its
+  // linking tile); any other node's parent p is that smallest node or a
+  // node whose own word is it (non-negative) or a code (p is it).  Words
+  // are read from the copy before any is rewritten.
+  std::vector<int64_t> w(labels, labels + d.n_nodes);
+  for (int64_t v = 0; v < d.n_nodes; ++v) {
+    const int64_t p = w[v];
+    if (p < 0) {
+      labels[v] = v;
+    } else {
+      const int64_t pl = p - d.node_base;
+      if (pl < 0 || pl >= d.n_nodes) return LC_EDEVICE;  // not a node of this chain
+      const int64_t pp = w[pl];
+      labels[v] = (pp >= 0 ? pp : p) - d.node_base;
+    }
+  }
   return LC_OK;
 }
 
@@ -1199,6 +1311,12 @@ int lc_batch_update(lc_batch* b, int64_t n_sweeps, int accumulate) {
   return run_engine(b->eng, n_sweeps, accumulate);
 }
 
+int lc_batch_scratch_bytes(const lc_batch* b, size_t* bytes) {
+  if (!b || !bytes) return LC_EINVAL;
+  *bytes = b->eng.ar ? static_cast<size_t>(b->eng.ar->bytes()) : 0;
+  return LC_OK;
+}
+
 int lc_batch_set_schedule(lc_batch* b, int grid_blocks, int use_graph) {
   if (!b || grid_blocks < 0) return LC_EINVAL;
   b->eng.grid = grid_blocks > 0 ? grid_blocks : kDefaultGrid;
@@ -1208,8 +1326,8 @@ int lc_batch_set_schedule(lc_batch* b, int grid_blocks, int use_graph) {
 }
 
 static const char* const kPhaseNames[LC_PH_COUNT] = {
-    "setup",     "gen_count", "scan_ops", "gen_write",    "init_parent", "link_ops",  "link_sites",
-    "compress",  "roots",     "accum",    "cluster_sums", "flip",        "scan_kept", "compact"};
+    "setup",    "gen_count", "scan_ops",     "gen_write", "link_tiles", "link_cross", "compress",
+    "roots",    "accum",     "cluster_sums", "flip",      "scan_kept",  "compact"};
 
 int lc_phase_count(void) { return LC_PH_COUNT; }
 

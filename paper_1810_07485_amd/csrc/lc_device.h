@@ -68,7 +68,10 @@ struct ChainDesc {
   int32_t K;           // threshold table length
   uint32_t sweep;      // sweep being run (advanced on the device)
   int32_t cur;         // which of the two state buffers is current
+  int32_t tile_j;      // linking tile: spins per tile
+  int32_t tile_k;      //               windows per tile
   int32_t pad;
+  int64_t ntj;         // tiles along the chain, ceil(L / tile_j)
   uint64_t T[kMaxTable];
 };
 

@@ -8,18 +8,39 @@
 #include "lc_device.h"
 
 #define LC_SCAN_BLOCKS 1024
-#define LC_ACC_WORDS 3  // accumulator words per loop record
+#define LC_ACC_WORDS 4       // words per loop record: nodes + tops << 40, sum hi, sum lo, chain
 #define LC_STAT_STRIPES 256  // striped copies of each statistics word (after the words)
+#define LC_MAX_TS 8          // 2S of the largest spin (S = 4)
+
+// Linking tiles (bond range x window range of one chain, one workgroup).
+#define LC_TILE_OPS 2048     // operators of a tile held in LDS
+#define LC_TILE_BONDS 256    // owned bonds of a tile
+#define LC_TILE_THREADS 256  // (subspin, window) walkers of a tile
+
+// Chains of one spin length form a group: the linking kernel is compiled per
+// 2S, and each group is one launch over its chains' tiles.
+struct LcTileGroup {
+  int two_s;                // 2S of the group's chains
+  int nchain;               // chains in the group
+  int offset;               // first entry of the group in grp_chain / grp_tile_base
+  int64_t ntiles;           // tiles of all the group's chains
+};
 
 struct LcSweepArgs {
   lc::ChainDesc* descs;       // nchain descriptors
   const int64_t* win_bases;   // first flat window per chain
   const int64_t* site_bases;  // first flat subspin per chain
   const int64_t* spin_bases;  // first flat spin per chain
+  const int64_t* bn_bases;    // first flat boundary node per chain
   int nchain;
   int any_split;              // some chain has S > 1/2
-  int64_t nwin, nsites, nspins;
+  int64_t nwin, nsites, nspins, nbn;
   int grid_blocks;            // persistent grid size of the node/window loops
+  // linking tiles, per spin-length group
+  int ngroups;
+  LcTileGroup groups[LC_MAX_TS];
+  const int* grp_chain;       // chain index of each group entry
+  const int64_t* grp_tile_base;  // first tile of each group entry (within its group)
   // flat per-sweep scratch
   int64_t* opstart;           // nwin + 1
   uint32_t* accmask;          // nwin: acceptance mask of each window (<= 32 candidates)
@@ -27,11 +48,13 @@ struct LcSweepArgs {
   uint64_t* optime;           // op_cap
   uint8_t* optype;            // op_cap
   int64_t* parent;            // node_cap
-  unsigned long long* acc;    // 3 root_cap: loop accumulators
+  int64_t* xedge;             // 2 xcap: loop-graph edges between tiles (node, node)
+  int64_t* frag;              // 4 fcap: open fragments (rep, size | chain << 16, sum hi, sum lo)
+  unsigned long long* acc;    // LC_ACC_WORDS root_cap: loop records
   unsigned long long* bacc;   // nsites: boundary sums of loops rooted at each bottom node
-  int64_t* loop_bases;        // nchain: first loop index of each chain
-  int64_t op_cap, node_cap, root_cap;
-  int64_t* rcnt;              // loops per node chunk, scanned (node_cap / 4096 + 2)
+  int64_t op_cap, node_cap, root_cap, xcap, fcap;
+  int64_t* rcnt;              // roots per chunk of 4,096 items, scanned ((fcap + nbn) / 4096 + 2)
+  unsigned long long* dyncnt; // 4: cross edges, fragments written this sweep
   lc::ChainDyn* dyn;          // nchain
   int64_t* op_bases;          // nchain
   int64_t* node_bases;        // nchain
@@ -52,9 +75,8 @@ enum LcPhase {
   LC_PH_GEN_COUNT,
   LC_PH_SCAN_OPS,
   LC_PH_GEN_WRITE,
-  LC_PH_INIT_PARENT,
-  LC_PH_LINK_OPS,
-  LC_PH_LINK_SITES,
+  LC_PH_LINK_TILES,
+  LC_PH_LINK_CROSS,
   LC_PH_COMPRESS,
   LC_PH_ROOTS,
   LC_PH_ACCUM,
@@ -71,6 +93,10 @@ enum LcPhase {
 #define LC_FLAG_SYM 4u       // split-spin ends cannot be matched
 #define LC_FLAG_KEPT 8u      // a chain's kept-operator buffer too small
 #define LC_FLAG_ROOTS 16u    // loop-record buffer too small
+#define LC_FLAG_TILE 32u     // a linking tile exceeded its LDS capacities
+#define LC_FLAG_XEDGE 64u    // cross-edge buffer too small
+#define LC_FLAG_FRAG 128u    // fragment buffer too small
+#define LC_FLAG_GRAPH 256u   // a union-find word outside the loop graph (internal error)
 
 hipError_t lc_launch_sweep(const LcSweepArgs& a, hipStream_t s);
 hipError_t lc_launch_scan(int64_t* a, int64_t n, int64_t* bsum, hipStream_t s);

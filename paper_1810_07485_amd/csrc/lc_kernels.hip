@@ -24,10 +24,6 @@ namespace lc {
 constexpr int kBlock = 256;
 constexpr int kCap = 12;  // candidate times per window kept in LDS while writing; more are redrawn
 
-// Parent word of the upper node of a closed two-node loop (see k_link_ops):
-// below every root code -1 - index, so no kernel takes it for a loop index.
-constexpr int64_t kPairRoot = INT64_MIN;
-
 __device__ inline int lane_id() { return __lane_id(); }
 
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
@@ -362,35 +358,98 @@ __global__ void k_chain_bases(const ChainDesc* __restrict__ descs, int nchain,
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_init_parent(const int64_t* __restrict__ totals,
-                                                         int64_t node_cap,
-                                                         int64_t* __restrict__ parent) {
-  const int64_t n = min(totals[1], node_cap);
-  for (int64_t g = xcd_block() * kBlock + threadIdx.x; g < n;
-       g += static_cast<int64_t>(gridDim.x) * kBlock)
+
+// Loop-flip bit of a chain-local label: bit (label mod 128) of the Philox
+// block (label / 128) of the FLIP stream of this sweep.
+__device__ inline uint32_t flip_bit(const ChainDesc& D, int64_t label) {
+  const uint64_t q = static_cast<uint64_t>(label) >> 7;
+  const uint32_t i = static_cast<uint32_t>(label & 127);
+  const u32x4 r = philox10(D.seed, static_cast<uint32_t>(q),
+                           (DOM_FLIP << 24) | static_cast<uint32_t>((q >> 32) & 0xFFFFFFu), 0u,
+                           D.sweep);
+  const uint32_t wsel = i >> 5;
+  const uint32_t word = wsel == 0 ? r.x : (wsel == 1 ? r.y : (wsel == 2 ? r.z : r.w));
+  return (word >> (i & 31)) & 1u;
+}
+
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kBlock * kScanItems;
+
+__device__ inline int64_t block_exclusive_scan(int64_t v, int64_t* sh, int64_t& total) {
+  // wave inclusive scan
+  const int lane = lane_id(), wv = threadIdx.x >> 6;
+  int64_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sh[wv] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t s = 0;
+    for (int q = 0; q < kBlock / 64; ++q) {
+      const int64_t t = sh[q];
+      sh[q] = s;
+      s += t;
+    }
+    sh[kBlock / 64] = s;
+  }
+  __syncthreads();
+  const int64_t r = sh[wv] + x - v;
+  total = sh[kBlock / 64];
+  __syncthreads();
+  return r;
+}
+
+// Boundary nodes start as their own roots (operator nodes get their parent
+// words from the linking tiles).
+__global__ __launch_bounds__(kBlock) void k_init_bnodes(const int64_t* __restrict__ bn_bases,
+                                                         int nchain, int64_t nbn,
+                                                         const ChainDyn* __restrict__ dyn,
+                                                         int64_t* __restrict__ parent,
+                                                         const uint32_t* __restrict__ flags) {
+  if (*flags) return;
+  for (int64_t i = xcd_block() * kBlock + threadIdx.x; i < nbn;
+       i += static_cast<int64_t>(gridDim.x) * kBlock) {
+    const int c = chain_of(bn_bases, nchain, i);
+    const int64_t g = dyn[c].node_base + (i - bn_bases[c]);
     parent[g] = g;
+  }
 }
 
 // ---------------------------------------------------------------------------
 // Union-find, lock-free: roots are hooked to the smaller root with a CAS on
 // the parent word (parent[x] <= x always, so no cycle can form; leaves never
 // become roots again, which is what makes the finds safe without locks,
-// Sec. 3.2).  Finds halve the path as they go.
-__device__ inline int64_t uf_find(int64_t* parent, int64_t x) {
+// Sec. 3.2).  Finds halve the path as they go.  The same algorithm runs on
+// the LDS forest of a linking tile (lfind / lunion, 32-bit local indices)
+// and on the parent words in HBM (uf_find / uf_union).
+// Every word met on the way must be a node id below `n` (a finished loop's
+// negative word or anything else is an inconsistent graph): the find then
+// returns -1 and the union raises LC_FLAG_GRAPH instead of reading outside
+// the parent words.
+__device__ inline int64_t uf_find(int64_t* parent, int64_t x, int64_t n) {
+  if (x < 0 || x >= n) return -1;
   int64_t p = parent[x];
   while (p != x) {
+    if (p < 0 || p >= n) return -1;
     const int64_t gp = parent[p];
-    if (gp != p) parent[x] = gp;  // path halving; gp is an ancestor of x
+    if (gp != p && gp >= 0 && gp < n) parent[x] = gp;  // path halving; gp is an ancestor of x
     x = p;
     p = gp;
   }
   return x;
 }
 
-__device__ inline void uf_union(int64_t* parent, int64_t a, int64_t b) {
-  a = uf_find(parent, a);
-  b = uf_find(parent, b);
+__device__ inline void uf_union(int64_t* parent, int64_t a, int64_t b, int64_t n, uint32_t* flags) {
+  a = uf_find(parent, a, n);
+  b = uf_find(parent, b, n);
   while (a != b) {
+    if (a < 0 || b < 0) {
+      atomicOr(flags, LC_FLAG_GRAPH);
+      return;
+    }
     if (a < b) {
       const int64_t t = a;
       a = b;
@@ -401,206 +460,490 @@ __device__ inline void uf_union(int64_t* parent, int64_t a, int64_t b) {
         atomicCAS(reinterpret_cast<unsigned long long*>(parent + a), static_cast<unsigned long long>(a),
                   static_cast<unsigned long long>(b));
     if (static_cast<int64_t>(old) == a) return;
-    a = uf_find(parent, static_cast<int64_t>(old));
-    b = uf_find(parent, b);
+    a = uf_find(parent, static_cast<int64_t>(old), n);
+    b = uf_find(parent, b, n);
   }
 }
 
-// Next event on subspin x after operator (t, b, q): the earliest operator on
-// any bond touching x that comes after it in (time, bond, index) order.
-// Returns a flat operator index or -1.
-__device__ inline int64_t next_event(const ChainDesc& D, const int64_t* __restrict__ opstart,
-                                     const uint64_t* __restrict__ optime, int64_t x, int64_t b,
-                                     uint64_t k, uint64_t t, int64_t q) {
-  int64_t best = -1, bestb = 0;
-  uint64_t bestt = 0;
-  const int nt = 2 * D.two_s;
-  const int64_t W = int64_t(1) << D.w;
-  for (int s = 0; s < nt; ++s) {
-    const int64_t bb = bond_touching(D, x, s);
-    const int64_t i0 = D.win_base + bb * W;
-    const int64_t bend = opstart[i0 + W];
-    int64_t cand;
-    if (bb == b) {
-      cand = (q + 1 < bend) ? q + 1 : -1;
-    } else {
-      int64_t idx = opstart[i0 + static_cast<int64_t>(k)];
-      const int64_t we = opstart[i0 + static_cast<int64_t>(k) + 1];
-      while (idx < we && precedes(optime[idx], bb, t, b)) ++idx;
-      cand = (idx < bend) ? idx : -1;
-    }
-    if (cand < 0) continue;
-    const uint64_t ct = optime[cand];
-    if (best < 0 || ct < bestt || (ct == bestt && (bb < bestb || (bb == bestb && cand < best)))) {
-      best = cand;
-      bestb = bb;
-      bestt = ct;
-    }
+__device__ inline uint32_t lfind(uint32_t* lp, uint32_t x) {
+  volatile uint32_t* v = lp;
+  uint32_t p = v[x];
+  while (p != x) {
+    const uint32_t gp = v[p];
+    if (gp != p) v[x] = gp;
+    x = p;
+    p = gp;
   }
-  return best;
+  return x;
 }
 
-// Earlier of two candidate events (index, time, bond) in (time, bond,
-// index) order; -1 marks no candidate.
-__device__ inline int64_t earlier(int64_t c1, uint64_t t1, int64_t b1, int64_t c2, uint64_t t2,
-                                  int64_t b2) {
-  if (c1 < 0) return c2;
-  if (c2 < 0) return c1;
-  if (t1 != t2) return t1 < t2 ? c1 : c2;
-  if (b1 != b2) return b1 < b2 ? c1 : c2;
-  return c1 < c2 ? c1 : c2;
+__device__ inline void lunion(uint32_t* lp, uint32_t a, uint32_t b) {
+  a = lfind(lp, a);
+  b = lfind(lp, b);
+  while (a != b) {
+    if (a < b) {
+      const uint32_t t = a;
+      a = b;
+      b = t;
+    }
+    const uint32_t old = atomicCAS(lp + a, a, b);
+    if (old == a) return;
+    a = lfind(lp, old);
+    b = lfind(lp, b);
+  }
 }
 
-// Leg linking (Sec. 2, loops as trees of world-line fragments): the upper
-// node of every operator joins, on each of its two subspins, the lower node
-// of the next event there, or the top node of that subspin after the last.
-// For S = 1/2 the next event on a site is the bond's own next operator or
-// the first operator of the neighbouring bond after it: one forward pointer
-// per neighbour walks that bond's operators as the window's operators
-// advance in time (a merge of three sorted lists).
-//
-// When the next event on both sites of operator q is the bond's own next
-// operator q+1, upper(q) and lower(q+1) are joined by both of their edges
-// and by nothing else: a closed loop of two nodes (nine loops in ten at low
-// temperature).  It is finished here without union-find: plain stores mark
-// it (kPairRoot at its smallest node upper(q), lower(q+1) -> upper(q)), and
-// its estimators (size 2, no boundary node, length 2 (t_{q+1} - t_q)) go to
-// the chain statistics; the root and accumulation kernels skip it.
-struct PairSums {
+// Loop length >> 32 from its per-loop sums: length = 2^64 tops
+// + 2 (2^32 shi + slo), with shi and slo the sums of +-hi32(t) and +-lo32(t)
+// over its operator nodes (lower nodes +t, upper nodes -t: each node ends or
+// starts two vertical segments) read as signed words; length < 2^96.
+__device__ inline uint64_t loop_len32(uint64_t tops, uint64_t shi_w, uint64_t slo_w) {
+  const int64_t shi = static_cast<int64_t>(shi_w), slo = static_cast<int64_t>(slo_w);
+  uint64_t llo = static_cast<uint64_t>(slo) << 1;
+  uint64_t lhi = static_cast<uint64_t>(slo >> 63);        // sign extension of 2 slo
+  const uint64_t hlo = static_cast<uint64_t>(shi) << 33;
+  const uint64_t hhi = static_cast<uint64_t>(shi >> 31);  // arithmetic: bits 31.. of shi
+  const uint64_t t1 = llo + hlo;
+  lhi = lhi + hhi + (t1 < llo ? 1u : 0u) + tops;
+  llo = t1;
+  return (llo >> 32) | (lhi << 32);
+}
+
+// Per-thread sums of the loops a thread finishes (flushed per lane when the
+// thread moves to another chain, per block at the end).
+struct LoopSums {
   int c = -1;
-  uint64_t n = 0, l2lo = 0, l2hi = 0;
+  uint64_t n = 0, s2lo = 0, s2hi = 0, l2lo = 0, l2hi = 0, mx = 0;
   __device__ void flush_lane(unsigned long long* stats, int nchain) {
-    if (c < 0 || n == 0) return;
+    if (c < 0) return;  // stat_apply skips zero words
     stat_apply(stats, nchain, c, ST_CLUSTERS, -1, FLUSH_ADD, n, 0);
-    stat_apply(stats, nchain, c, ST_SIZE2_LO, ST_SIZE2_HI, FLUSH_ADD, 4 * n, 0);
+    stat_apply(stats, nchain, c, ST_SIZE2_LO, ST_SIZE2_HI, FLUSH_ADD, s2lo, s2hi);
     stat_apply(stats, nchain, c, ST_LEN2_LO, ST_LEN2_HI, FLUSH_ADD, l2lo, l2hi);
-    stat_apply(stats, nchain, c, ST_MAXSIZE, -1, FLUSH_MAX, 2, 0);
-    n = l2lo = l2hi = 0;
+    stat_apply(stats, nchain, c, ST_MAXSIZE, -1, FLUSH_MAX, mx, 0);
+    n = s2lo = s2hi = l2lo = l2hi = mx = 0;
   }
   __device__ void at(int cn, unsigned long long* stats, int nchain) {
     if (cn == c) return;
     flush_lane(stats, nchain);
     c = cn;
   }
-  __device__ void add(uint64_t dt) {
-    n += 1;
-    const uint64_t l32 = dt >> 31;  // (2 dt) >> 32
-    const u128p q = mul64x64(l32, l32);
-    l2lo += q.lo;
-    l2hi += q.hi + (l2lo < q.lo ? 1u : 0u);
+  // count = false: the loop was counted elsewhere (its root was numbered)
+  __device__ void add(uint64_t size, uint64_t len32, bool count = true) {
+    n += count ? 1 : 0;
+    const u128p a = mul64x64(size, size);
+    s2lo += a.lo;
+    s2hi += a.hi + (s2lo < a.lo ? 1u : 0u);
+    const u128p b = mul64x64(len32, len32);
+    l2lo += b.lo;
+    l2hi += b.hi + (l2lo < b.lo ? 1u : 0u);
+    mx = size > mx ? size : mx;
   }
   // convergent: every thread of the block must call it
   __device__ void flush(unsigned long long* stats, int nchain) {
     block_flush(stats, nchain, c, ST_CLUSTERS, -1, FLUSH_ADD, n, 0);
-    block_flush(stats, nchain, c, ST_SIZE2_LO, ST_SIZE2_HI, FLUSH_ADD, 4 * n, 0);
+    block_flush(stats, nchain, c, ST_SIZE2_LO, ST_SIZE2_HI, FLUSH_ADD, s2lo, s2hi);
     block_flush(stats, nchain, c, ST_LEN2_LO, ST_LEN2_HI, FLUSH_ADD, l2lo, l2hi);
-    block_flush(stats, nchain, c, ST_MAXSIZE, -1, FLUSH_MAX, n ? 2 : 0, 0);
+    block_flush(stats, nchain, c, ST_MAXSIZE, -1, FLUSH_MAX, mx, 0);
   }
 };
 
-__global__ __launch_bounds__(kBlock) void k_link_ops(
-    const ChainDesc* __restrict__ descs, const int64_t* __restrict__ win_bases, int nchain,
-    int64_t nwin, const ChainDyn* __restrict__ dyn, const int64_t* __restrict__ opstart,
-    const uint64_t* __restrict__ optime, int64_t* __restrict__ parent,
-    unsigned long long* __restrict__ stats, const uint32_t* __restrict__ flags) {
-  if (*flags) return;
-  PairSums pairs;
-  for (int64_t i = xcd_block() * kBlock + threadIdx.x; i < nwin;
-       i += static_cast<int64_t>(gridDim.x) * kBlock) {
-    const int c = chain_of(win_bases, nchain, i);
-    const ChainDesc& D = descs[c];
-    const ChainDyn dy = dyn[c];
-    const int64_t li = i - D.win_base;
-    const int64_t b = li >> D.w;
-    const uint64_t k = static_cast<uint64_t>(li & ((int64_t(1) << D.w) - 1));
-    const int64_t xs[2] = {bond_x(D, b), bond_y(D, b)};
-    if (D.two_s == 1) {
-      const int64_t W = int64_t(1) << D.w;
-      const int64_t bl = b == 0 ? D.L - 1 : b - 1, br = b + 1 == D.L ? 0 : b + 1;
-      const int64_t il = D.win_base + bl * W, ir = D.win_base + br * W;
-      const int64_t el = opstart[il + k + 1], er = opstart[ir + k + 1];  // window ends
-      const int64_t lend = opstart[il + W], rend = opstart[ir + W];      // bond ends
-      const int64_t bend = opstart[D.win_base + b * W + W];
-      int64_t pl = opstart[il + k], pr = opstart[ir + k];
-      uint64_t tl = pl < lend ? optime[pl] : 0, tr = pr < rend ? optime[pr] : 0;
-      const int64_t qe = opstart[i + 1];
-      for (int64_t q = opstart[i]; q < qe; ++q) {
-        const uint64_t t = optime[q];
-        while (pl < el && precedes(tl, bl, t, b)) {
-          ++pl;
-          tl = pl < lend ? optime[pl] : 0;
-        }
-        while (pr < er && precedes(tr, br, t, b)) {
-          ++pr;
-          tr = pr < rend ? optime[pr] : 0;
-        }
-        const int64_t own = q + 1 < bend ? q + 1 : -1;
-        const uint64_t tn = own >= 0 ? optime[own] : 0;
-        const int64_t nx = earlier(own, tn, b, pl < lend ? pl : -1, tl, bl);
-        const int64_t ny = earlier(own, tn, b, pr < rend ? pr : -1, tr, br);
-        const int64_t up = dy.node_base + D.nbn + 2 * (q - dy.op_base) + 1;
-        if (own >= 0 && nx == own && ny == own) {  // closed two-node loop
-          parent[up] = kPairRoot;
-          parent[up + 1] = up;
-          pairs.at(c, stats, nchain);
-          pairs.add(tn - t);
-          continue;
-        }
-        uf_union(parent, up, nx >= 0 ? dy.node_base + D.nbn + 2 * (nx - dy.op_base) : dy.node_base + xs[0]);
-        uf_union(parent, up, ny >= 0 ? dy.node_base + D.nbn + 2 * (ny - dy.op_base) : dy.node_base + xs[1]);
-      }
-      continue;
-    }
-    for (int64_t q = opstart[i]; q < opstart[i + 1]; ++q) {
-      const uint64_t t = optime[q];
-      const int64_t up = dy.node_base + D.nbn + 2 * (q - dy.op_base) + 1;
-      for (int e = 0; e < 2; ++e) {
-        const int64_t nx = next_event(D, opstart, optime, xs[e], b, k, t, q);
-        const int64_t top = (D.two_s == 1) ? xs[e] : D.n_sites + xs[e];
-        const int64_t to = (nx >= 0) ? dy.node_base + D.nbn + 2 * (nx - dy.op_base)
-                                     : dy.node_base + top;
-        uf_union(parent, up, to);
-      }
-    }
-  }
-  pairs.flush(stats, nchain);
+// ---------------------------------------------------------------------------
+// Leg linking and union-find by tiles (Sec. 2: loops as trees of world-line
+// fragments; Sec. 3.1: union-find inside a domain first, then a merge of the
+// fragments that leave it).  A tile is a range of spins times a range of
+// time windows of one chain.  It owns the operators on the bonds that start
+// at its spins (bond ((2S j) + a) 2S + c belongs to spin j) in its windows:
+// at most LC_TILE_OPS operators, whose two nodes each get a 32-bit local
+// index in LDS (lower 2l, upper 2l + 1 for local operator l, bond-major).
+//
+// Each thread walks one (subspin, window) of the tile: a merge of the
+// time-ordered operator lists of the 2 2S bonds touching the subspin, in
+// (time, bond) order, gives the events on the subspin; consecutive events
+// are joined upper -> lower, the first event of the subspin to its bottom
+// boundary node and the last one to its top node (the walker whose window
+// holds that event emits the edge, so every edge is emitted once).  An edge
+// whose two ends are local nodes is a local union in LDS; any other edge is
+// staged as a cross edge for the global union-find.
+//
+// After the local unions, the tile knows for every local component its
+// smallest node (rep), its size, and whether it is open (a node with fewer
+// than two local edges: the loop continues outside the tile).  A closed
+// component is a whole loop: the tile finishes it -- loop count, size^2,
+// length^2 into the chain statistics, its rep gets kClosedRoot -- without
+// any global work (closed two-node loops directly from the two times, larger
+// ones through an LDS accumulator slot).  An open component is a fragment:
+// its rep, size and length sums go to the fragment list, which is all the
+// later phases see of it.  Every node's parent word is written once,
+// coalesced: its rep (a rep of an open component points to itself).
+constexpr int64_t kClosedRoot = INT64_MIN;  // below every loop code -1 - index
+constexpr int kTileOps = LC_TILE_OPS;
+constexpr int kTileNodes = 2 * kTileOps;
+constexpr int kTileBonds = LC_TILE_BONDS;
+constexpr int kTileSlots = 256;
+constexpr int kTileCross = 512;
+static_assert(LC_TILE_THREADS == kBlock, "one (subspin, window) walker per thread");
+
+// aux word of a local node
+constexpr uint32_t kAuxSize = 0x1FFFu;   // bits 0..12: nodes of the component (at its rep)
+constexpr int kAuxSlotShift = 13;        // bits 13..22: accumulator slot + 1 (at its rep)
+constexpr uint32_t kAuxSlotMask = 0x3FFu;
+constexpr int kAuxDegShift = 24;         // bits 24..25: edges of the node inside the tile
+constexpr uint32_t kAuxOpen = 1u << 31;  // the component leaves the tile (at its rep)
+static_assert(kTileNodes <= static_cast<int>(kAuxSize), "component size field");
+static_assert(kTileSlots < static_cast<int>(kAuxSlotMask), "slot field");
+
+struct TileLds {
+  uint32_t lpar[kTileNodes];         // local forest
+  uint32_t aux[kTileNodes];
+  int64_t slot_hi[kTileSlots], slot_lo[kTileSlots];
+  uint32_t slot_rep[kTileSlots];
+  uint32_t tpre[kTileBonds + 1];     // first local operator of each owned bond
+  int64_t tos[kTileBonds];           // first (flat) operator of each owned bond in the tile
+  int64_t xsrc[kTileCross], xdst[kTileCross];
+  int64_t scan[kWaves + 1];
+  int64_t base[2];                   // reserved positions: cross edges, fragments
+  int cnt[4];                        // staged cross edges, slots, open slots, fragment cursor
+  uint32_t fl;
+};
+
+// Local operator index of flat operator e on bond bb, or -1 if the tile does
+// not own it.
+__device__ inline int tile_local(const TileLds& S, int64_t B0, int nbt, int64_t bb, int64_t e) {
+  const int64_t lb = bb - B0;
+  if (lb < 0 || lb >= nbt) return -1;
+  const int64_t off = e - S.tos[lb];
+  if (off < 0 || off >= static_cast<int64_t>(S.tpre[lb + 1] - S.tpre[lb])) return -1;
+  return static_cast<int>(S.tpre[lb] + off);
 }
 
-// Boundary nodes: bottom(x) joins the lower node of the first event on x;
-// an empty subspin joins bottom and top directly (S=1/2: one node, no edge).
-__global__ __launch_bounds__(kBlock) void k_link_sites(
-    const ChainDesc* __restrict__ descs, const int64_t* __restrict__ site_bases, int nchain,
-    int64_t nsites, const ChainDyn* __restrict__ dyn, const int64_t* __restrict__ opstart,
-    const uint64_t* __restrict__ optime, int64_t* __restrict__ parent,
-    const uint32_t* __restrict__ flags) {
-  if (*flags) return;
-  for (int64_t gi = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; gi < nsites;
-       gi += static_cast<int64_t>(gridDim.x) * kBlock) {
-    const int c = chain_of(site_bases, nchain, gi);
-    const ChainDesc& D = descs[c];
-    const ChainDyn dy = dyn[c];
-    const int64_t x = gi - D.site_base;
-    const int64_t W = int64_t(1) << D.w;
-    int64_t best = -1, bestb = 0;
-    uint64_t bestt = 0;
-    for (int s = 0; s < 2 * D.two_s; ++s) {
-      const int64_t bb = bond_touching(D, x, s);
-      const int64_t i0 = D.win_base + bb * W;
-      const int64_t f = opstart[i0];
-      if (f >= opstart[i0 + W]) continue;
-      const uint64_t ct = optime[f];
-      if (best < 0 || ct < bestt || (ct == bestt && bb < bestb)) {
-        best = f;
-        bestb = bb;
-        bestt = ct;
+// Flat operator of local operator lo (0 <= lo < tile operators): the last
+// owned bond whose first local operator is <= lo is non-empty and holds it.
+__device__ inline int64_t tile_op(const TileLds& S, int nbt, uint32_t lo) {
+  int a = 0, b = nbt - 1;
+  while (a < b) {
+    const int m = (a + b + 1) >> 1;
+    if (S.tpre[m] <= lo)
+      a = m;
+    else
+      b = m - 1;
+  }
+  return S.tos[a] + static_cast<int64_t>(lo - S.tpre[a]);
+}
+
+// An edge between nodes (gu, gv); lu, lv their local indices or -1.
+__device__ inline void tile_edge(TileLds& S, int64_t gu, int lu, int64_t gv, int lv) {
+  if (lu >= 0 && lv >= 0) {
+    atomicAdd(S.aux + lu, 1u << kAuxDegShift);
+    atomicAdd(S.aux + lv, 1u << kAuxDegShift);
+    lunion(S.lpar, static_cast<uint32_t>(lu), static_cast<uint32_t>(lv));
+  } else {
+    const int s = atomicAdd(&S.cnt[0], 1);
+    if (s < kTileCross) {
+      S.xsrc[s] = gu;
+      S.xdst[s] = gv;
+    }
+  }
+}
+
+// The walker of subspin x in window k (see above).  nb0: node id of the
+// lower node of flat operator 0 of the chain's numbering (lower(e) = nb0 + 2e).
+template <int TS>
+__device__ inline void tile_walk(TileLds& S, const ChainDesc& D, int64_t x, int64_t k, int64_t nb0,
+                                 int64_t node_base, int64_t B0, int nbt,
+                                 const int64_t* __restrict__ opstart,
+                                 const uint64_t* __restrict__ optime) {
+  constexpr int NB = 2 * TS;
+  const int64_t W = int64_t(1) << D.w;
+  const int64_t j = x / TS, a = x - j * TS;
+  const int64_t jl = (j == 0) ? D.L - 1 : j - 1;
+  int64_t bnd[NB], h[NB], e[NB];
+  uint64_t th[NB];
+  bool before = false, any = false;
+#pragma unroll
+  for (int s = 0; s < NB; ++s) {
+    bnd[s] = s < TS ? (jl * TS + s) * TS + a : (j * TS + a) * TS + (s - TS);
+    const int64_t i0 = D.win_base + bnd[s] * W;
+    h[s] = opstart[i0 + k];
+    e[s] = opstart[i0 + k + 1];
+    before = before || opstart[i0] < h[s];
+    th[s] = h[s] < e[s] ? optime[h[s]] : 0;
+    any = any || h[s] < e[s];
+  }
+  if (!any) {
+    if (TS > 1 && k == 0) {  // a subspin without events: bottom joins top
+      bool empty = true;
+#pragma unroll
+      for (int s = 0; s < NB; ++s) {
+        const int64_t i0 = D.win_base + bnd[s] * W;
+        empty = empty && opstart[i0 + W] == opstart[i0];
+      }
+      if (empty) tile_edge(S, node_base + x, -1, node_base + D.n_sites + x, -1);
+    }
+    return;
+  }
+  int64_t prev = -1;
+  int lprev = -1;
+  for (;;) {
+    int sm = -1;
+    uint64_t tm = 0;
+    int64_t bm = 0, cur = 0, em = 0;
+#pragma unroll
+    for (int s = 0; s < NB; ++s) {
+      if (h[s] < e[s] && (sm < 0 || th[s] < tm || (th[s] == tm && bnd[s] < bm))) {
+        sm = s;
+        tm = th[s];
+        bm = bnd[s];
+        cur = h[s];
+        em = e[s];
       }
     }
-    const int64_t bottom = dy.node_base + x;
-    if (best >= 0)
-      uf_union(parent, bottom, dy.node_base + D.nbn + 2 * (best - dy.op_base));
-    else if (D.two_s > 1)
-      uf_union(parent, bottom, dy.node_base + D.n_sites + x);
+    if (sm < 0) break;
+    const int lcur = tile_local(S, B0, nbt, bm, cur);
+    const int64_t gl = nb0 + 2 * cur;
+    if (prev < 0) {
+      if (!before) tile_edge(S, node_base + x, -1, gl, lcur >= 0 ? 2 * lcur : -1);
+    } else {
+      tile_edge(S, nb0 + 2 * prev + 1, lprev >= 0 ? 2 * lprev + 1 : -1, gl, lcur >= 0 ? 2 * lcur : -1);
+    }
+    prev = cur;
+    lprev = lcur;
+    const int64_t nh = cur + 1;
+    const uint64_t nt = nh < em ? optime[nh] : 0;
+#pragma unroll
+    for (int s = 0; s < NB; ++s) {
+      if (s == sm) {
+        h[s] = nh;
+        th[s] = nt;
+      }
+    }
   }
+  // the event after window k on this subspin: the first operator after the
+  // window on each touching bond, earliest in (time, bond) order
+  int64_t nxt = -1, bn = 0;
+  uint64_t tn = 0;
+#pragma unroll
+  for (int s = 0; s < NB; ++s) {
+    const int64_t i0 = D.win_base + bnd[s] * W;
+    const int64_t idx = e[s];
+    if (idx < opstart[i0 + W]) {
+      const uint64_t t = optime[idx];
+      if (nxt < 0 || t < tn || (t == tn && bnd[s] < bn)) {
+        nxt = idx;
+        tn = t;
+        bn = bnd[s];
+      }
+    }
+  }
+  const int64_t gu = nb0 + 2 * prev + 1;
+  const int lu = lprev >= 0 ? 2 * lprev + 1 : -1;
+  if (nxt >= 0) {
+    const int ln = tile_local(S, B0, nbt, bn, nxt);
+    tile_edge(S, gu, lu, nb0 + 2 * nxt, ln >= 0 ? 2 * ln : -1);
+  } else {
+    tile_edge(S, gu, lu, node_base + (TS == 1 ? x : D.n_sites + x), -1);
+  }
+}
+
+template <int TS>
+__global__ __launch_bounds__(kBlock) void k_link_tile(
+    const ChainDesc* __restrict__ descs, const ChainDyn* __restrict__ dyn, int nchain,
+    const int* __restrict__ grp_chain, const int64_t* __restrict__ grp_tile_base, int ngrp,
+    int64_t ntiles, const int64_t* __restrict__ opstart, const uint64_t* __restrict__ optime,
+    int64_t* __restrict__ parent, int64_t* __restrict__ xedge, int64_t xcap,
+    int64_t* __restrict__ frag, int64_t fcap, unsigned long long* __restrict__ dyncnt,
+    unsigned long long* __restrict__ stats, uint32_t* __restrict__ flags) {
+  __shared__ TileLds S;
+  const int tid = threadIdx.x;
+  // flags are read once per block: later kernels of this launch may set them
+  if (tid == 0) S.fl = *flags;
+  __syncthreads();
+  if (S.fl) return;
+  LoopSums sums;
+  for (int64_t t = xcd_block(); t < ntiles; t += gridDim.x) {
+    const int p = chain_of(grp_tile_base, ngrp, t);
+    const int c = grp_chain[p];
+    const ChainDesc& D = descs[c];
+    const ChainDyn dy = dyn[c];
+    const int64_t lt = t - grp_tile_base[p];
+    const int64_t W = int64_t(1) << D.w;
+    const int64_t tj = lt % D.ntj, tk = lt / D.ntj;
+    const int64_t j0 = tj * D.tile_j, k0 = tk * D.tile_k;
+    const int nj = static_cast<int>(min(static_cast<int64_t>(D.tile_j), D.L - j0));
+    const int nk = static_cast<int>(min(static_cast<int64_t>(D.tile_k), W - k0));
+    const int64_t B0 = j0 * TS * TS;
+    const int nbt = nj * TS * TS;
+    const int nthr = nj * TS * nk;
+    const int64_t nb0 = dy.node_base + D.nbn - 2 * dy.op_base;
+    // operators of the owned bonds in windows [k0, k0 + nk)
+    int64_t cnt = 0;
+    if (tid < nbt && tid < kTileBonds) {
+      const int64_t i0 = D.win_base + (B0 + tid) * W + k0;
+      const int64_t s = opstart[i0];
+      S.tos[tid] = s;
+      cnt = opstart[i0 + nk] - s;
+    }
+    int64_t total;
+    const int64_t ex = block_exclusive_scan(cnt, S.scan, total);
+    if (nbt > kTileBonds || nthr > kBlock || total > kTileOps) {  // block-uniform
+      if (tid == 0) atomicOr(flags, LC_FLAG_TILE);
+      break;
+    }
+    if (tid < nbt) S.tpre[tid] = static_cast<uint32_t>(ex);
+    if (tid == 0) {
+      S.tpre[nbt] = static_cast<uint32_t>(total);
+      S.cnt[0] = S.cnt[1] = S.cnt[2] = S.cnt[3] = 0;
+    }
+    const int nlo = static_cast<int>(total);
+    const int nn = 2 * nlo;
+    for (int u = tid; u < nn; u += kBlock) {
+      S.lpar[u] = static_cast<uint32_t>(u);
+      S.aux[u] = 0;
+    }
+    __syncthreads();
+    if (tid < nthr) {
+      const int xs = tid % (nj * TS);
+      const int kk = tid / (nj * TS);
+      tile_walk<TS>(S, D, j0 * TS + xs, k0 + kk, nb0, dy.node_base, B0, nbt, opstart, optime);
+    }
+    __syncthreads();
+    // full compression in two steps: every root is found by read-only walks
+    // first (a halving write landing after another thread's final write
+    // would leave a node below a non-root), then written
+    uint32_t roots[(kTileNodes + kBlock - 1) / kBlock];
+#pragma unroll
+    for (int i = 0; i < (kTileNodes + kBlock - 1) / kBlock; ++i) {
+      const int u = tid + i * kBlock;
+      uint32_t r = static_cast<uint32_t>(u);
+      if (u < nn)
+        while (S.lpar[r] != r) r = S.lpar[r];
+      roots[i] = r;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < (kTileNodes + kBlock - 1) / kBlock; ++i) {
+      const int u = tid + i * kBlock;
+      if (u < nn) S.lpar[u] = roots[i];
+    }
+    __syncthreads();
+    // component sizes; components with a node lacking a local edge are open
+    for (int u = tid; u < nn; u += kBlock) {
+      const uint32_t r = S.lpar[u];
+      const uint32_t deg = (S.aux[u] >> kAuxDegShift) & 3u;
+      atomicAdd(S.aux + r, 1u);
+      if (deg < 2) atomicOr(S.aux + r, kAuxOpen);
+    }
+    __syncthreads();
+    // closed two-node loops are finished from their two times; every other
+    // component gets an accumulator slot
+    sums.at(c, stats, nchain);
+    for (int u = tid; u < nn; u += kBlock) {
+      if (S.lpar[u] != static_cast<uint32_t>(u)) continue;
+      const uint32_t av = S.aux[u];
+      const bool open = (av & kAuxOpen) != 0;
+      if (!open && (av & kAuxSize) == 2 && (u & 1) && u + 1 < nn &&
+          S.lpar[u + 1] == static_cast<uint32_t>(u)) {
+        const int64_t q = tile_op(S, nbt, static_cast<uint32_t>(u >> 1));
+        const int64_t q1 = tile_op(S, nbt, static_cast<uint32_t>((u + 1) >> 1));
+        sums.add(2, (optime[q1] - optime[q]) >> 31);  // length 2 (t1 - t0), >> 32
+        continue;
+      }
+      const int s = atomicAdd(&S.cnt[1], 1);
+      if (s < kTileSlots) {
+        S.aux[u] = av | (static_cast<uint32_t>(s + 1) << kAuxSlotShift);
+        S.slot_rep[s] = static_cast<uint32_t>(u);
+        S.slot_hi[s] = 0;
+        S.slot_lo[s] = 0;
+        if (open) atomicAdd(&S.cnt[2], 1);
+      }
+    }
+    __syncthreads();
+    if (S.cnt[0] > kTileCross || S.cnt[1] > kTileSlots) {  // block-uniform
+      if (tid == 0) atomicOr(flags, LC_FLAG_TILE);
+      break;
+    }
+    // length sums of the slotted components: lower nodes +t, upper nodes -t
+    for (int lo = tid; lo < nlo; lo += kBlock) {
+      const uint64_t tq = optime[tile_op(S, nbt, static_cast<uint32_t>(lo))];
+      const uint64_t th = tq >> 32, tl = tq & 0xFFFFFFFFull;
+#pragma unroll
+      for (int hh = 0; hh < 2; ++hh) {
+        const uint32_t sl = (S.aux[S.lpar[2 * lo + hh]] >> kAuxSlotShift) & kAuxSlotMask;
+        if (!sl) continue;
+        atomicAdd(reinterpret_cast<unsigned long long*>(S.slot_hi + sl - 1),
+                  static_cast<unsigned long long>(hh ? 0 - th : th));
+        atomicAdd(reinterpret_cast<unsigned long long*>(S.slot_lo + sl - 1),
+                  static_cast<unsigned long long>(hh ? 0 - tl : tl));
+      }
+    }
+    if (tid == 0) {
+      const int nx = S.cnt[0], nf = S.cnt[2];
+      S.base[0] = nx ? static_cast<int64_t>(atomicAdd(dyncnt + 0, static_cast<unsigned long long>(nx))) : 0;
+      S.base[1] = nf ? static_cast<int64_t>(atomicAdd(dyncnt + 1, static_cast<unsigned long long>(nf))) : 0;
+      if (S.base[0] + nx > xcap) atomicOr(flags, LC_FLAG_XEDGE);
+      if (S.base[1] + nf > fcap) atomicOr(flags, LC_FLAG_FRAG);
+    }
+    __syncthreads();
+    const int nx = S.cnt[0];
+    for (int i = tid; i < nx; i += kBlock) {
+      const int64_t g = S.base[0] + i;
+      if (g < xcap) {
+        xedge[2 * g] = S.xsrc[i];
+        xedge[2 * g + 1] = S.xdst[i];
+      }
+    }
+    // closed components are finished here; open ones become fragments
+    const int ns = S.cnt[1];
+    for (int s = tid; s < ns; s += kBlock) {
+      const uint32_t u = S.slot_rep[s];
+      const uint32_t av = S.aux[u];
+      const uint64_t size = av & kAuxSize;
+      if (av & kAuxOpen) {
+        const int64_t f = S.base[1] + atomicAdd(&S.cnt[3], 1);
+        if (f < fcap) {
+          frag[4 * f + 0] = nb0 + 2 * tile_op(S, nbt, u >> 1) + (u & 1);
+          frag[4 * f + 1] = static_cast<int64_t>(size | (static_cast<uint64_t>(c) << 16));
+          frag[4 * f + 2] = S.slot_hi[s];
+          frag[4 * f + 3] = S.slot_lo[s];
+        }
+      } else {
+        sums.add(size, loop_len32(0, static_cast<uint64_t>(S.slot_hi[s]),
+                                  static_cast<uint64_t>(S.slot_lo[s])));
+      }
+    }
+    // parent words: the component's rep; a rep holds itself (open) or
+    // kClosedRoot (finished)
+    for (int lo = tid; lo < nlo; lo += kBlock) {
+      const int64_t q = tile_op(S, nbt, static_cast<uint32_t>(lo));
+#pragma unroll
+      for (int hh = 0; hh < 2; ++hh) {
+        const uint32_t u = static_cast<uint32_t>(2 * lo + hh);
+        const uint32_t r = S.lpar[u];
+        const int64_t g = nb0 + 2 * q + hh;
+        if (r == u)
+          parent[g] = (S.aux[u] & kAuxOpen) ? g : kClosedRoot;
+        else
+          parent[g] = nb0 + 2 * tile_op(S, nbt, r >> 1) + (r & 1);
+      }
+    }
+    __syncthreads();  // the LDS is reused by the next tile
+  }
+  sums.flush(stats, nchain);
+}
+
+// Edges between tiles: global unions of the nodes' components (through their
+// reps, which the tiles wrote as the nodes' parents).
+__global__ __launch_bounds__(kBlock) void k_link_cross(const int64_t* __restrict__ xedge,
+                                                        const unsigned long long* __restrict__ dyncnt,
+                                                        int64_t xcap, const int64_t* __restrict__ totals,
+                                                        int64_t* __restrict__ parent,
+                                                        uint32_t* __restrict__ flags) {
+  if (*flags) return;
+  const int64_t nx = static_cast<int64_t>(dyncnt[0]);
+  const int64_t n = nx < xcap ? nx : xcap;
+  const int64_t nodes = totals[1];
+  for (int64_t i = xcd_block() * kBlock + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kBlock)
+    uf_union(parent, xedge[2 * i], xedge[2 * i + 1], nodes, flags);
 }
 
 // Symmetrization of the 2S subspins of each spin (split-spin only): a
@@ -609,9 +952,10 @@ __global__ __launch_bounds__(kBlock) void k_link_sites(
 // bottom(j, pi(a)).  Fisher-Yates on the SYM stream of the spin.
 __global__ __launch_bounds__(kBlock) void k_symmetrize(
     const ChainDesc* __restrict__ descs, const int64_t* __restrict__ spin_bases, int nchain,
-    int64_t nspins, const ChainDyn* __restrict__ dyn, int64_t* __restrict__ parent,
-    uint32_t* __restrict__ flags) {
+    int64_t nspins, const ChainDyn* __restrict__ dyn, const int64_t* __restrict__ totals,
+    int64_t* __restrict__ parent, uint32_t* __restrict__ flags) {
   if (*flags) return;
+  const int64_t nodes = totals[1];
   for (int64_t gj = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; gj < nspins;
        gj += static_cast<int64_t>(gridDim.x) * kBlock) {
     const int c = chain_of(spin_bases, nchain, gj);
@@ -677,36 +1021,82 @@ __global__ __launch_bounds__(kBlock) void k_symmetrize(
     }
     for (int q = 0; q < nut; ++q) {
       perm[up_t[q]] = up_b[q];
-      uf_union(parent, dy.node_base + D.n_sites + up_t[q], dy.node_base + up_b[q]);
+      uf_union(parent, dy.node_base + D.n_sites + up_t[q], dy.node_base + up_b[q], nodes, flags);
     }
     for (int q = 0; q < ndt; ++q) {
       perm[dn_t[q]] = dn_b[q];
-      uf_union(parent, dy.node_base + D.n_sites + dn_t[q], dy.node_base + dn_b[q]);
+      uf_union(parent, dy.node_base + D.n_sites + dn_t[q], dy.node_base + dn_b[q], nodes, flags);
     }
   }
 }
 
 // Full path compression: parent[g] = root = smallest node of g's loop.
-// Roots (parent[g] == g) are counted per chunk of 4,096 nodes on the way
-// (each wave covers 64 consecutive nodes of one chunk): rcnt feeds the
-// numbering of the loops.
-__global__ __launch_bounds__(kBlock) void k_compress(const int64_t* __restrict__ totals,
-                                                      int64_t* __restrict__ parent,
-                                                      unsigned long long* __restrict__ rcnt,
-                                                      const uint32_t* __restrict__ flags) {
+
+
+// ---------------------------------------------------------------------------
+// After the cross-tile unions every open loop is a tree over its items: the
+// reps of its fragments and its boundary nodes (every other operator node
+// points at a rep, or has been halved to an ancestor rep or boundary node).
+// Item i < nf is fragment i; item nf + b is flat boundary node b.
+__device__ inline int64_t item_node(int64_t i, int64_t nf, const int64_t* __restrict__ frag,
+                                    const int64_t* __restrict__ bn_bases, int nchain,
+                                    const ChainDyn* __restrict__ dyn, int* chain) {
+  if (i < nf) {
+    *chain = static_cast<int>(static_cast<uint64_t>(frag[4 * i + 1]) >> 16);
+    return frag[4 * i];
+  }
+  const int64_t b = i - nf;
+  const int c = chain_of(bn_bases, nchain, b);
+  *chain = c;
+  return dyn[c].node_base + (b - bn_bases[c]);
+}
+
+__device__ inline int64_t items_count(const unsigned long long* __restrict__ dyncnt, int64_t fcap,
+                                      int64_t nbn, int64_t* nf) {
+  const int64_t f = static_cast<int64_t>(dyncnt[1]);
+  *nf = f < fcap ? f : fcap;
+  return *nf + nbn;
+}
+
+// Loop label of node g: its loop's smallest node.  A node whose parent word
+// is negative is that node (a loop code, or kClosedRoot); otherwise its
+// parent p is a rep, a boundary node or the root, and p's word is the root
+// (items are fully compressed) or negative (p is the root).
+__device__ inline int64_t node_label(const int64_t* __restrict__ parent, int64_t g) {
+  const int64_t p = parent[g];
+  if (p < 0) return g;
+  const int64_t pp = parent[p];
+  return pp >= 0 ? pp : p;
+}
+
+// Full path compression of the items: parent = root (smallest node of the
+// loop).  Roots are counted per chunk of 4,096 items (each wave covers 64
+// consecutive items of one chunk): rcnt feeds the numbering of the loops.
+constexpr int kRootPer = 16;                   // steps per chunk
+constexpr int kRootChunk = kBlock * kRootPer;  // items per chunk
+static_assert(kRootChunk == 4096, "roots are counted per 4,096 items");
+
+__global__ __launch_bounds__(kBlock) void k_compress_items(
+    const int64_t* __restrict__ frag, const unsigned long long* __restrict__ dyncnt, int64_t fcap,
+    const int64_t* __restrict__ bn_bases, int nchain, int64_t nbn, const ChainDyn* __restrict__ dyn,
+    int64_t* __restrict__ parent, unsigned long long* __restrict__ rcnt,
+    const uint32_t* __restrict__ flags) {
   if (*flags) return;
-  const int64_t n = totals[1];
+  int64_t nf;
+  const int64_t n = items_count(dyncnt, fcap, nbn, &nf);
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
   const int64_t iters = (n + stride - 1) / stride;
   for (int64_t it = 0; it < iters; ++it) {
-    const int64_t g = xcd_block() * kBlock + threadIdx.x + it * stride;
-    const int64_t p0 = g < n ? parent[g] : -1;
-    const unsigned long long roots = __ballot(p0 == g);
+    const int64_t i = xcd_block() * kBlock + threadIdx.x + it * stride;
+    int c = 0;
+    const int64_t g = i < n ? item_node(i, nf, frag, bn_bases, nchain, dyn, &c) : -1;
+    const int64_t p0 = g >= 0 ? parent[g] : -1;
+    const unsigned long long roots = __ballot(g >= 0 && p0 == g);
     if (lane_id() == 0 && roots)
-      atomicAdd(rcnt + (g >> 12), static_cast<unsigned long long>(__popcll(roots)));
-    if (g >= n) continue;
+      atomicAdd(rcnt + (i >> 12), static_cast<unsigned long long>(__popcll(roots)));
+    if (g < 0) continue;
     int64_t r = g, p = p0;
-    while (p != r && p >= 0) {  // a negative word marks a finished two-node loop
+    while (p != r && p >= 0) {
       r = p;
       p = parent[r];
     }
@@ -714,94 +1104,54 @@ __global__ __launch_bounds__(kBlock) void k_compress(const int64_t* __restrict__
   }
 }
 
-// Loop-flip bit of a chain-local label: bit (label mod 128) of the Philox
-// block (label / 128) of the FLIP stream of this sweep.
-__device__ inline uint32_t flip_bit(const ChainDesc& D, int64_t label) {
-  const uint64_t q = static_cast<uint64_t>(label) >> 7;
-  const uint32_t i = static_cast<uint32_t>(label & 127);
-  const u32x4 r = philox10(D.seed, static_cast<uint32_t>(q),
-                           (DOM_FLIP << 24) | static_cast<uint32_t>((q >> 32) & 0xFFFFFFu), 0u,
-                           D.sweep);
-  const uint32_t wsel = i >> 5;
-  const uint32_t word = wsel == 0 ? r.x : (wsel == 1 ? r.y : (wsel == 2 ? r.z : r.w));
-  return (word >> (i & 31)) & 1u;
-}
-
-constexpr int kScanItems = 16;
-constexpr int kScanTile = kBlock * kScanItems;
-
-__device__ inline int64_t block_exclusive_scan(int64_t v, int64_t* sh, int64_t& total) {
-  // wave inclusive scan
-  const int lane = lane_id(), wv = threadIdx.x >> 6;
-  int64_t x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int64_t y = __shfl_up(x, o);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) sh[wv] = x;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int64_t s = 0;
-    for (int q = 0; q < kBlock / 64; ++q) {
-      const int64_t t = sh[q];
-      sh[q] = s;
-      s += t;
-    }
-    sh[kBlock / 64] = s;
-  }
-  __syncthreads();
-  const int64_t r = sh[wv] + x - v;
-  total = sh[kBlock / 64];
-  __syncthreads();
-  return r;
-}
-
-// Roots get compact loop indices in node order: roots are counted per chunk
-// of kRootChunk nodes, the counts are scanned, and each chunk numbers its
-// roots from its offset (no shared counter).  A chunk is kRootPer steps of
-// kBlock consecutive nodes (coalesced loads, all issued before use); a
-// root's rank in its chunk is the roots of earlier steps, of earlier waves
-// in its step, and of lower lanes in its wave's ballot.
+// Roots get compact loop indices in item order: roots are counted per chunk
+// (k_compress_items), the counts are scanned, and each chunk numbers its
+// roots from its offset.  A chunk is kRootPer steps of kBlock consecutive
+// items; a root's rank in its chunk is the roots of earlier steps, of
+// earlier waves in its step, and of lower lanes in its wave's ballot.
+// The root's parent word becomes the code -1 - index; its record is cleared
+// and tagged with its chain.  A loop through a boundary node has a bottom
+// boundary node as its smallest node, so its boundary sums live in a
+// per-subspin record bacc[site], cleared here.
 constexpr int kAccWords = LC_ACC_WORDS;
-constexpr int kRootPer = 16;                      // steps per chunk
-constexpr int kRootChunk = kBlock * kRootPer;     // nodes per chunk (2^12, counted in k_compress)
-static_assert(kRootChunk == 4096, "k_compress counts roots per 4,096 nodes");
 
-// Roots: compact index (stored as the code -1 - index in the root's parent
-// word), cleared accumulators, loop count.  A loop
-// through a boundary node has a bottom boundary node as its smallest node
-// (boundary ids come first, and every top node is joined to a bottom one),
-// so its boundary sums live in a per-subspin record bacc[site], cleared here.
-__global__ __launch_bounds__(kBlock) void k_roots(
-    const ChainDesc* __restrict__ descs, const int64_t* __restrict__ node_bases, int nchain,
-    const int64_t* __restrict__ totals, int64_t* __restrict__ parent,
+__global__ __launch_bounds__(kBlock) void k_roots_items(
+    const ChainDesc* __restrict__ descs, const int64_t* __restrict__ frag,
+    const unsigned long long* __restrict__ dyncnt, int64_t fcap, const int64_t* __restrict__ bn_bases,
+    int nchain, int64_t nbn, const ChainDyn* __restrict__ dyn, int64_t* __restrict__ parent,
     unsigned long long* __restrict__ acc, unsigned long long* __restrict__ bacc, int64_t root_cap,
     int64_t nchunks, const int64_t* __restrict__ rbase, unsigned long long* __restrict__ stats,
     uint32_t* __restrict__ flags) {
   __shared__ int wsum[kRootPer][kWaves];
-  if (*flags) return;
-  if (rbase[nchunks] > root_cap) {
+  __shared__ uint32_t fl;
+  if (threadIdx.x == 0) fl = *flags;
+  __syncthreads();
+  if (fl) return;
+  if (rbase[nchunks] > root_cap) {  // the same for every thread
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flags, LC_FLAG_ROOTS);
     return;
   }
-  const int64_t n = totals[1];
+  int64_t nf;
+  const int64_t n = items_count(dyncnt, fcap, nbn, &nf);
   const int lane = lane_id(), wv = threadIdx.x >> 6;
   const unsigned long long below = (1ull << lane) - 1ull;
   constexpr int kIdx[1] = {ST_CLUSTERS};
   Partial<1> part;
-  for (int64_t ch = xcd_block(); ch < nchunks; ch += gridDim.x) {
-    const int64_t g0 = ch * kRootChunk + threadIdx.x;
-    int64_t pv[kRootPer];
+  for (int64_t ch = xcd_block(); ch * kRootChunk < n; ch += gridDim.x) {
+    const int64_t i0 = ch * kRootChunk + threadIdx.x;
+    int64_t gv[kRootPer], pv[kRootPer];
+    int cv[kRootPer];
 #pragma unroll
     for (int s = 0; s < kRootPer; ++s) {
-      const int64_t g = g0 + s * kBlock;
-      pv[s] = g < n ? parent[g] : -1;
+      const int64_t i = i0 + s * kBlock;
+      cv[s] = 0;
+      gv[s] = i < n ? item_node(i, nf, frag, bn_bases, nchain, dyn, &cv[s]) : -1;
+      pv[s] = gv[s] >= 0 ? parent[gv[s]] : -2;
     }
     unsigned long long m[kRootPer];
 #pragma unroll
     for (int s = 0; s < kRootPer; ++s) {
-      m[s] = __ballot(pv[s] == g0 + s * kBlock);
+      m[s] = __ballot(gv[s] >= 0 && pv[s] == gv[s]);
       if (lane == 0) wsum[s][wv] = __popcll(m[s]);
     }
     __syncthreads();
@@ -815,19 +1165,19 @@ __global__ __launch_bounds__(kBlock) void k_roots(
         woff += q < wv ? x : 0;
         tot += x;
       }
-      const int64_t g = g0 + s * kBlock;
-      if (pv[s] == g) {
-        const int64_t i = idx + woff + __popcll(m[s] & below);
-        const int c = chain_of(node_bases, nchain, g);
+      if (gv[s] >= 0 && pv[s] == gv[s]) {
+        const int64_t li = idx + woff + __popcll(m[s] & below);
+        const int c = cv[s];
         part.at(c, stats, nchain, kIdx);
         part.v[0] += 1;
         const ChainDesc& D = descs[c];
-        const int64_t v = g - node_bases[c];
-        parent[g] = -1 - i;
-        unsigned long long* a = acc + kAccWords * i;
+        const int64_t v = gv[s] - dyn[c].node_base;
+        parent[gv[s]] = -1 - li;
+        unsigned long long* a = acc + kAccWords * li;
         a[0] = 0;
         a[1] = 0;
         a[2] = 0;
+        a[3] = static_cast<unsigned long long>(c);
         if (v < D.n_sites) bacc[D.site_base + v] = 0;
       }
       idx += tot;
@@ -854,89 +1204,70 @@ __device__ inline void flush_carry(unsigned long long* acc, int64_t key, uint64_
   if (v2) atomicAdd(a + 2, static_cast<unsigned long long>(v2));
 }
 
-// Per-loop accumulators (before the flip), three 64-bit words per loop:
+// Per-loop records (before the flip) of the open loops, from their items:
 //   [0] nodes + (top nodes << 40)
 //   [1] sum of +-hi32(t), [2] sum of +-lo32(t)  over operator nodes: lower
 //       nodes count +t, upper nodes -t (two vertical segments end / start)
-// so the loop length is 2^64 tops + 2 (2^32 [1] + [2]) ticks.  Every word
-// takes plain additions without carries between words (the sums are exact
-// modulo 2^64 and their true values fit).  Bottom boundary nodes add
-// 1 + (spin << 32) to bacc of their loop's root subspin.
-__global__ __launch_bounds__(kBlock) void k_accum(
-    const ChainDesc* __restrict__ descs, const int64_t* __restrict__ node_bases, int nchain,
-    const ChainDyn* __restrict__ dyn, const int64_t* __restrict__ totals,
-    const int64_t* __restrict__ parent, const uint64_t* __restrict__ optime,
+// so the loop length is 2^64 tops + 2 (2^32 [1] + [2]) ticks.  A fragment
+// brings its node count and its sums; a boundary node one node (a top node
+// also 2^64 of length); every word takes plain additions (exact modulo 2^64,
+// the true values fit).  Bottom boundary nodes add 1 + (spin << 32) to bacc
+// of their loop's root subspin.
+__global__ __launch_bounds__(kBlock) void k_accum_items(
+    const ChainDesc* __restrict__ descs, const int64_t* __restrict__ frag,
+    const unsigned long long* __restrict__ dyncnt, int64_t fcap, const int64_t* __restrict__ bn_bases,
+    int nchain, int64_t nbn, const ChainDyn* __restrict__ dyn, const int64_t* __restrict__ parent,
     unsigned long long* __restrict__ acc, unsigned long long* __restrict__ bacc,
-    const uint32_t* __restrict__ flags) {
+    const int64_t* __restrict__ nloops, uint32_t* __restrict__ flags) {
   if (*flags) return;
-  const int64_t n = totals[1];
+  const int64_t nl = *nloops;
+  int64_t nf;
+  const int64_t n = items_count(dyncnt, fcap, nbn, &nf);
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
   const int64_t iters = (n + stride - 1) / stride;
-  // fields of the chain of the current node, reloaded only when the node
-  // leaves the chain's range [cbeg, cend)
-  int64_t cbeg = 0, cend = -1, op_base = 0, nbn = 0, n_sites = 0, site_base = 0;
-  int two_s = 1;
-  const uint8_t* s0p = nullptr;
   // wave carry: sums of one hot loop (wave-uniform), flushed once
   int64_t ck = -1;
   uint64_t cv0 = 0, cv1 = 0, cv2 = 0;
   for (int64_t it = 0; it < iters; ++it) {
-    const int64_t g = xcd_block() * kBlock + threadIdx.x + it * stride;
-    bool active = g < n;
+    const int64_t i = xcd_block() * kBlock + threadIdx.x + it * stride;
     int64_t r = -1;
     uint64_t w0 = 0, w1 = 0, w2 = 0;
-    if (active) {
-      if (g < cbeg || g >= cend) {
-        const int c = chain_of(node_bases, nchain, g);
-        const ChainDesc& D = descs[c];
-        const ChainDyn dy = dyn[c];
-        cbeg = dy.node_base;
-        cend = dy.node_base + dy.n_nodes;
-        op_base = dy.op_base;
-        nbn = D.nbn;
-        n_sites = D.n_sites;
-        site_base = D.site_base;
-        two_s = D.two_s;
-        s0p = D.s0[D.cur];
-      }
-      const int64_t v = g - cbeg;
+    if (i < n) {
+      int c = 0;
+      const int64_t g = item_node(i, nf, frag, bn_bases, nchain, dyn, &c);
       const int64_t p = parent[g];
       const int64_t code = p >= 0 ? parent[p] : p;
-      active = code != kPairRoot;  // two-node loops were finished while linking
-      if (active) {
-        r = -1 - code;
+      r = -1 - code;
+      if (code >= 0 || r >= nl) {  // not a numbered loop: inconsistent graph
+        atomicOr(flags, LC_FLAG_GRAPH);
+        r = -1;
+      } else if (i < nf) {
+        w0 = static_cast<uint64_t>(frag[4 * i + 1]) & 0xFFFFull;
+        w1 = static_cast<uint64_t>(frag[4 * i + 2]);
+        w2 = static_cast<uint64_t>(frag[4 * i + 3]);
+      } else {
+        const ChainDesc& D = descs[c];
+        const int64_t cb = dyn[c].node_base;
+        const int64_t v = g - cb;
+        const bool bottom = v < D.n_sites;
         w0 = 1;
-        if (v < nbn) {
-          const bool bottom = v < n_sites;
-          if ((two_s == 1) || !bottom) w0 += 1ull << 40;  // top node: + 2^64
-          const int64_t root = (p >= 0 ? p : g) - cbeg;
-          if (bottom && root < n_sites)  // always true: the root is a bottom node
-            atomicAdd(bacc + site_base + root,
-                      1ull + (static_cast<uint64_t>(2 * static_cast<int64_t>(s0p[v]) - 1) << 32));
-        } else {
-          const int64_t q = (v - nbn) >> 1;
-          const uint64_t t = optime[op_base + q];
-          const uint64_t th = t >> 32, tl = t & 0xFFFFFFFFull;
-          if (((v - nbn) & 1) == 0) {
-            w1 = th;
-            w2 = tl;
-          } else {
-            w1 = 0 - th;
-            w2 = 0 - tl;
-          }
-        }
+        if (D.two_s == 1 || !bottom) w0 += 1ull << 40;  // a top node: + 2^64
+        const int64_t root = (p >= 0 ? p : g) - cb;
+        if (bottom && root < D.n_sites)  // always true: the root is a bottom node
+          atomicAdd(bacc + D.site_base + root,
+                    1ull + (static_cast<uint64_t>(2 * static_cast<int64_t>(D.s0[D.cur][v]) - 1) << 32));
       }
     }
     // Reduce by loop within the wave: bitonic sort of one packed word per
     // lane, (loop << 6) | lane (loop indices are below 2^40), so only the key
     // moves through the 21 exchange stages; each lane then fetches the sums
-    // of the element it ended up with, a segmented scan adds equal loops, and
+    // of the item it ended up with, a segmented scan adds equal loops, and
     // the last lane of each run issues one set of atomics per distinct loop.
-    // Very large loops (high spin, low temperature) meet nearly every wave:
-    // the wave carries the sums of one such loop across its steps instead of
-    // adding them to the same record from every wave and step.
+    // Very large loops meet nearly every wave: the wave carries the sums of
+    // one such loop across its steps instead of adding them to the same
+    // record from every wave and step.
     const int lane = lane_id();
-    uint64_t sk = active ? ((static_cast<uint64_t>(r) << 6) | static_cast<uint64_t>(lane)) : ~0ull;
+    uint64_t sk = r >= 0 ? ((static_cast<uint64_t>(r) << 6) | static_cast<uint64_t>(lane)) : ~0ull;
 #pragma unroll
     for (int k = 2; k <= 64; k <<= 1) {
 #pragma unroll
@@ -949,8 +1280,7 @@ __global__ __launch_bounds__(kBlock) void k_accum(
     }
     const int src = static_cast<int>(sk & 63ull);
     const int64_t key = sk == ~0ull ? INT64_MAX : static_cast<int64_t>(sk >> 6);
-    // per-wave node and top counts fit 16 bits each
-    uint32_t c0 = static_cast<uint32_t>(__shfl(static_cast<uint32_t>((w0 & 0xFFFFull) | ((w0 >> 40) << 16)), src));
+    w0 = __shfl(w0, src);
     w1 = __shfl(w1, src);
     w2 = __shfl(w2, src);
     // runs of equal loops: head lanes from one ballot, segment id = heads so far
@@ -960,24 +1290,23 @@ __global__ __launch_bounds__(kBlock) void k_accum(
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
       const int qs = __shfl_up(seg, d);
-      const uint32_t q0 = __shfl_up(c0, d);
-      const uint64_t q1 = __shfl_up(w1, d), q2 = __shfl_up(w2, d);
+      const uint64_t q0 = __shfl_up(w0, d), q1 = __shfl_up(w1, d), q2 = __shfl_up(w2, d);
       if (lane >= d && qs == seg) {
-        c0 += q0;
+        w0 += q0;
         w1 += q1;
         w2 += q2;
       }
     }
     const bool last = lane == 63 || ((heads >> (lane + 1)) & 1ull);
     const bool seg_end = key != INT64_MAX && last;
-    const uint64_t v0 = static_cast<uint64_t>(c0 & 0xFFFFu) + (static_cast<uint64_t>(c0 >> 16) << 40);
     // the carried loop absorbs its segment without atomics
     bool absorbed = seg_end && key == ck;
     unsigned long long m = __ballot(absorbed);
     if (!m) {
-      // the carried loop is absent: a segment of at least 16 nodes takes over
+      // the carried loop is absent: a segment of at least 16 items takes over
       // the carry (the old carry is flushed); the largest such segment wins
-      const uint32_t cnt = seg_end ? (c0 & 0xFFFFu) : 0u;
+      const int seglen = seg_end ? (lane + 1 - (63 - __clzll(static_cast<long long>(heads & ((2ull << lane) - 1ull))))) : 0;
+      const uint32_t cnt = static_cast<uint32_t>(seglen);
       const uint32_t best = wave_max_u32((cnt << 6) | static_cast<uint32_t>(lane));
       if ((best >> 6) >= 16) {
         if (ck >= 0 && lane == 0) flush_carry(acc, ck, cv0, cv1, cv2);
@@ -988,14 +1317,14 @@ __global__ __launch_bounds__(kBlock) void k_accum(
       }
     }
     if (m) {
-      const int src = __ffsll(static_cast<long long>(m)) - 1;
-      cv0 += __shfl(v0, src);
-      cv1 += __shfl(w1, src);
-      cv2 += __shfl(w2, src);
+      const int sl = __ffsll(static_cast<long long>(m)) - 1;
+      cv0 += __shfl(w0, sl);
+      cv1 += __shfl(w1, sl);
+      cv2 += __shfl(w2, sl);
     }
     if (seg_end && !absorbed) {
       unsigned long long* a = acc + kAccWords * key;
-      atomicAdd(a + 0, static_cast<unsigned long long>(v0));
+      atomicAdd(a + 0, static_cast<unsigned long long>(w0));
       if (w1) atomicAdd(a + 1, static_cast<unsigned long long>(w1));
       if (w2) atomicAdd(a + 2, static_cast<unsigned long long>(w2));
     }
@@ -1003,71 +1332,24 @@ __global__ __launch_bounds__(kBlock) void k_accum(
   if (ck >= 0 && lane_id() == 0) flush_carry(acc, ck, cv0, cv1, cv2);
 }
 
-// First loop index of each chain: a chain's node 0 is always a root (the
-// smallest node of its loop) and loops are numbered in node order.
-__global__ void k_loop_bases(const int64_t* __restrict__ node_bases, int nchain,
-                             const int64_t* __restrict__ parent, int64_t* __restrict__ loop_bases,
-                             const uint32_t* __restrict__ flags) {
-  if (*flags) return;
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nchain; c += gridDim.x * blockDim.x)
-    loop_bases[c] = -1 - parent[node_bases[c]];
-}
-
-// Per-loop squares summed into the chain statistics (walks the compact loop
-// records; the chain of a loop is found from its index range).
+// Per-loop squares of the open loops summed into the chain statistics (the
+// chain of a record is its word 3).
 __global__ __launch_bounds__(kBlock) void k_cluster_sums(
-    const int64_t* __restrict__ loop_bases, int nchain, const int64_t* __restrict__ nloops,
-    int64_t root_cap, const unsigned long long* __restrict__ acc,
-    unsigned long long* __restrict__ stats, const uint32_t* __restrict__ flags) {
+    int nchain, const int64_t* __restrict__ nloops, int64_t root_cap,
+    const unsigned long long* __restrict__ acc, unsigned long long* __restrict__ stats,
+    const uint32_t* __restrict__ flags) {
   if (*flags) return;
   const int64_t n = *nloops < root_cap ? *nloops : root_cap;
-  int cc = -1;
-  int64_t cend = 0;  // first loop index past chain cc
-  uint64_t s2lo = 0, s2hi = 0, l2lo = 0, l2hi = 0, mx = 0;
-  auto flush_lane = [&]() {  // into this block's stripes
-    stat_apply(stats, nchain, cc, ST_SIZE2_LO, ST_SIZE2_HI, FLUSH_ADD, s2lo, s2hi);
-    stat_apply(stats, nchain, cc, ST_LEN2_LO, ST_LEN2_HI, FLUSH_ADD, l2lo, l2hi);
-    stat_apply(stats, nchain, cc, ST_MAXSIZE, -1, FLUSH_MAX, mx, 0);
-    s2lo = s2hi = l2lo = l2hi = mx = 0;
-  };
+  LoopSums sums;
   for (int64_t i = xcd_block() * kBlock + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * kBlock) {
-    if (cc < 0 || i >= cend) {
-      if (cc >= 0) flush_lane();
-      cc = chain_of(loop_bases, nchain, i);
-      cend = cc + 1 < nchain ? loop_bases[cc + 1] : n;
-    }
     const unsigned long long* a = acc + kAccWords * i;
+    sums.at(static_cast<int>(a[3]), stats, nchain);
     const uint64_t sz = a[0] & ((1ull << 40) - 1), tops = a[0] >> 40;
-    const u128p q2 = mul64x64(sz, sz);
-    s2lo += q2.lo;
-    s2hi += q2.hi + (s2lo < q2.lo ? 1u : 0u);
-    // len = 2^64 tops + 2^33 S_hi + 2 S_lo as a signed 128-bit sum, then >> 32
-    const int64_t shi = static_cast<int64_t>(a[1]), slo = static_cast<int64_t>(a[2]);
-    uint64_t llo = static_cast<uint64_t>(slo) << 1;
-    uint64_t lhi = static_cast<uint64_t>(slo >> 63);  // sign extension of 2 S_lo
-    const uint64_t hlo = static_cast<uint64_t>(shi) << 33;
-    const uint64_t hhi = static_cast<uint64_t>(shi >> 31);  // arithmetic: bits 31.. of shi
-    const uint64_t t1 = llo + hlo;
-    lhi = lhi + hhi + (t1 < llo ? 1u : 0u) + tops;
-    llo = t1;
-    const uint64_t l32 = (llo >> 32) | (lhi << 32);  // len >> 32, len < 2^96
-    const u128p l2 = mul64x64(l32, l32);
-    l2lo += l2.lo;
-    l2hi += l2.hi + (l2lo < l2.lo ? 1u : 0u);
-    mx = sz > mx ? sz : mx;
+    // the loop was counted when its root was numbered
+    sums.add(sz, loop_len32(tops, a[1], a[2]), false);
   }
-  block_flush(stats, nchain, cc, ST_SIZE2_LO, ST_SIZE2_HI, FLUSH_ADD, s2lo, s2hi);
-  block_flush(stats, nchain, cc, ST_LEN2_LO, ST_LEN2_HI, FLUSH_ADD, l2lo, l2hi);
-  block_flush(stats, nchain, cc, ST_MAXSIZE, -1, FLUSH_MAX, mx, 0);
-}
-
-// Flip bit of the loop through node g, from its root (the loop's smallest
-// node): after compression a non-root holds its root, a root a negative code.
-__device__ inline uint32_t node_flip(const ChainDesc& D, int64_t node_base,
-                                     const int64_t* __restrict__ parent, int64_t g) {
-  const int64_t p = parent[g];
-  return flip_bit(D, (p >= 0 ? p : g) - node_base);
+  sums.flush(stats, nchain);
 }
 
 // Cluster flip (step 7): the type of an operator changes when exactly one of
@@ -1075,8 +1357,8 @@ __device__ inline uint32_t node_flip(const ChainDesc& D, int64_t node_base,
 __global__ __launch_bounds__(kBlock) void k_flip_ops(
     const ChainDesc* __restrict__ descs, const int64_t* __restrict__ win_bases, int nchain,
     int64_t nwin, const ChainDyn* __restrict__ dyn, const int64_t* __restrict__ opstart,
-    const int64_t* __restrict__ parent, uint8_t* __restrict__ optype, int64_t* __restrict__ kcnt, unsigned long long* __restrict__ stats,
-    const uint32_t* __restrict__ flags) {
+    const int64_t* __restrict__ parent, uint8_t* __restrict__ optype, int64_t* __restrict__ kcnt,
+    unsigned long long* __restrict__ stats, const uint32_t* __restrict__ flags) {
   if (*flags) return;
   constexpr int kIdx[1] = {ST_KEPT_OUT};
   Partial<1> part;
@@ -1086,12 +1368,14 @@ __global__ __launch_bounds__(kBlock) void k_flip_ops(
     part.at(c, stats, nchain, kIdx);
     const ChainDesc& D = descs[c];
     const ChainDyn dy = dyn[c];
+    const int64_t nb0 = dy.node_base + D.nbn - 2 * dy.op_base;
     uint64_t kept = 0;
     for (int64_t q = opstart[i]; q < opstart[i + 1]; ++q) {
-      const int64_t lo = dy.node_base + D.nbn + 2 * (q - dy.op_base);
+      const int64_t lo = nb0 + 2 * q;
       const uint8_t v = optype[q];
-      const uint8_t ty = static_cast<uint8_t>((v & 1) ^ node_flip(D, dy.node_base, parent, lo) ^
-                                              node_flip(D, dy.node_base, parent, lo + 1));
+      const uint8_t ty = static_cast<uint8_t>(
+          (v & 1) ^ flip_bit(D, node_label(parent, lo) - dy.node_base) ^
+          flip_bit(D, node_label(parent, lo + 1) - dy.node_base));
       optype[q] = static_cast<uint8_t>(ty | (v & 2));
       kept += ty;
     }
@@ -1294,6 +1578,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(int64_t* __restrict__ a, 
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) a[n] = carry;
 }
 
+
 }  // namespace lc
 
 // ---------------------------------------------------------------------------
@@ -1320,6 +1605,14 @@ hipError_t lc_launch_scan(int64_t* a, int64_t n, int64_t* bsum, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int TS>
+static void launch_tiles(const LcSweepArgs& A, const LcTileGroup& g, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((k_link_tile<TS>), dim3(grid), dim3(kBlock), 0, s, A.descs, A.dyn, A.nchain,
+                     A.grp_chain + g.offset, A.grp_tile_base + g.offset, g.nchain, g.ntiles,
+                     A.opstart, A.optime, A.parent, A.xedge, A.xcap, A.frag, A.fcap, A.dyncnt,
+                     reinterpret_cast<unsigned long long*>(A.stats), A.flags);
+}
+
 hipError_t lc_launch_sweep(const LcSweepArgs& A, hipStream_t s) {
   const int G = A.grid_blocks;
   unsigned long long* st = reinterpret_cast<unsigned long long*>(A.stats);
@@ -1332,6 +1625,7 @@ hipError_t lc_launch_sweep(const LcSweepArgs& A, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(stat_words, 1024)), dim3(kBlock), 0, s, st, stat_words, 0ull);
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s,
                      reinterpret_cast<unsigned long long*>(A.flags), 1, 0ull);
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, A.dyncnt, 4, 0ull);
   // 1. count operators per window, 2. scan
   mark(LC_PH_GEN_COUNT);
   hipLaunchKernelGGL((k_gen<false>), dim3(grid_for(A.nwin, G)), dim3(kBlock), 0, s, A.descs,
@@ -1347,52 +1641,60 @@ hipError_t lc_launch_sweep(const LcSweepArgs& A, hipStream_t s) {
   hipLaunchKernelGGL((k_gen<true>), dim3(grid_for(A.nwin, G)), dim3(kBlock), 0, s, A.descs,
                      A.win_bases, A.nchain, A.nwin, A.opstart, A.accmask, A.optime, A.optype,
                      A.op_cap, st, A.flags);
-  // 4. loop graph and union-find
-  mark(LC_PH_INIT_PARENT);
-  hipLaunchKernelGGL(k_init_parent, dim3(G), dim3(kBlock), 0, s, A.totals, A.node_cap, A.parent);
-  mark(LC_PH_LINK_OPS);
-  hipLaunchKernelGGL(k_link_ops, dim3(grid_for(A.nwin, G)), dim3(kBlock), 0, s, A.descs,
-                     A.win_bases, A.nchain, A.nwin, A.dyn, A.opstart, A.optime, A.parent, st,
-                     A.flags);
-  mark(LC_PH_LINK_SITES);
-  hipLaunchKernelGGL(k_link_sites, dim3(grid_for(A.nsites, G)), dim3(kBlock), 0, s, A.descs,
-                     A.site_bases, A.nchain, A.nsites, A.dyn, A.opstart, A.optime, A.parent,
-                     A.flags);
+  // 4. loop graph and union-find: tiles, then the edges between them
+  mark(LC_PH_LINK_TILES);
+  hipLaunchKernelGGL(k_init_bnodes, dim3(grid_for(A.nbn, G)), dim3(kBlock), 0, s, A.bn_bases,
+                     A.nchain, A.nbn, A.dyn, A.parent, A.flags);
+  for (int gi = 0; gi < A.ngroups; ++gi) {
+    const LcTileGroup& g = A.groups[gi];
+    const int grid = static_cast<int>(g.ntiles < G ? (g.ntiles > 0 ? g.ntiles : 1) : G);
+    switch (g.two_s) {
+      case 1: launch_tiles<1>(A, g, grid, s); break;
+      case 2: launch_tiles<2>(A, g, grid, s); break;
+      case 3: launch_tiles<3>(A, g, grid, s); break;
+      case 4: launch_tiles<4>(A, g, grid, s); break;
+      case 5: launch_tiles<5>(A, g, grid, s); break;
+      case 6: launch_tiles<6>(A, g, grid, s); break;
+      case 7: launch_tiles<7>(A, g, grid, s); break;
+      case 8: launch_tiles<8>(A, g, grid, s); break;
+      default: break;
+    }
+  }
+  mark(LC_PH_LINK_CROSS);
+  hipLaunchKernelGGL(k_link_cross, dim3(G), dim3(kBlock), 0, s, A.xedge, A.dyncnt, A.xcap,
+                     A.totals, A.parent, A.flags);
   if (A.any_split)
     hipLaunchKernelGGL(k_symmetrize, dim3(grid_for(A.nspins, G)), dim3(kBlock), 0, s, A.descs,
-                       A.spin_bases, A.nchain, A.nspins, A.dyn, A.parent, A.flags);
+                       A.spin_bases, A.nchain, A.nspins, A.dyn, A.totals, A.parent, A.flags);
+  // 5. loops: compress the items (fragment reps, boundary nodes), number the roots
   mark(LC_PH_COMPRESS);
-  const int64_t nroot_chunks = (A.node_cap + kRootChunk - 1) / kRootChunk;
-  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(nroot_chunks + 1, 1024)), dim3(kBlock), 0, s,
-                     reinterpret_cast<unsigned long long*>(A.rcnt), nroot_chunks + 1, 0ull);
-  hipLaunchKernelGGL(k_compress, dim3(G), dim3(kBlock), 0, s, A.totals, A.parent,
+  const int64_t nchunks = (A.fcap + A.nbn + kRootChunk - 1) / kRootChunk;
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(nchunks + 1, 1024)), dim3(kBlock), 0, s,
+                     reinterpret_cast<unsigned long long*>(A.rcnt), nchunks + 1, 0ull);
+  hipLaunchKernelGGL(k_compress_items, dim3(G), dim3(kBlock), 0, s, A.frag, A.dyncnt, A.fcap,
+                     A.bn_bases, A.nchain, A.nbn, A.dyn, A.parent,
                      reinterpret_cast<unsigned long long*>(A.rcnt), A.flags);
-  // 5. flips and estimators
   mark(LC_PH_ROOTS);
-  {
-    const int64_t nch = nroot_chunks;
-    (void)lc_launch_scan(A.rcnt, nch, A.scan_tmp, s);
-    hipLaunchKernelGGL(k_roots, dim3(grid_for(nch, G)), dim3(kBlock), 0, s, A.descs, A.node_bases,
-                       A.nchain, A.totals, A.parent, A.acc, A.bacc, A.root_cap, nch,
-                       A.rcnt, st, A.flags);
-    hipLaunchKernelGGL(k_loop_bases, dim3(grid_for(A.nchain, 64)), dim3(kBlock), 0, s,
-                       A.node_bases, A.nchain, A.parent, A.loop_bases, A.flags);
-  }
+  (void)lc_launch_scan(A.rcnt, nchunks, A.scan_tmp, s);
+  hipLaunchKernelGGL(k_roots_items, dim3(grid_for(nchunks, G)), dim3(kBlock), 0, s, A.descs,
+                     A.frag, A.dyncnt, A.fcap, A.bn_bases, A.nchain, A.nbn, A.dyn, A.parent, A.acc,
+                     A.bacc, A.root_cap, nchunks, A.rcnt, st, A.flags);
+  // 6. estimators of the open loops, flips
   mark(LC_PH_ACCUM);
-  hipLaunchKernelGGL(k_accum, dim3(G), dim3(kBlock), 0, s, A.descs, A.node_bases, A.nchain, A.dyn,
-                     A.totals, A.parent, A.optime, A.acc, A.bacc, A.flags);
+  hipLaunchKernelGGL(k_accum_items, dim3(G), dim3(kBlock), 0, s, A.descs, A.frag, A.dyncnt, A.fcap,
+                     A.bn_bases, A.nchain, A.nbn, A.dyn, A.parent, A.acc, A.bacc, A.rcnt + nchunks,
+                     A.flags);
   mark(LC_PH_CLUSTER_SUMS);
   // few resident threads: each flushes its partial sums with atomics
-  hipLaunchKernelGGL(k_cluster_sums, dim3(G < 2048 ? G : 2048), dim3(kBlock), 0, s, A.loop_bases, A.nchain,
-                     A.rcnt + (A.node_cap + kRootChunk - 1) / kRootChunk, A.root_cap, A.acc, st,
-                     A.flags);
+  hipLaunchKernelGGL(k_cluster_sums, dim3(G < 2048 ? G : 2048), dim3(kBlock), 0, s, A.nchain,
+                     A.rcnt + nchunks, A.root_cap, A.acc, st, A.flags);
   mark(LC_PH_FLIP);
   hipLaunchKernelGGL(k_flip_ops, dim3(grid_for(A.nwin, G)), dim3(kBlock), 0, s, A.descs,
                      A.win_bases, A.nchain, A.nwin, A.dyn, A.opstart, A.parent, A.optype,
                      A.kflat, st, A.flags);
   hipLaunchKernelGGL(k_flip_sites, dim3(grid_for(A.nsites, G)), dim3(kBlock), 0, s, A.descs,
                      A.site_bases, A.nchain, A.nsites, A.dyn, A.parent, A.bacc, st, A.flags);
-  // 6. next world lines
+  // 7. next world lines
   mark(LC_PH_SCAN_KEPT);
   (void)lc_launch_scan(A.kflat, A.nwin, A.scan_tmp, s);
   mark(LC_PH_COMPACT);

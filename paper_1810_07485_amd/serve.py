@@ -25,32 +25,55 @@ from . import Batch, Chain, lc_footprint_parts
 
 
 class Admission:
-    """Footprint accounting: resident jobs' bytes must stay within budget."""
+    """Footprint accounting.  A resident job holds its world-line state; the
+    per-sweep scratch of all resident jobs lives in one arena of the batch,
+    which grows with headroom (up to a quarter more than the largest need it
+    has seen, plus 1/16) and does not shrink while the batch lives.  A job is
+    admitted only if the resident states, its own state and the larger of
+    the arena's current size and the grown scratch of all resident jobs with
+    it stay within the budget."""
+
+    GROWTH = 1.25 * 17 / 16
 
     def __init__(self, budget_bytes: int, max_resident: int = 512):
         self.budget = int(budget_bytes)
         self.max_resident = int(max_resident)
-        self.used = 0
+        self.state = 0
+        self.scratch = 0
         self.resident = 0
 
-    def fits_ever(self, nbytes: int) -> bool:
-        return nbytes <= self.budget
+    @property
+    def used(self) -> int:
+        return self.state + self.scratch
 
-    def try_admit(self, nbytes: int) -> bool:
-        if self.resident >= self.max_resident or self.used + nbytes > self.budget:
+    def need(self, state: int, scratch: int, arena_bytes: int = 0) -> float:
+        return self.state + state + max(float(arena_bytes), self.GROWTH * (self.scratch + scratch))
+
+    def fits_ever(self, state: int, scratch: int = 0) -> bool:
+        return state + self.GROWTH * scratch <= self.budget
+
+    def try_admit(self, state: int, scratch: int = 0, arena_bytes: int = 0) -> bool:
+        if self.resident >= self.max_resident or self.need(state, scratch, arena_bytes) > self.budget:
             return False
-        self.used += nbytes
+        self.state += state
+        self.scratch += scratch
         self.resident += 1
         return True
 
-    def release(self, nbytes: int):
-        self.used -= nbytes
+    def release(self, state: int, scratch: int = 0):
+        self.state -= state
+        self.scratch -= scratch
         self.resident -= 1
 
 
 def job_bytes(job) -> int:
     st, sc = lc_footprint_parts(job.L, job.S, job.beta)
     return st + sc
+
+
+def job_parts(job) -> tuple:
+    """(world-line state bytes, per-sweep scratch bytes) of a job."""
+    return lc_footprint_parts(job.L, job.S, job.beta)
 
 
 @dataclass
@@ -118,19 +141,23 @@ class Server:
                     waiting.append(pending.popleft())
                 # admission: first fit over the arrived jobs, oldest first
                 for job in list(waiting):
-                    nb = job_bytes(job)
-                    if not self.adm.fits_ever(nb):
+                    nb = job_parts(job)
+                    if not self.adm.fits_ever(*nb):
                         waiting.remove(job)
                         rejected.append(job)
                         if log:
-                            log(f"reject job {job.job_id}: {nb / 2**30:.1f} GiB")
+                            log(f"reject job {job.job_id}: {sum(nb) / 2**30:.1f} GiB")
                         continue
-                    if self.adm.try_admit(nb):
+                    if self.adm.try_admit(*nb, arena_bytes=batch.scratch_bytes()):
                         waiting.remove(job)
                         c = Chain(job.L, job.S, job.beta, job.seed, stream=self.stream)
                         batch.add(c)
                         resident[job.job_id] = [job, c, 0, nb, time.perf_counter() - t0, 0.0]
                 if not resident:
+                    if batch.scratch_bytes():
+                        # an empty batch gives its scratch arena back
+                        batch.close()
+                        batch = Batch(self.stream)
                     if pending:
                         time.sleep(max(0.0, min(0.05, pending[0].arrival - now)))
                     continue
@@ -153,7 +180,7 @@ class Server:
                         records.append(JobRecord(jid, job.arrival, rec[4], time.perf_counter() - t0,
                                                  rec[2], rec[5], c.measure(), st))
                         c.close()
-                        self.adm.release(rec[3])
+                        self.adm.release(*rec[3])
                         del resident[jid]
                         if log:
                             log(f"job {jid} done after {rec[2]} sweeps")

@@ -1,13 +1,17 @@
-"""Write per-sweep digests of the oracle at the medium single-chain size.
+"""Write per-sweep digests of the oracle for one chain.
 
-Calls only ``oracle/``.  For the S=1/2 chain L=65,536, beta=4,096, seed 1,
-started from its initial Neel state, it records for each of the first
-sweeps: every integer of the sweep statistics and SHA-256 digests of the
-world lines after the sweep (spins, per-bond offsets, kept times), of the
-operators of the sweep (bond, time, type before the flip) and of the loop
-labels.  The GPU test recomputes the same digests from the library.
+Calls only ``oracle/``.  For an S chain of L spins at inverse temperature
+beta with Philox seed `seed`, started from its initial Neel state, it
+records for each sweep: every integer of the sweep statistics and SHA-256
+digests of the world lines after the sweep (spins, per-bond offsets, kept
+times), of the operators of the sweep (bond, time, type before the flip),
+of the loop labels and (split spins) of the symmetrization permutation.  The
+GPU tests recompute the same digests from the library.  The file is
+rewritten after every sweep, so an interrupted run leaves the sweeps it
+finished.
 
-Run:  python tests/golden/make_digest_golden.py [n_sweeps]
+Run:  python tests/golden/make_digest_golden.py [n_sweeps] [L S beta seed [out.json]]
+      (default: the medium chain L=65,536, beta=4,096, seed 1, 3 sweeps)
 """
 import hashlib
 import json
@@ -22,8 +26,6 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 from oracle import oracle  # noqa: E402
 
-L, S, BETA, SEED = 65536, 0.5, 4096.0, 1
-
 
 def sha(*arrays) -> str:
     h = hashlib.sha256()
@@ -32,26 +34,49 @@ def sha(*arrays) -> str:
     return h.hexdigest()
 
 
+def default_name(L, S, beta, seed):
+    sp = "" if S == 0.5 else f"_S{S:g}"
+    sd = "" if seed == 1 else f"_seed{seed}"
+    return f"digest_L{L}{sp}_beta{beta:g}{sd}.json"
+
+
+def digest_record(ch, st):
+    s0, off, kt, sw = ch.export_state()
+    b, t, ty0 = ch.export_ops()
+    lab = ch.export_labels()
+    rec = dict(stats={k: int(v) for k, v in st.items()},
+               state=sha(s0, off, kt), ops=sha(b.astype(np.int64), t, ty0),
+               labels=sha(lab), next_sweep=int(sw))
+    if ch.two_s > 1:
+        rec["perm"] = sha(ch.export_perm())
+    return rec
+
+
+def write(out, path):
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(out, f, indent=1)
+    os.replace(tmp, path)
+
+
 def main():
-    n = int(sys.argv[1]) if len(sys.argv) > 1 else 3
-    ch = oracle.Chain(L, S, BETA, SEED)
-    w, mu, T = oracle.window_table(BETA)
-    out = dict(L=L, S=S, beta=BETA, seed=SEED, window_w=w, mu=mu,
+    a = sys.argv[1:]
+    n = int(a[0]) if a else 3
+    if len(a) >= 5:
+        L, S, beta, seed = int(a[1]), float(a[2]), float(a[3]), int(a[4])
+    else:
+        L, S, beta, seed = 65536, 0.5, 4096.0, 1
+    path = os.path.join(HERE, a[5] if len(a) >= 6 else default_name(L, S, beta, seed))
+    ch = oracle.Chain(L, S, beta, seed)
+    w, mu, T = oracle.window_table(beta)
+    out = dict(L=L, S=S, beta=beta, seed=seed, window_w=w, mu=mu,
                thresholds=[str(t) for t in T], sweeps=[])
     for s in range(n):
         t0 = time.time()
         st = ch.sweep()
-        s0, off, kt, sw = ch.export_state()
-        b, t, ty0 = ch.export_ops()
-        lab = ch.export_labels()
-        rec = dict(stats={k: int(v) for k, v in st.items()},
-                   state=sha(s0, off, kt), ops=sha(b.astype(np.int64), t, ty0),
-                   labels=sha(lab), next_sweep=int(sw))
-        out["sweeps"].append(rec)
-        print(s, f"{time.time() - t0:.0f}s", rec["stats"]["n_ops"], flush=True)
-        del b, t, ty0, lab
-    with open(os.path.join(HERE, "digest_L65536_beta4096.json"), "w") as f:
-        json.dump(out, f, indent=1)
+        out["sweeps"].append(digest_record(ch, st))
+        write(out, path)
+        print(s, f"{time.time() - t0:.0f}s", st["n_ops"], flush=True)
 
 
 if __name__ == "__main__":

@@ -84,3 +84,8 @@ def test_footprint_and_argument_checks(lib):
         lib.lc_footprint(16, 0.5, -1.0)
     with pytest.raises(lib.LcError):
         lib.lc_footprint(16, 4.5, 1.0)      # 2S > 8
+    with pytest.raises(lib.LcError):
+        lib.lc_footprint(1 << 32, 0.5, 1.0)   # L beyond 32-bit bond counters
+    with pytest.raises(lib.LcError):
+        lib.lc_footprint(1 << 27, 4.0, 1.0)   # (2S)^2 L = 2^33 sub-bonds
+    assert lib.lc_footprint((1 << 26) - 2, 4.0, 0.01) > 0

@@ -43,10 +43,22 @@ def test_pack_first_fit_decreasing():
 
 def test_admission_accounting():
     from paper_1810_07485_amd.serve import Admission
+    g = Admission.GROWTH
     a = Admission(100, max_resident=3)
     assert a.fits_ever(100) and not a.fits_ever(101)
+    assert a.fits_ever(0, 100 / g) and not a.fits_ever(1, 100 / g)
     assert a.try_admit(60) and not a.try_admit(50) and a.try_admit(40)
     assert a.used == 100 and a.resident == 2
     a.release(60)
     assert a.try_admit(30) and a.try_admit(1) and not a.try_admit(1)  # slot limit
     assert a.resident == 3 and a.used == 71
+    # scratch counts with the arena's growth headroom, and the arena's
+    # current size bounds it from below (it does not shrink)
+    b = Admission(100)
+    assert b.try_admit(10, 40)                  # 10 + 1.33 * 40 = 63
+    assert not b.try_admit(10, 25)              # 20 + 1.33 * 65 = 106 > 100
+    assert b.try_admit(5, 10)                   # 15 + 1.33 * 50 = 81
+    b.release(10, 40)
+    assert b.state == 5 and b.scratch == 10
+    assert not b.try_admit(10, 1, arena_bytes=90)  # 15 + max(90, ...) > 100
+    assert b.try_admit(10, 1, arena_bytes=60)

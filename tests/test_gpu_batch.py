@@ -168,3 +168,42 @@ def test_exports_refuse_scratch_overwritten_by_another_engine(lc):
         a.export_ops()
     a.update(1)
     assert len(a.export_ops()[0]) == a.last_sweep()["n_ops"]
+
+
+def test_batch_workload_members_match_oracle_digests(lc):
+    """All 512 chains of the batch workload run in footprint-packed batches;
+    a sample of members (tests/golden/batch_members.json, written by the
+    oracle alone) matches the oracle's digests after each of the first
+    sweeps: every integer of the sweep and the world lines."""
+    import hashlib
+    import json
+    import os
+
+    import torch
+    from paper_1810_07485_amd import batching, workloads
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "batch_members.json")
+    with open(path) as f:
+        gold = json.load(f)["members"]
+    assert len(gold) >= 30
+    inst = workloads.batch_instances()
+    chains = [lc.Chain(i.L, i.S, i.beta, i.seed) for i in inst]
+    runner = batching.BatchRunner(chains, 48 << 30)
+    assert len(runner.batches) > 1 or len(chains) == 512
+    nsw = min(len(m["sweeps"]) for m in gold)
+    for s in range(nsw):
+        runner.update(1)
+        for m in gold:
+            i = m["index"]
+            assert (inst[i].L, inst[i].beta, inst[i].seed) == (m["L"], m["beta"], m["seed"])
+            c = chains[i]
+            rec = m["sweeps"][s]
+            assert c.last_sweep() == rec["stats"], (i, s)
+            h = hashlib.sha256()
+            for a in c.export_state()[:3]:
+                h.update(np.ascontiguousarray(a).tobytes())
+            assert h.hexdigest() == rec["state"], (i, s)
+    runner.close()
+    for c in chains:
+        c.close()
+    torch.cuda.empty_cache()

@@ -7,7 +7,7 @@
   (tests/worldlines.py + scipy connected_components).
 - World-line invariants before and after the flip.
 - Physics: exact diagonalization, high-temperature limits, Bethe ansatz and
-  the paper's printed ratios (arXiv:1810.07485, Sec. 4.3).
+  the paper's printed ratios (arXiv:1810.07485, Sec. 4.4).
 """
 import json
 import math
@@ -295,7 +295,7 @@ def test_high_temperature_limits(orc):
 def test_bethe_ansatz_and_paper_ratios(orc):
     """Large L, low T: e -> 1/4 - ln 2 (Bethe ansatz); operators per unit
     space-time volume -> 0.693 and loops per unit volume -> 0.398
-    (Sec. 4.3: 5.64e11 operators and 3.24e11 loops at L beta = 8.14e11)."""
+    (Sec. 4.4: 5.64e11 operators and 3.24e11 loops at L beta = 8.14e11)."""
     L, beta = 512, 512.0
     st = _run(orc, L, 0.5, beta, 21, 60, 120)
     ser = _series(st, L, 0.5, beta)
@@ -307,3 +307,72 @@ def test_bethe_ansatz_and_paper_ratios(orc):
     # printed to three digits: 5.64e11 / 8.14e11 and 3.24e11 / 8.14e11
     assert abs(ops - 5.64 / 8.14) < 0.0015, ops
     assert abs(loops - 3.24 / 8.14) < 0.0015, loops
+
+
+# ------------------------------------------------------- loop-flip bits ----
+M32 = 0xFFFFFFFF
+
+
+def py_philox(seed: int, ctr) -> tuple:
+    """Philox4x32-10 written out in Python from its published definition
+    (Salmon et al., SC'11): per round, two 32x32 -> 64-bit products of
+    counter words 0 and 2; the new word 0 is hi(c2 M1) ^ c1 ^ k0, word 1 is
+    lo(c2 M1), word 2 is hi(c0 M0) ^ c3 ^ k1, word 3 is lo(c0 M0); the key
+    advances by the Weyl increments between rounds."""
+    M0, M1, W0, W1 = 0xD2511F53, 0xCD9E8D57, 0x9E3779B9, 0xBB67AE85
+    k0, k1 = seed & M32, (seed >> 32) & M32
+    c0, c1, c2, c3 = (int(x) & M32 for x in ctr)
+    for r in range(10):
+        if r:
+            k0, k1 = (k0 + W0) & M32, (k1 + W1) & M32
+        p0, p1 = M0 * c0, M1 * c2
+        c0, c1, c2, c3 = ((p1 >> 32) ^ c1 ^ k0) & M32, p1 & M32, ((p0 >> 32) ^ c3 ^ k1) & M32, p0 & M32
+    return c0, c1, c2, c3
+
+
+@pytest.mark.parametrize("ctr,key,out", KAT)
+def test_python_philox_known_answers(ctr, key, out):
+    assert py_philox(key[0] | (key[1] << 32), ctr) == out
+
+
+def py_flip_bit(seed: int, sweep: int, label: int) -> int:
+    """Loop-flip bit of a loop whose smallest node id is `label`: 128 bits
+    per Philox block of the FLIP domain (2 in the top byte of counter word
+    1); block q = label / 128 is addressed by counter words 0 (low 32 bits of
+    q) and 1 (bits 32..55 of q), word 3 holds the sweep; the bit is bit
+    (label mod 128) of the block read as words 0..3, least significant first."""
+    q, i = label >> 7, label & 127
+    words = py_philox(seed, (q & M32, (2 << 24) | ((q >> 32) & 0xFFFFFF), 0, sweep & M32))
+    return (words[i >> 5] >> (i & 31)) & 1
+
+
+def test_flip_bits_against_independent_philox(orc):
+    """The oracle's flip bit equals a bit recomputed from a separately
+    written Philox (pinned above by the known-answer vectors) for labels in
+    every word and bit position, block boundaries and labels beyond 2^39
+    (high block bits in counter word 1)."""
+    rng = np.random.default_rng(11)
+    labels = list(range(0, 520)) + [127, 128, 255, 256, (1 << 32) - 1, 1 << 32, (1 << 39) + 5,
+                                    (1 << 40) + 129, (1 << 50) + 77]
+    labels += [int(x) for x in rng.integers(0, 1 << 45, 300)]
+    for seed, sweep in ((1, 0), (0xDEADBEEFCAFEF00D, 7), (12345, 100000)):
+        for lab in labels:
+            assert orc.flip_bit(seed, sweep, lab) == py_flip_bit(seed, sweep, lab), (seed, sweep, lab)
+
+
+def test_flip_bits_fair_and_independent(orc):
+    """Each loop flips with probability 1/2 (Sec. 2, cluster flip), and the
+    bits of labels c, c+1 and c+128 (same word, neighbouring bit; same bit of
+    the next block) and of consecutive sweeps are independent: chi^2 tests
+    on the 2x2 tables of each pair."""
+    n = 20000
+    base = np.arange(0, 3 * n, 3, dtype=np.int64) * 129 + 17
+    f0 = np.array([orc.flip_bit(3, 5, int(c)) for c in base])
+    f1 = np.array([orc.flip_bit(3, 5, int(c) + 1) for c in base])
+    f128 = np.array([orc.flip_bit(3, 5, int(c) + 128) for c in base])
+    fs = np.array([orc.flip_bit(3, 6, int(c)) for c in base])
+    z = (f0.sum() - n / 2) / math.sqrt(n / 4)
+    assert abs(z) < 4
+    for other in (f1, f128, fs):
+        tab = np.array([[np.sum((f0 == a) & (other == b)) for b in (0, 1)] for a in (0, 1)])
+        assert stats.chi2_contingency(tab, correction=False)[1] > 1e-4, tab
