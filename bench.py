@@ -82,45 +82,55 @@ def device_ceilings(lc):
                    "read + written bytes per second, best of 3"}
 
 
-def phase_bytes(n_ops, n_nodes, n_clusters, n_win, n_sites, kept_in, kept_out):
-    """Algorithmic HBM bytes of each phase for one sweep (compulsory traffic:
-    every array element the phase must read or write, counted once).
+def phase_bytes(n_ops, n_bnodes, n_loops, n_win, n_sites, kept_in, kept_out, n_cross, n_frags):
+    """Algorithmic HBM bytes of each phase for one sweep: every array element
+    the phase must read or write, counted once (random accesses of the
+    global union-find at one 8-byte word each).
 
-    n_ops operators, n_nodes loop-graph nodes, n_win (bond, window) cells,
-    kept_in / kept_out off-diagonal operators before / after the sweep."""
-    N, V, Cl, W, S = n_ops, n_nodes, n_clusters, n_win, n_sites
+    n_ops operators, n_bnodes boundary nodes, n_loops loops recorded for the
+    global phases (roots among fragments and boundary nodes), n_win (bond,
+    window) cells, kept_in / kept_out off-diagonal operators before / after
+    the sweep, n_cross edges between linking tiles, n_frags open fragments."""
+    N, B, Cl, W, S = n_ops, n_bnodes, n_loops, n_win, n_sites
+    X, F = n_cross, n_frags
+    items = F + B
     return {
-        "gen_count": 8 * kept_in + 8 * W + S + 8 * W,
+        # kept times, window scans (read kstart, write opstart), acceptance masks, spins
+        "gen_count": 8 * kept_in + 16 * W + 4 * W + S,
         "scan_ops": 24 * W,
-        "gen_write": 8 * kept_in + 8 * W + 8 * W + 9 * N,
-        "init_parent": 8 * V,
-        # per-site time order read once, fused into linking (8 B per
-        # operator), and two edges per operator, each two finds and one
-        # CAS on 8-byte parent words (48 B per operator)
-        "link_ops": 56 * N,
-        "link_sites": 24 * S,
-        "compress": 16 * V,
-        # roots: read parent words to find the roots (8V), assign loop
-        # indices, clear the three record words (8C + 24C); the counts per
-        # chunk are taken inside compression
-        "roots": 8 * V + 32 * Cl,
-        # accum: parent word per node, time per operator, bottom spins;
-        # read-modify-write of 3 words per loop record
-        "accum": 8 * V + 8 * N + S + 48 * Cl,
-        "cluster_sums": 24 * Cl,
-        # flip: parent word of both nodes of every operator (flip bit from
-        # the root id), type read and written, kept count per window
-        "flip": 8 * V + 2 * N + 8 * W + 2 * S,
+        # kept times, window scans, masks, operator time and type written
+        "gen_write": 8 * kept_in + 16 * W + 4 * W + 9 * N,
+        # operator times and window starts read, both parent words written,
+        # boundary nodes initialised, cross edges (16 B) and fragments (32 B) out
+        "link_tiles": 8 * W + 8 * N + 16 * N + 8 * B + 16 * X + 32 * F,
+        # cross edges read; two finds and one CAS of 8-byte words per edge
+        "link_cross": 16 * X + 24 * X,
+        # item nodes (fragment records, parent words) read, parents written
+        "compress": 8 * F + 16 * items,
+        # item parents read, roots coded, records cleared (32 B)
+        "roots": 8 * F + 8 * items + 32 * Cl,
+        # fragment records, two parent words per item, record atomics
+        "accum": 32 * F + 16 * items + 24 * Cl,
+        "cluster_sums": 32 * Cl,
+        # two parent words per operator node pair (label lookups), type r/w,
+        # kept counts per window, spins r/w
+        "flip": 16 * N + 2 * N + 8 * W + 2 * S,
         "scan_kept": 24 * W,
         "compact": 24 * W + 9 * N + 8 * kept_out,
         "setup": 0,
     }
 
 
+# per-operator bytes of the path, from the survey's model of one sweep
+# (a1+a2 11.5, a3 fused into linking 8, a4+a5 16 + 48 + 32, a6+a7 28)
+SURVEY_BYTES_PER_OP = 11.5 + 8 + 16 + 48 + 32 + 28
+
+
 PHASE_KERNELS = {
-    "gen_count": ["k_gen<false>"], "gen_write": ["k_gen<true>"], "init_parent": ["k_init_parent"],
-    "link_ops": ["k_link_ops"], "compress": ["k_compress"], "roots": ["k_roots", "k_loop_bases"],
-    "accum": ["k_accum"], "cluster_sums": ["k_cluster_sums"], "flip": ["k_flip_ops", "k_flip_sites"],
+    "gen_count": ["k_gen<false>"], "gen_write": ["k_gen<true>"],
+    "link_tiles": ["k_init_bnodes", "k_link_tile<1>"], "link_cross": ["k_link_cross"],
+    "compress": ["k_compress_items"], "roots": ["k_roots_items"], "accum": ["k_accum_items"],
+    "cluster_sums": ["k_cluster_sums"], "flip": ["k_flip_ops", "k_flip_sites"],
     "compact": ["k_compact"],
 }
 TRAFFIC_FILES = {"medium": os.path.join(ROOT, "profiles", "hbm_traffic_L65536_beta4096.txt"),
@@ -396,8 +406,9 @@ def main():
     frag_total = (2 * m["mean_ops"] + nbn) * args.steps
     wtab = lc.lc_debug_window_table(w["beta"])
     n_win = chain.n_bonds << wtab[0]
-    pb = phase_bytes(m["mean_ops"], 2 * m["mean_ops"] + nbn, m["mean_clusters"], n_win,
-                     n_sites, last["n_kept_in"], last["n_kept_out"])
+    n_cross, n_frags = chain.work()
+    pb = phase_bytes(last["n_ops"], nbn, n_frags + nbn, n_win, n_sites, last["n_kept_in"],
+                     last["n_kept_out"], n_cross, n_frags)
     phase_ms = {k: v / nsw for k, v in prof.items()}
     dom = max(phase_ms, key=phase_ms.get)
     achieved = pb[dom] / (phase_ms[dom] * 1e-3) / 1e9
@@ -426,6 +437,11 @@ def main():
                      "bytes_per_launch": pb[dom], "avg_ms": phase_ms[dom],
                      "timing": f"HIP events around each phase on the library stream, "
                                f"{nsw} directly launched sweeps after the timed region"},
+        "path_roofline": {"model": "survey per-operator bytes of one sweep", "bytes_per_op":
+                          SURVEY_BYTES_PER_OP, "achieved": SURVEY_BYTES_PER_OP * ops_total / el / 1e9,
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": SURVEY_BYTES_PER_OP * ops_total / el / 1e9 / HBM_PEAK_GBS},
+        "work": {"cross_edges_per_op": n_cross / last["n_ops"], "fragments_per_op": n_frags / last["n_ops"]},
         "phase_ms": phase_ms,
         "profiled_ms_per_sweep": sum(phase_ms.values()),
         "observables": {"e": m["e"], "ops_per_L_beta": m["mean_ops"] / (w["L"] * w["beta"]),

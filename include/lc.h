@@ -266,6 +266,11 @@ int lc_probe_copy(int64_t bytes, int repeats, void *hip_stream, double *gb_per_s
  * w (2^w windows per bond), mu = beta / 2^(w+1) and thresholds
  * T[i] = floor(P(n <= i) 2^64) with T[*K - 1] = 2^64 - 1 (T holds 64). */
 int lc_debug_philox(uint64_t seed, const uint32_t ctr[4], uint32_t out[4]);
+/* Work counts of the most recent sweep of the chain's own engine (the chain
+ * run alone): loop-graph edges between linking tiles and open fragments the
+ * tiles left for the global union-find (the benchmark's byte model uses
+ * them).  LC_ESTATE before a sweep; synchronous device read. */
+int lc_debug_work(const lc_chain *c, int64_t *n_cross, int64_t *n_frags);
 int lc_debug_window_table(double beta, int *w, double *mu, uint64_t *T, int *K);
 
 #ifdef __cplusplus

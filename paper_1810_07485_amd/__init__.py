@@ -122,6 +122,7 @@ def load():
         "lc_probe_copy": ([C.c_int64, C.c_int, vp, C.POINTER(C.c_double)], C.c_int),
         "lc_debug_philox": ([C.c_uint64, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)], C.c_int),
         "lc_debug_window_table": ([C.c_double, pi, C.POINTER(C.c_double), pu64, pi], C.c_int),
+        "lc_debug_work": ([vp, p64, p64], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -330,6 +331,12 @@ class Chain:
     def profile(self) -> tuple:
         """(dict phase -> summed ms, sweeps) since profiling was switched on."""
         return _profile(load().lc_profile, self._h)
+
+    def work(self) -> tuple:
+        """(edges between linking tiles, open fragments) of the last sweep."""
+        x, f = C.c_int64(), C.c_int64()
+        _check(load().lc_debug_work(self._h, C.byref(x), C.byref(f)), "lc_debug_work")
+        return x.value, f.value
 
     def export_state(self):
         lib = load()

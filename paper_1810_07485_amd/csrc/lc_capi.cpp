@@ -860,6 +860,16 @@ int lc_debug_philox(uint64_t seed, const uint32_t ctr[4], uint32_t out[4]) {
   return LC_OK;
 }
 
+int lc_debug_work(const lc_chain* c, int64_t* n_cross, int64_t* n_frags) {
+  if (!c || !n_cross || !n_frags) return LC_EINVAL;
+  if (!c->own || !c->has_last || c->last_engine != c->own) return LC_ESTATE;
+  unsigned long long d[2] = {0, 0};
+  if (hipMemcpy(d, c->own->dyncnt.p, sizeof(d), hipMemcpyDeviceToHost) != hipSuccess) return LC_EDEVICE;
+  *n_cross = static_cast<int64_t>(d[0]);
+  *n_frags = static_cast<int64_t>(d[1]);
+  return LC_OK;
+}
+
 int lc_debug_window_table(double beta, int* w, double* mu, uint64_t* T, int* K) {
   if (!w || !mu || !T || !K) return LC_EINVAL;
   return window_rule(beta, w, mu, T, K);

@@ -579,22 +579,23 @@ constexpr int64_t kClosedRoot = INT64_MIN;  // below every loop code -1 - index
 constexpr int kTileOps = LC_TILE_OPS;
 constexpr int kTileNodes = 2 * kTileOps;
 constexpr int kTileBonds = LC_TILE_BONDS;
-constexpr int kTileSlots = 256;
-constexpr int kTileCross = 512;
+constexpr int kTileSlots = 512;
+constexpr int kTileCross = 1024;
 static_assert(LC_TILE_THREADS == kBlock, "one (subspin, window) walker per thread");
 
-// aux word of a local node
-constexpr uint32_t kAuxSize = 0x1FFFu;   // bits 0..12: nodes of the component (at its rep)
-constexpr int kAuxSlotShift = 13;        // bits 13..22: accumulator slot + 1 (at its rep)
-constexpr uint32_t kAuxSlotMask = 0x3FFu;
-constexpr int kAuxDegShift = 24;         // bits 24..25: edges of the node inside the tile
-constexpr uint32_t kAuxOpen = 1u << 31;  // the component leaves the tile (at its rep)
-static_assert(kTileNodes <= static_cast<int>(kAuxSize), "component size field");
-static_assert(kTileSlots < static_cast<int>(kAuxSlotMask), "slot field");
+// After the local compression the word of a non-rep node is its rep; the
+// word of a rep holds the component's fields:
+constexpr uint32_t kRepFlag = 1u << 31;   // this node is its component's rep
+constexpr uint32_t kRepOpen = 1u << 30;   // the component leaves the tile
+constexpr uint32_t kRepSize = 0x1FFFu;    // bits 0..12: nodes of the component
+constexpr int kRepSlotShift = 13;         // bits 13..22: accumulator slot + 1
+constexpr uint32_t kRepSlotMask = 0x3FFu;
+static_assert(kTileNodes <= static_cast<int>(kRepSize), "component size field");
+static_assert(kTileSlots < static_cast<int>(kRepSlotMask), "slot field");
 
 struct TileLds {
-  uint32_t lpar[kTileNodes];         // local forest
-  uint32_t aux[kTileNodes];
+  uint32_t lpar[kTileNodes];         // local forest, then reps and their fields
+  uint32_t deg[kTileNodes / 16];     // 2-bit counts of the edges of each node inside the tile
   int64_t slot_hi[kTileSlots], slot_lo[kTileSlots];
   uint32_t slot_rep[kTileSlots];
   uint32_t tpre[kTileBonds + 1];     // first local operator of each owned bond
@@ -633,8 +634,8 @@ __device__ inline int64_t tile_op(const TileLds& S, int nbt, uint32_t lo) {
 // An edge between nodes (gu, gv); lu, lv their local indices or -1.
 __device__ inline void tile_edge(TileLds& S, int64_t gu, int lu, int64_t gv, int lv) {
   if (lu >= 0 && lv >= 0) {
-    atomicAdd(S.aux + lu, 1u << kAuxDegShift);
-    atomicAdd(S.aux + lv, 1u << kAuxDegShift);
+    atomicAdd(S.deg + (lu >> 4), 1u << ((lu & 15) * 2));
+    atomicAdd(S.deg + (lv >> 4), 1u << ((lv & 15) * 2));
     lunion(S.lpar, static_cast<uint32_t>(lu), static_cast<uint32_t>(lv));
   } else {
     const int s = atomicAdd(&S.cnt[0], 1);
@@ -795,10 +796,8 @@ __global__ __launch_bounds__(kBlock) void k_link_tile(
     }
     const int nlo = static_cast<int>(total);
     const int nn = 2 * nlo;
-    for (int u = tid; u < nn; u += kBlock) {
-      S.lpar[u] = static_cast<uint32_t>(u);
-      S.aux[u] = 0;
-    }
+    for (int u = tid; u < nn; u += kBlock) S.lpar[u] = static_cast<uint32_t>(u);
+    for (int i = tid; i < kTileNodes / 16; i += kBlock) S.deg[i] = 0;
     __syncthreads();
     if (tid < nthr) {
       const int xs = tid % (nj * TS);
@@ -822,25 +821,29 @@ __global__ __launch_bounds__(kBlock) void k_link_tile(
 #pragma unroll
     for (int i = 0; i < (kTileNodes + kBlock - 1) / kBlock; ++i) {
       const int u = tid + i * kBlock;
-      if (u < nn) S.lpar[u] = roots[i];
+      if (u < nn) S.lpar[u] = roots[i] == static_cast<uint32_t>(u) ? kRepFlag : roots[i];
     }
     __syncthreads();
     // component sizes; components with a node lacking a local edge are open
+    auto rep_of = [&](int u) -> uint32_t {
+      const uint32_t w = S.lpar[u];
+      return (w & kRepFlag) ? static_cast<uint32_t>(u) : w;
+    };
     for (int u = tid; u < nn; u += kBlock) {
-      const uint32_t r = S.lpar[u];
-      const uint32_t deg = (S.aux[u] >> kAuxDegShift) & 3u;
-      atomicAdd(S.aux + r, 1u);
-      if (deg < 2) atomicOr(S.aux + r, kAuxOpen);
+      const uint32_t r = rep_of(u);
+      const uint32_t deg = (S.deg[u >> 4] >> ((u & 15) * 2)) & 3u;
+      atomicAdd(S.lpar + r, 1u);
+      if (deg < 2) atomicOr(S.lpar + r, kRepOpen);
     }
     __syncthreads();
     // closed two-node loops are finished from their two times; every other
     // component gets an accumulator slot
     sums.at(c, stats, nchain);
     for (int u = tid; u < nn; u += kBlock) {
-      if (S.lpar[u] != static_cast<uint32_t>(u)) continue;
-      const uint32_t av = S.aux[u];
-      const bool open = (av & kAuxOpen) != 0;
-      if (!open && (av & kAuxSize) == 2 && (u & 1) && u + 1 < nn &&
+      const uint32_t av = S.lpar[u];
+      if (!(av & kRepFlag)) continue;
+      const bool open = (av & kRepOpen) != 0;
+      if (!open && (av & kRepSize) == 2 && (u & 1) && u + 1 < nn &&
           S.lpar[u + 1] == static_cast<uint32_t>(u)) {
         const int64_t q = tile_op(S, nbt, static_cast<uint32_t>(u >> 1));
         const int64_t q1 = tile_op(S, nbt, static_cast<uint32_t>((u + 1) >> 1));
@@ -849,7 +852,7 @@ __global__ __launch_bounds__(kBlock) void k_link_tile(
       }
       const int s = atomicAdd(&S.cnt[1], 1);
       if (s < kTileSlots) {
-        S.aux[u] = av | (static_cast<uint32_t>(s + 1) << kAuxSlotShift);
+        S.lpar[u] = av | (static_cast<uint32_t>(s + 1) << kRepSlotShift);
         S.slot_rep[s] = static_cast<uint32_t>(u);
         S.slot_hi[s] = 0;
         S.slot_lo[s] = 0;
@@ -867,7 +870,7 @@ __global__ __launch_bounds__(kBlock) void k_link_tile(
       const uint64_t th = tq >> 32, tl = tq & 0xFFFFFFFFull;
 #pragma unroll
       for (int hh = 0; hh < 2; ++hh) {
-        const uint32_t sl = (S.aux[S.lpar[2 * lo + hh]] >> kAuxSlotShift) & kAuxSlotMask;
+        const uint32_t sl = (S.lpar[rep_of(2 * lo + hh)] >> kRepSlotShift) & kRepSlotMask;
         if (!sl) continue;
         atomicAdd(reinterpret_cast<unsigned long long*>(S.slot_hi + sl - 1),
                   static_cast<unsigned long long>(hh ? 0 - th : th));
@@ -895,9 +898,9 @@ __global__ __launch_bounds__(kBlock) void k_link_tile(
     const int ns = S.cnt[1];
     for (int s = tid; s < ns; s += kBlock) {
       const uint32_t u = S.slot_rep[s];
-      const uint32_t av = S.aux[u];
-      const uint64_t size = av & kAuxSize;
-      if (av & kAuxOpen) {
+      const uint32_t av = S.lpar[u];
+      const uint64_t size = av & kRepSize;
+      if (av & kRepOpen) {
         const int64_t f = S.base[1] + atomicAdd(&S.cnt[3], 1);
         if (f < fcap) {
           frag[4 * f + 0] = nb0 + 2 * tile_op(S, nbt, u >> 1) + (u & 1);
@@ -917,10 +920,10 @@ __global__ __launch_bounds__(kBlock) void k_link_tile(
 #pragma unroll
       for (int hh = 0; hh < 2; ++hh) {
         const uint32_t u = static_cast<uint32_t>(2 * lo + hh);
-        const uint32_t r = S.lpar[u];
+        const uint32_t r = rep_of(static_cast<int>(u));
         const int64_t g = nb0 + 2 * q + hh;
         if (r == u)
-          parent[g] = (S.aux[u] & kAuxOpen) ? g : kClosedRoot;
+          parent[g] = (S.lpar[u] & kRepOpen) ? g : kClosedRoot;
         else
           parent[g] = nb0 + 2 * tile_op(S, nbt, r >> 1) + (r & 1);
       }
