@@ -439,8 +439,9 @@ int ensure_scratch(Arena& A, int64_t ops, int64_t nodes, int64_t xe, int64_t fe,
 
 // Linking tile of a chain: spins x windows with at most LC_TILE_THREADS
 // (subspin, window) walkers and LC_TILE_BONDS owned bonds, sized for about
-// 1,500 operators (LC_TILE_OPS is the hard limit: a tile beyond it makes the
-// sweep replay with tiles half as large, tile_shrink).  S = 1/2 tiles are
+// 1,500 operators at S = 1/2 and 1,100 for split spins (LC_TILE_OPS and
+// LC_TILE_OPS_SPLIT are the hard limits: a tile beyond one makes the sweep
+// replay with tiles half as large, tile_shrink).  S = 1/2 tiles are
 // 4 windows tall: a site crosses a window boundary once, a tile side on
 // about half of its events.  Split-spin tiles are one window tall: 2S bonds
 // wide at each side, they need all the spins they can get.
@@ -452,7 +453,7 @@ void choose_tile(lc_chain* c) {
   // the bound (N_b/4 + L S(S+1)) / N_b otherwise
   const double rho = ts == 1 ? 0.72 : (ts + 1.0) / (2.0 * ts);
   const double per_spin_window = std::max(rho * ts * ts * win_tau, 1e-9);
-  const double target = 1500.0 / static_cast<double>(int64_t(1) << c->tile_shrink);
+  const double target = (ts == 1 ? 1500.0 : 1100.0) / static_cast<double>(int64_t(1) << c->tile_shrink);
   int64_t tk = std::min<int64_t>(W, ts == 1 ? 4 : 1);
   while (tk > 1 && per_spin_window * static_cast<double>(tk) > target) tk >>= 1;
   int64_t tj = static_cast<int64_t>(target / (per_spin_window * static_cast<double>(tk)));

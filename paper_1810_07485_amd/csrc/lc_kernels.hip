@@ -576,12 +576,21 @@ struct LoopSums {
 // later phases see of it.  Every node's parent word is written once,
 // coalesced: its rep (a rep of an open component points to itself).
 constexpr int64_t kClosedRoot = INT64_MIN;  // below every loop code -1 - index
-constexpr int kTileOps = LC_TILE_OPS;
-constexpr int kTileNodes = 2 * kTileOps;
 constexpr int kTileBonds = LC_TILE_BONDS;
-constexpr int kTileSlots = 512;
-constexpr int kTileCross = 1024;
 static_assert(LC_TILE_THREADS == kBlock, "one (subspin, window) walker per thread");
+static_assert(kTileBonds <= 256, "owned bonds are numbered in one byte");
+
+// LDS capacities of a tile, per spin length.  S = 1/2 tiles hold up to
+// LC_TILE_OPS operators; split-spin tiles hold fewer but, being narrow (2S
+// bonds of each subspin cross a tile side), more edges leaving the tile and
+// more components.
+template <int TS>
+struct TileCfg {
+  static constexpr int kOps = TS == 1 ? LC_TILE_OPS : LC_TILE_OPS_SPLIT;
+  static constexpr int kNodes = 2 * kOps;
+  static constexpr int kCross = TS == 1 ? 384 : 1024;
+  static constexpr int kSlots = TS == 1 ? 256 : 768;
+};
 
 // After the local compression the word of a non-rep node is its rep; the
 // word of a rep holds the component's fields:
@@ -590,17 +599,21 @@ constexpr uint32_t kRepOpen = 1u << 30;   // the component leaves the tile
 constexpr uint32_t kRepSize = 0x1FFFu;    // bits 0..12: nodes of the component
 constexpr int kRepSlotShift = 13;         // bits 13..22: accumulator slot + 1
 constexpr uint32_t kRepSlotMask = 0x3FFu;
-static_assert(kTileNodes <= static_cast<int>(kRepSize), "component size field");
-static_assert(kTileSlots < static_cast<int>(kRepSlotMask), "slot field");
 
+template <int TS>
 struct TileLds {
-  uint32_t lpar[kTileNodes];         // local forest, then reps and their fields
-  uint32_t deg[kTileNodes / 16];     // 2-bit counts of the edges of each node inside the tile
-  int64_t slot_hi[kTileSlots], slot_lo[kTileSlots];
-  uint32_t slot_rep[kTileSlots];
+  using C = TileCfg<TS>;
+  static_assert(C::kNodes <= static_cast<int>(kRepSize), "component size field");
+  static_assert(C::kSlots < static_cast<int>(kRepSlotMask), "slot field");
+  uint32_t lpar[C::kNodes];          // local forest, then reps and their fields
+  uint32_t deg[C::kNodes / 16];      // 2-bit counts of the edges of each node inside the tile
+  uint64_t ltime[C::kOps];           // times of the tile's operators
+  uint8_t lbond[C::kOps];            // owned bond (local index) of each tile operator
+  int64_t slot_hi[C::kSlots], slot_lo[C::kSlots];
+  uint32_t slot_rep[C::kSlots];
   uint32_t tpre[kTileBonds + 1];     // first local operator of each owned bond
   int64_t tos[kTileBonds];           // first (flat) operator of each owned bond in the tile
-  int64_t xsrc[kTileCross], xdst[kTileCross];
+  int64_t xsrc[C::kCross], xdst[C::kCross];
   int64_t scan[kWaves + 1];
   int64_t base[2];                   // reserved positions: cross edges, fragments
   int cnt[4];                        // staged cross edges, slots, open slots, fragment cursor
@@ -609,7 +622,8 @@ struct TileLds {
 
 // Local operator index of flat operator e on bond bb, or -1 if the tile does
 // not own it.
-__device__ inline int tile_local(const TileLds& S, int64_t B0, int nbt, int64_t bb, int64_t e) {
+template <class Lds>
+__device__ inline int tile_local(const Lds& S, int64_t B0, int nbt, int64_t bb, int64_t e) {
   const int64_t lb = bb - B0;
   if (lb < 0 || lb >= nbt) return -1;
   const int64_t off = e - S.tos[lb];
@@ -617,29 +631,23 @@ __device__ inline int tile_local(const TileLds& S, int64_t B0, int nbt, int64_t 
   return static_cast<int>(S.tpre[lb] + off);
 }
 
-// Flat operator of local operator lo (0 <= lo < tile operators): the last
-// owned bond whose first local operator is <= lo is non-empty and holds it.
-__device__ inline int64_t tile_op(const TileLds& S, int nbt, uint32_t lo) {
-  int a = 0, b = nbt - 1;
-  while (a < b) {
-    const int m = (a + b + 1) >> 1;
-    if (S.tpre[m] <= lo)
-      a = m;
-    else
-      b = m - 1;
-  }
-  return S.tos[a] + static_cast<int64_t>(lo - S.tpre[a]);
+// Flat operator of local operator lo.
+template <class Lds>
+__device__ inline int64_t tile_op(const Lds& S, uint32_t lo) {
+  const uint32_t lb = S.lbond[lo];
+  return S.tos[lb] + static_cast<int64_t>(lo - S.tpre[lb]);
 }
 
 // An edge between nodes (gu, gv); lu, lv their local indices or -1.
-__device__ inline void tile_edge(TileLds& S, int64_t gu, int lu, int64_t gv, int lv) {
+template <class Lds>
+__device__ inline void tile_edge(Lds& S, int64_t gu, int lu, int64_t gv, int lv) {
   if (lu >= 0 && lv >= 0) {
     atomicAdd(S.deg + (lu >> 4), 1u << ((lu & 15) * 2));
     atomicAdd(S.deg + (lv >> 4), 1u << ((lv & 15) * 2));
     lunion(S.lpar, static_cast<uint32_t>(lu), static_cast<uint32_t>(lv));
   } else {
     const int s = atomicAdd(&S.cnt[0], 1);
-    if (s < kTileCross) {
+    if (s < Lds::C::kCross) {
       S.xsrc[s] = gu;
       S.xdst[s] = gv;
     }
@@ -648,9 +656,10 @@ __device__ inline void tile_edge(TileLds& S, int64_t gu, int lu, int64_t gv, int
 
 // The walker of subspin x in window k (see above).  nb0: node id of the
 // lower node of flat operator 0 of the chain's numbering (lower(e) = nb0 + 2e).
+// Times of the tile's own operators come from LDS, others from HBM.
 template <int TS>
-__device__ inline void tile_walk(TileLds& S, const ChainDesc& D, int64_t x, int64_t k, int64_t nb0,
-                                 int64_t node_base, int64_t B0, int nbt,
+__device__ inline void tile_walk(TileLds<TS>& S, const ChainDesc& D, int64_t x, int64_t k,
+                                 int64_t nb0, int64_t node_base, int64_t B0, int nbt,
                                  const int64_t* __restrict__ opstart,
                                  const uint64_t* __restrict__ optime) {
   constexpr int NB = 2 * TS;
@@ -658,6 +667,7 @@ __device__ inline void tile_walk(TileLds& S, const ChainDesc& D, int64_t x, int6
   const int64_t j = x / TS, a = x - j * TS;
   const int64_t jl = (j == 0) ? D.L - 1 : j - 1;
   int64_t bnd[NB], h[NB], e[NB];
+  int hl[NB];  // local index of the head (owned bonds), or -1
   uint64_t th[NB];
   bool before = false, any = false;
 #pragma unroll
@@ -667,7 +677,9 @@ __device__ inline void tile_walk(TileLds& S, const ChainDesc& D, int64_t x, int6
     h[s] = opstart[i0 + k];
     e[s] = opstart[i0 + k + 1];
     before = before || opstart[i0] < h[s];
-    th[s] = h[s] < e[s] ? optime[h[s]] : 0;
+    const int64_t lb = bnd[s] - B0;
+    hl[s] = (lb >= 0 && lb < nbt) ? static_cast<int>(S.tpre[lb] + (h[s] - S.tos[lb])) : -1;
+    th[s] = h[s] < e[s] ? (hl[s] >= 0 ? S.ltime[hl[s]] : optime[h[s]]) : 0;
     any = any || h[s] < e[s];
   }
   if (!any) {
@@ -685,7 +697,7 @@ __device__ inline void tile_walk(TileLds& S, const ChainDesc& D, int64_t x, int6
   int64_t prev = -1;
   int lprev = -1;
   for (;;) {
-    int sm = -1;
+    int sm = -1, lcur = -1;
     uint64_t tm = 0;
     int64_t bm = 0, cur = 0, em = 0;
 #pragma unroll
@@ -696,10 +708,10 @@ __device__ inline void tile_walk(TileLds& S, const ChainDesc& D, int64_t x, int6
         bm = bnd[s];
         cur = h[s];
         em = e[s];
+        lcur = hl[s];
       }
     }
     if (sm < 0) break;
-    const int lcur = tile_local(S, B0, nbt, bm, cur);
     const int64_t gl = nb0 + 2 * cur;
     if (prev < 0) {
       if (!before) tile_edge(S, node_base + x, -1, gl, lcur >= 0 ? 2 * lcur : -1);
@@ -709,11 +721,13 @@ __device__ inline void tile_walk(TileLds& S, const ChainDesc& D, int64_t x, int6
     prev = cur;
     lprev = lcur;
     const int64_t nh = cur + 1;
-    const uint64_t nt = nh < em ? optime[nh] : 0;
+    const int nl = lcur >= 0 ? lcur + 1 : -1;
+    const uint64_t nt = nh < em ? (nl >= 0 ? S.ltime[nl] : optime[nh]) : 0;
 #pragma unroll
     for (int s = 0; s < NB; ++s) {
       if (s == sm) {
         h[s] = nh;
+        hl[s] = nl;
         th[s] = nt;
       }
     }
@@ -727,7 +741,8 @@ __device__ inline void tile_walk(TileLds& S, const ChainDesc& D, int64_t x, int6
     const int64_t i0 = D.win_base + bnd[s] * W;
     const int64_t idx = e[s];
     if (idx < opstart[i0 + W]) {
-      const uint64_t t = optime[idx];
+      const int li = tile_local(S, B0, nbt, bnd[s], idx);
+      const uint64_t t = li >= 0 ? S.ltime[li] : optime[idx];
       if (nxt < 0 || t < tn || (t == tn && bnd[s] < bn)) {
         nxt = idx;
         tn = t;
@@ -753,7 +768,9 @@ __global__ __launch_bounds__(kBlock) void k_link_tile(
     int64_t* __restrict__ parent, int64_t* __restrict__ xedge, int64_t xcap,
     int64_t* __restrict__ frag, int64_t fcap, unsigned long long* __restrict__ dyncnt,
     unsigned long long* __restrict__ stats, uint32_t* __restrict__ flags) {
-  __shared__ TileLds S;
+  using C = TileCfg<TS>;
+  constexpr int kNodes = C::kNodes;
+  __shared__ TileLds<TS> S;
   const int tid = threadIdx.x;
   // flags are read once per block: later kernels of this launch may set them
   if (tid == 0) S.fl = *flags;
@@ -785,11 +802,14 @@ __global__ __launch_bounds__(kBlock) void k_link_tile(
     }
     int64_t total;
     const int64_t ex = block_exclusive_scan(cnt, S.scan, total);
-    if (nbt > kTileBonds || nthr > kBlock || total > kTileOps) {  // block-uniform
+    if (nbt > kTileBonds || nthr > kBlock || total > C::kOps) {  // block-uniform
       if (tid == 0) atomicOr(flags, LC_FLAG_TILE);
       break;
     }
-    if (tid < nbt) S.tpre[tid] = static_cast<uint32_t>(ex);
+    if (tid < nbt) {
+      S.tpre[tid] = static_cast<uint32_t>(ex);
+      for (int64_t q = 0; q < cnt; ++q) S.lbond[ex + q] = static_cast<uint8_t>(tid);
+    }
     if (tid == 0) {
       S.tpre[nbt] = static_cast<uint32_t>(total);
       S.cnt[0] = S.cnt[1] = S.cnt[2] = S.cnt[3] = 0;
@@ -797,7 +817,10 @@ __global__ __launch_bounds__(kBlock) void k_link_tile(
     const int nlo = static_cast<int>(total);
     const int nn = 2 * nlo;
     for (int u = tid; u < nn; u += kBlock) S.lpar[u] = static_cast<uint32_t>(u);
-    for (int i = tid; i < kTileNodes / 16; i += kBlock) S.deg[i] = 0;
+    for (int i = tid; i < kNodes / 16; i += kBlock) S.deg[i] = 0;
+    __syncthreads();
+    // the tile's operator times, coalesced
+    for (int lo = tid; lo < nlo; lo += kBlock) S.ltime[lo] = optime[tile_op(S, static_cast<uint32_t>(lo))];
     __syncthreads();
     if (tid < nthr) {
       const int xs = tid % (nj * TS);
@@ -807,10 +830,11 @@ __global__ __launch_bounds__(kBlock) void k_link_tile(
     __syncthreads();
     // full compression in two steps: every root is found by read-only walks
     // first (a halving write landing after another thread's final write
-    // would leave a node below a non-root), then written
-    uint32_t roots[(kTileNodes + kBlock - 1) / kBlock];
+    // would leave a node below a non-root), then written; a rep's word
+    // becomes its fields
+    uint32_t roots[(kNodes + kBlock - 1) / kBlock];
 #pragma unroll
-    for (int i = 0; i < (kTileNodes + kBlock - 1) / kBlock; ++i) {
+    for (int i = 0; i < (kNodes + kBlock - 1) / kBlock; ++i) {
       const int u = tid + i * kBlock;
       uint32_t r = static_cast<uint32_t>(u);
       if (u < nn)
@@ -819,16 +843,16 @@ __global__ __launch_bounds__(kBlock) void k_link_tile(
     }
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < (kTileNodes + kBlock - 1) / kBlock; ++i) {
+    for (int i = 0; i < (kNodes + kBlock - 1) / kBlock; ++i) {
       const int u = tid + i * kBlock;
       if (u < nn) S.lpar[u] = roots[i] == static_cast<uint32_t>(u) ? kRepFlag : roots[i];
     }
     __syncthreads();
-    // component sizes; components with a node lacking a local edge are open
     auto rep_of = [&](int u) -> uint32_t {
       const uint32_t w = S.lpar[u];
       return (w & kRepFlag) ? static_cast<uint32_t>(u) : w;
     };
+    // component sizes; components with a node lacking a local edge are open
     for (int u = tid; u < nn; u += kBlock) {
       const uint32_t r = rep_of(u);
       const uint32_t deg = (S.deg[u >> 4] >> ((u & 15) * 2)) & 3u;
@@ -845,13 +869,11 @@ __global__ __launch_bounds__(kBlock) void k_link_tile(
       const bool open = (av & kRepOpen) != 0;
       if (!open && (av & kRepSize) == 2 && (u & 1) && u + 1 < nn &&
           S.lpar[u + 1] == static_cast<uint32_t>(u)) {
-        const int64_t q = tile_op(S, nbt, static_cast<uint32_t>(u >> 1));
-        const int64_t q1 = tile_op(S, nbt, static_cast<uint32_t>((u + 1) >> 1));
-        sums.add(2, (optime[q1] - optime[q]) >> 31);  // length 2 (t1 - t0), >> 32
+        sums.add(2, (S.ltime[(u + 1) >> 1] - S.ltime[u >> 1]) >> 31);  // length 2 (t1 - t0), >> 32
         continue;
       }
       const int s = atomicAdd(&S.cnt[1], 1);
-      if (s < kTileSlots) {
+      if (s < C::kSlots) {
         S.lpar[u] = av | (static_cast<uint32_t>(s + 1) << kRepSlotShift);
         S.slot_rep[s] = static_cast<uint32_t>(u);
         S.slot_hi[s] = 0;
@@ -860,13 +882,13 @@ __global__ __launch_bounds__(kBlock) void k_link_tile(
       }
     }
     __syncthreads();
-    if (S.cnt[0] > kTileCross || S.cnt[1] > kTileSlots) {  // block-uniform
+    if (S.cnt[0] > C::kCross || S.cnt[1] > C::kSlots) {  // block-uniform
       if (tid == 0) atomicOr(flags, LC_FLAG_TILE);
       break;
     }
     // length sums of the slotted components: lower nodes +t, upper nodes -t
     for (int lo = tid; lo < nlo; lo += kBlock) {
-      const uint64_t tq = optime[tile_op(S, nbt, static_cast<uint32_t>(lo))];
+      const uint64_t tq = S.ltime[lo];
       const uint64_t th = tq >> 32, tl = tq & 0xFFFFFFFFull;
 #pragma unroll
       for (int hh = 0; hh < 2; ++hh) {
@@ -903,7 +925,7 @@ __global__ __launch_bounds__(kBlock) void k_link_tile(
       if (av & kRepOpen) {
         const int64_t f = S.base[1] + atomicAdd(&S.cnt[3], 1);
         if (f < fcap) {
-          frag[4 * f + 0] = nb0 + 2 * tile_op(S, nbt, u >> 1) + (u & 1);
+          frag[4 * f + 0] = nb0 + 2 * tile_op(S, u >> 1) + (u & 1);
           frag[4 * f + 1] = static_cast<int64_t>(size | (static_cast<uint64_t>(c) << 16));
           frag[4 * f + 2] = S.slot_hi[s];
           frag[4 * f + 3] = S.slot_lo[s];
@@ -916,7 +938,7 @@ __global__ __launch_bounds__(kBlock) void k_link_tile(
     // parent words: the component's rep; a rep holds itself (open) or
     // kClosedRoot (finished)
     for (int lo = tid; lo < nlo; lo += kBlock) {
-      const int64_t q = tile_op(S, nbt, static_cast<uint32_t>(lo));
+      const int64_t q = tile_op(S, static_cast<uint32_t>(lo));
 #pragma unroll
       for (int hh = 0; hh < 2; ++hh) {
         const uint32_t u = static_cast<uint32_t>(2 * lo + hh);
@@ -925,7 +947,7 @@ __global__ __launch_bounds__(kBlock) void k_link_tile(
         if (r == u)
           parent[g] = (S.lpar[u] & kRepOpen) ? g : kClosedRoot;
         else
-          parent[g] = nb0 + 2 * tile_op(S, nbt, r >> 1) + (r & 1);
+          parent[g] = nb0 + 2 * tile_op(S, r >> 1) + (r & 1);
       }
     }
     __syncthreads();  // the LDS is reused by the next tile
