@@ -145,6 +145,22 @@ int lc_update(lc_chain *c, int64_t n_sweeps, int accumulate);
  * NULL.  Host-only: no device work. */
 int lc_measure(const lc_chain *c, lc_measurement *out);
 
+/* update without allocating: for callers that cannot allocate device
+ * memory (code under graph capture, tight serving loops).  The same sweeps
+ * as lc_update (bit for bit), launched directly on the chain's stream, with
+ * every per-sweep buffer carved from the library's static device scratch of
+ * 64 MiB per GPU instead of the arena; the chain's own state buffers come
+ * from lc_init_lattice.  No device or library allocation happens in the
+ * call (the scratch address is looked up once per GPU).  Chains whose
+ * per-sweep scratch does not fit in 64 MiB (about L beta <= 1e6 at S = 1/2)
+ * are refused with LC_ETOOLARGE before any work, and so is a sweep whose
+ * operators outgrow the estimate or the chain's kept-operator buffer (the
+ * chain is left unchanged; lc_update can grow them).  Calls on one GPU share
+ * the scratch: they must not overlap.  Exports of the operators and labels
+ * of these sweeps are not available (LC_ESTATE).  LC_ESTATE for a batch
+ * member. */
+int lc_update_noalloc(lc_chain *c, int64_t n_sweeps, int accumulate);
+
 /* Integers of the most recent sweep; LC_ESTATE before the first sweep. */
 int lc_last_sweep(const lc_chain *c, lc_sweep_stats *out);
 

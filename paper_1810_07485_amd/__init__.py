@@ -92,6 +92,7 @@ def load():
         "lc_init_lattice": ([C.c_int64, C.c_double, C.c_double, C.c_uint64, C.POINTER(Alloc), vp,
                              C.POINTER(vp)], C.c_int),
         "lc_update": ([vp, C.c_int64, C.c_int], C.c_int),
+        "lc_update_noalloc": ([vp, C.c_int64, C.c_int], C.c_int),
         "lc_measure": ([vp, C.POINTER(Measurement)], C.c_int),
         "lc_last_sweep": ([vp, C.POINTER(SweepStats)], C.c_int),
         "lc_reset_measurements": ([vp], C.c_int),
@@ -303,6 +304,11 @@ class Chain:
 
     def update(self, n_sweeps: int = 1, accumulate: bool = True):
         _check(load().lc_update(self._h, int(n_sweeps), int(bool(accumulate))), "lc_update")
+
+    def update_noalloc(self, n_sweeps: int = 1, accumulate: bool = True):
+        """lc_update_noalloc: the same sweeps with no allocation (static scratch)."""
+        _check(load().lc_update_noalloc(self._h, int(n_sweeps), int(bool(accumulate))),
+               "lc_update_noalloc")
 
     def measure(self) -> dict:
         m = Measurement()

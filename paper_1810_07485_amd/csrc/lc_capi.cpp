@@ -27,6 +27,7 @@
 #include <vector>
 
 #include "lc_kernels.h"
+#include "lc_static.h"
 
 using lc::ChainDesc;
 using lc::ChainDyn;
@@ -836,6 +837,80 @@ size_t footprint_bytes(int64_t L, int two_s, double beta) {
 }  // namespace
 
 // ------------------------------------------------------------------------
+// Scratch of one sweep of one chain carved from the static device array.
+namespace {
+
+struct Carver {
+  unsigned char* base;
+  size_t cap, used = 0;
+  template <class T>
+  T* take(size_t n) {
+    used = (used + 255) & ~size_t(255);
+    T* p = reinterpret_cast<T*>(base + used);
+    used += (n ? n : 1) * sizeof(T);
+    return p;
+  }
+};
+
+// Carve the scratch of one sweep of c; false if it does not fit.
+bool carve_static(lc_chain* c, unsigned char* base, size_t cap, LcSweepArgs* A) {
+  Carver K{base, cap};
+  const int64_t ops = ops_estimate(c);
+  const int64_t nodes = c->nbn + 2 * ops;
+  const int64_t xe = static_cast<int64_t>(cross_per_op(c->two_s) * static_cast<double>(ops)) + 4096;
+  const int64_t fe = static_cast<int64_t>(frags_per_op(c->two_s) * static_cast<double>(ops)) + 4096;
+  const int64_t items = fe + c->nbn;
+  std::memset(A, 0, sizeof(*A));
+  A->descs = K.take<ChainDesc>(1);
+  A->win_bases = K.take<int64_t>(1);
+  A->site_bases = K.take<int64_t>(1);
+  A->spin_bases = K.take<int64_t>(1);
+  A->bn_bases = K.take<int64_t>(1);
+  A->op_bases = K.take<int64_t>(1);
+  A->node_bases = K.take<int64_t>(1);
+  A->grp_chain = K.take<int>(1);
+  A->grp_tile_base = K.take<int64_t>(1);
+  A->dyn = K.take<ChainDyn>(1);
+  A->totals = K.take<int64_t>(2);
+  A->scan_tmp = K.take<int64_t>(LC_SCAN_BLOCKS + 1);
+  A->stats = K.take<uint64_t>(lc::ST_WORDS * (1 + LC_STAT_STRIPES));
+  A->flags = K.take<uint32_t>(2);
+  A->ring = K.take<unsigned long long>(lc::ST_WORDS + 1);
+  A->ring_ctr = K.take<uint32_t>(2);
+  A->dyncnt = K.take<unsigned long long>(4);
+  A->opstart = K.take<int64_t>(c->nwin + 1);
+  A->accmask = K.take<uint32_t>(c->nwin);
+  A->kflat = K.take<int64_t>(c->nwin + 1);
+  A->optime = K.take<uint64_t>(ops);
+  A->optype = K.take<uint8_t>(ops);
+  A->parent = K.take<int64_t>(nodes);
+  A->xedge = K.take<int64_t>(2 * xe);
+  A->frag = K.take<int64_t>(4 * fe);
+  A->acc = K.take<unsigned long long>(kAccWords * items);
+  A->bacc = K.take<unsigned long long>(c->n_sites);
+  A->rcnt = K.take<int64_t>(items / 4096 + 2);
+  if (K.used > K.cap) return false;
+  A->nchain = 1;
+  A->any_split = c->two_s > 1 ? 1 : 0;
+  A->nwin = c->nwin;
+  A->nsites = c->n_sites;
+  A->nspins = c->L;
+  A->nbn = c->nbn;
+  A->grid_blocks = kDefaultGrid;
+  A->ngroups = 1;
+  A->groups[0] = LcTileGroup{c->two_s, 1, 0, c->ntj * c->ntk};
+  A->op_cap = ops;
+  A->node_cap = nodes;
+  A->root_cap = items;
+  A->xcap = xe;
+  A->fcap = fe;
+  A->ring_cap = 1;
+  A->events = nullptr;
+  return true;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* lc_strerror(int code) {
@@ -1039,6 +1114,58 @@ int lc_update(lc_chain* c, int64_t n_sweeps, int accumulate) {
   Engine* E = own_engine(c);
   if (!E) return LC_ENOMEM;
   return run_engine(*E, n_sweeps, accumulate);
+}
+
+// Sweeps of one chain with all per-sweep scratch carved from the library's
+// static device array (lc_static.hip): no allocation anywhere in the call.
+int lc_update_noalloc(lc_chain* c, int64_t n_sweeps, int accumulate) {
+  if (!c || n_sweeps < 0) return LC_EINVAL;
+  if (c->batch) return LC_ESTATE;
+  if (n_sweeps == 0) return LC_OK;
+  size_t cap = 0;
+  unsigned char* base = static_cast<unsigned char*>(lc_static_scratch(&cap));
+  if (!base) return LC_EDEVICE;
+  hipStream_t s = c->stream;
+  int64_t done = 0;
+  int retries = 0;
+  while (done < n_sweeps) {
+    choose_tile(c);
+    LcSweepArgs A;
+    if (!carve_static(c, base, cap, &A)) return LC_ETOOLARGE;
+    const ChainDesc d = make_desc(c, 0, 0, 0, 0);
+    const int64_t zero = 0;
+    const int gc = 0;
+    unsigned long long rec[lc::ST_WORDS + 1];
+    if (hipMemcpyAsync(A.descs, &d, sizeof(d), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(const_cast<int64_t*>(A.win_bases), &zero, 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(const_cast<int64_t*>(A.site_bases), &zero, 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(const_cast<int64_t*>(A.spin_bases), &zero, 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(const_cast<int64_t*>(A.bn_bases), &zero, 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(const_cast<int64_t*>(A.grp_tile_base), &zero, 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(const_cast<int*>(A.grp_chain), &gc, sizeof(int), hipMemcpyHostToDevice, s) != hipSuccess ||
+        lc_launch_fill_u64(A.ring_ctr, 1, 0, s) != hipSuccess ||
+        lc_launch_sweep(A, s) != hipSuccess ||
+        hipMemcpyAsync(rec, A.ring, sizeof(rec), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return LC_EDEVICE;
+    const uint32_t bad = static_cast<uint32_t>(rec[lc::ST_WORDS]);
+    if (!bad) {
+      apply_record(c, rec, accumulate != 0);
+      ++done;
+      retries = 0;
+      continue;
+    }
+    // the sweep was discarded: the chain is unchanged
+    if (bad & LC_FLAG_SYM) return LC_ESTATE;
+    if (bad & LC_FLAG_GRAPH) return LC_EDEVICE;
+    if ((bad & ~LC_FLAG_TILE) || ++retries > 10) return LC_ETOOLARGE;  // cannot grow
+    c->tile_shrink = std::min(c->tile_shrink + 1, 10);
+  }
+  // the chain's own engine holds descriptors of an older sweep; the arena
+  // holds no operators or labels of these sweeps
+  if (c->own) c->own->dirty = true;
+  c->last_engine = nullptr;
+  return LC_OK;
 }
 
 int lc_measure(const lc_chain* c, lc_measurement* out) {
