@@ -207,6 +207,29 @@ int lc_export_labels(const lc_chain *c, int64_t *labels, int64_t *n_nodes);
  * count out. */
 int lc_export_perm(const lc_chain *c, int64_t *perm, int64_t *n);
 
+/* Open-boundary imaginary-time slices of the most recent sweep (Sec. 3.1:
+ * each process identifies the loops inside its time window first; the
+ * fragments crossing the window's two boundaries are what the global merge
+ * joins, Fig. 3 and the butterfly of Sec. 3.3).  The windows of every bond
+ * are cut into n_slices (1..2^w) contiguous slices, slice p holding windows
+ * [p W / G, (p + 1) W / G).  Inside each slice the loop graph of the sweep's
+ * operators is linked with the segments that cross a slice boundary cut:
+ * the first event of subspin x in slice p joins the slice's bottom node
+ * (p, x), its last event the top node (p, x), a subspin without events in
+ * the slice joins the two directly; the components are found by the
+ * library's union-find.  Every node gets the smallest id of its slice
+ * component, ids numbered 2 ns p + x (bottom), 2 ns p + ns + x (top) and
+ * 2 ns G + 2 q + h for node h of the chain's operator q (ns = 2S L):
+ * bottom[p ns + x], top[p ns + x] (G ns entries each) and op_labels[2 q + h]
+ * (2 n_ops entries).  Two boundary nodes with one label are joined inside
+ * their slice; a component without boundary nodes is a loop closed inside
+ * it.  *n_ops: capacity of op_labels / 2 in, operators out; all arrays NULL
+ * queries the count.  Valid as lc_export_ops; allocates and frees a
+ * temporary device array of that many words.  LC_EINVAL for n_slices out
+ * of range. */
+int lc_slice_tables(const lc_chain *c, int n_slices, int64_t *bottom, int64_t *top,
+                    int64_t *op_labels, int64_t *n_ops);
+
 void lc_free(lc_chain *c);
 const char *lc_strerror(int code);
 

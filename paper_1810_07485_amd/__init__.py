@@ -101,6 +101,7 @@ def load():
         "lc_export_ops": ([vp, p64, pu64, pu8, pu8, p64], C.c_int),
         "lc_export_labels": ([vp, p64, p64], C.c_int),
         "lc_export_perm": ([vp, p64, p64], C.c_int),
+        "lc_slice_tables": ([vp, C.c_int, p64, p64, p64, p64], C.c_int),
         "lc_free": ([vp], None),
         "lc_strerror": ([C.c_int], C.c_char_p),
         "lc_batch_create": ([C.POINTER(Alloc), vp, C.POINTER(vp)], C.c_int),
@@ -399,6 +400,24 @@ class Chain:
         n = C.c_int64(p.size)
         _check(lib.lc_export_perm(self._h, _p(p, C.c_int64), C.byref(n)), "lc_export_perm")
         return p[:k].copy()
+
+
+def slice_tables(chain, n_slices: int):
+    """lc_slice_tables: (bottom[G, ns], top[G, ns], op_labels[2 n_ops]) of the
+    chain's most recent sweep cut into n_slices open-boundary time slices."""
+    lib = load()
+    n = C.c_int64(0)
+    _check(lib.lc_slice_tables(chain._h, int(n_slices), None, None, None, C.byref(n)),
+           "lc_slice_tables")
+    k = n.value
+    ns = chain.n_sites
+    bot = np.zeros((int(n_slices), ns), np.int64)
+    top = np.zeros((int(n_slices), ns), np.int64)
+    lab = np.zeros(max(2 * k, 1), np.int64)
+    n = C.c_int64(k)
+    _check(lib.lc_slice_tables(chain._h, int(n_slices), _p(bot, C.c_int64), _p(top, C.c_int64),
+                               _p(lab, C.c_int64), C.byref(n)), "lc_slice_tables")
+    return bot, top, lab[: 2 * k].copy()
 
 
 class Batch:

@@ -1353,6 +1353,67 @@ int lc_export_labels(const lc_chain* c, int64_t* labels, int64_t* n_nodes) {
   return LC_OK;
 }
 
+int lc_slice_tables(const lc_chain* c, int n_slices, int64_t* bottom, int64_t* top,
+                    int64_t* op_labels, int64_t* n_ops) {
+  if (!c || !n_ops) return LC_EINVAL;
+  if (!c->last_engine) return LC_ESTATE;
+  Arena* R = c->last_engine->ar;
+  std::lock_guard<std::mutex> hold(R->mu);
+  ChainDyn d;
+  int64_t wb;
+  int rc = last_ranges(c, &d, &wb);
+  if (rc != LC_OK) return rc;
+  const int64_t W = int64_t(1) << c->w;
+  if (n_slices < 1 || n_slices > W) return LC_EINVAL;
+  const int64_t have = *n_ops;
+  *n_ops = d.n_ops;
+  if (!bottom && !top && !op_labels) return LC_OK;
+  if (!bottom || !top || !op_labels) return LC_EINVAL;
+  if (have < d.n_ops) return LC_ECAPACITY;
+  const int64_t ns = c->n_sites, G = n_slices;
+  const int64_t n = 2 * ns * G + 2 * d.n_ops;
+  int64_t* par = static_cast<int64_t*>(c->mem.get(static_cast<size_t>(n) * sizeof(int64_t)));
+  uint32_t* fl = static_cast<uint32_t*>(c->mem.get(8));
+  if (!par || !fl) {
+    c->mem.put(par, static_cast<size_t>(n) * sizeof(int64_t));
+    c->mem.put(fl, 8);
+    return LC_ENOMEM;
+  }
+  LcSliceArgs A;
+  A.L = c->L;
+  A.n_sites = ns;
+  A.two_s = c->two_s;
+  A.w = c->w;
+  A.win_base = wb;
+  A.op_base = d.op_base;
+  A.n_ops = d.n_ops;
+  A.opstart = R->opstart.p;
+  A.optime = R->optime.p;
+  A.n_slices = G;
+  A.parent = par;
+  A.flags = fl;
+  std::vector<int64_t> h(static_cast<size_t>(n));
+  uint32_t bad = 0;
+  hipStream_t s = c->stream;
+  rc = LC_OK;
+  if (lc_launch_fill_u64(fl, 1, 0, s) != hipSuccess || lc_launch_slices(A, s) != hipSuccess ||
+      hipMemcpyAsync(h.data(), par, static_cast<size_t>(n) * sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(&bad, fl, sizeof(bad), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    rc = LC_EDEVICE;
+  c->mem.put(par, static_cast<size_t>(n) * sizeof(int64_t));
+  c->mem.put(fl, 8);
+  if (rc != LC_OK) return rc;
+  if (bad) return LC_EDEVICE;
+  for (int64_t p = 0; p < G; ++p)
+    for (int64_t x = 0; x < ns; ++x) {
+      bottom[p * ns + x] = h[2 * ns * p + x];
+      top[p * ns + x] = h[2 * ns * p + ns + x];
+    }
+  for (int64_t i = 0; i < 2 * d.n_ops; ++i) op_labels[i] = h[2 * ns * G + i];
+  return LC_OK;
+}
+
 int lc_export_perm(const lc_chain* c, int64_t* perm, int64_t* n) {
   if (!c || !n) return LC_EINVAL;
   const int64_t have = *n;

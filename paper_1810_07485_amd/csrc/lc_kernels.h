@@ -99,7 +99,21 @@ enum LcPhase {
 #define LC_FLAG_FRAG 128u    // fragment buffer too small
 #define LC_FLAG_GRAPH 256u   // a union-find word outside the loop graph (internal error)
 
+// Open-boundary time slices of one chain's most recent sweep.
+struct LcSliceArgs {
+  int64_t L, n_sites;
+  int two_s, w;
+  int64_t win_base;           // flat window of the chain's bond 0, window 0
+  int64_t op_base, n_ops;     // the chain's operators in the flat list
+  const int64_t* opstart;
+  const uint64_t* optime;
+  int64_t n_slices;           // G, 1 <= G <= windows per bond
+  int64_t* parent;            // 2 n_sites G + 2 n_ops words
+  uint32_t* flags;            // LC_FLAG_GRAPH on an inconsistent graph
+};
+
 hipError_t lc_launch_sweep(const LcSweepArgs& a, hipStream_t s);
+hipError_t lc_launch_slices(const LcSliceArgs& a, hipStream_t s);
 hipError_t lc_launch_scan(int64_t* a, int64_t n, int64_t* bsum, hipStream_t s);
 hipError_t lc_launch_init_chain(const lc::ChainDesc* d, int64_t n, hipStream_t s);
 hipError_t lc_launch_fill_u64(void* p, int64_t n, uint64_t v, hipStream_t s);

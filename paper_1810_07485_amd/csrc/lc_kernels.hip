@@ -1604,6 +1604,124 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(int64_t* __restrict__ a, 
 }
 
 
+
+// ---------------------------------------------------------------------------
+// Imaginary-time slices with open boundaries (Sec. 3.1): the time axis is cut
+// into G slices of whole windows; inside each slice the loop graph of the
+// most recent sweep is linked and union-found on its own, the segments
+// crossing a slice boundary being cut: the first event of a subspin in the
+// slice joins the slice's bottom node of that subspin, its last event the
+// slice's top node, and a subspin without events in the slice joins the two
+// directly.  Node ids: bottom(p, x) = 2 ns p + x, top(p, x) = 2 ns p + ns + x,
+// operator node (q, h) = 2 ns G + 2 (q - op_base) + h.  What each slice
+// leaves open is its 2 ns boundary nodes' components: the table a global
+// merge of the slices needs (Sec. 3.1, Fig. 3; the butterfly of Sec. 3.3
+// exchanges exactly these).
+template <int TS>
+__global__ __launch_bounds__(kBlock) void k_slice_walk(LcSliceArgs A) {
+  constexpr int NB = 2 * TS;
+  const int64_t W = int64_t(1) << A.w;
+  const int64_t ns = A.n_sites, G = A.n_slices;
+  const int64_t nodes = 2 * ns * G + 2 * A.n_ops;
+  const int64_t nop0 = 2 * ns * G - 2 * A.op_base;  // node of lower(q) = nop0 + 2q
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < ns * W;
+       i += static_cast<int64_t>(gridDim.x) * kBlock) {
+    const int64_t x = i / W, k = i - x * W;
+    const int64_t p = ((k + 1) * G - 1) / W;
+    const int64_t kb = p * W / G, ke = (p + 1) * W / G;
+    const int64_t bot = 2 * ns * p + x, top = bot + ns;
+    const int64_t j = x / TS, a = x - j * TS;
+    const int64_t jl = (j == 0) ? A.L - 1 : j - 1;
+    int64_t bnd[NB], h[NB], e[NB], se[NB];
+    uint64_t th[NB];
+    bool before = false, any = false, inslice = false;
+#pragma unroll
+    for (int s = 0; s < NB; ++s) {
+      bnd[s] = s < TS ? (jl * TS + s) * TS + a : (j * TS + a) * TS + (s - TS);
+      const int64_t i0 = A.win_base + bnd[s] * W;
+      h[s] = A.opstart[i0 + k];
+      e[s] = A.opstart[i0 + k + 1];
+      se[s] = A.opstart[i0 + ke];  // end of the slice on this bond
+      const int64_t sb = A.opstart[i0 + kb];
+      before = before || sb < h[s];
+      inslice = inslice || sb < se[s];
+      th[s] = h[s] < e[s] ? A.optime[h[s]] : 0;
+      any = any || h[s] < e[s];
+    }
+    if (!any) {
+      if (k == kb && !inslice) uf_union(A.parent, bot, top, nodes, A.flags);
+      continue;
+    }
+    int64_t prev = -1;
+    for (;;) {
+      int sm = -1;
+      uint64_t tm = 0;
+      int64_t bm = 0, cur = 0, em = 0;
+#pragma unroll
+      for (int s = 0; s < NB; ++s) {
+        if (h[s] < e[s] && (sm < 0 || th[s] < tm || (th[s] == tm && bnd[s] < bm))) {
+          sm = s;
+          tm = th[s];
+          bm = bnd[s];
+          cur = h[s];
+          em = e[s];
+        }
+      }
+      if (sm < 0) break;
+      if (prev < 0) {
+        if (!before) uf_union(A.parent, bot, nop0 + 2 * cur, nodes, A.flags);
+      } else {
+        uf_union(A.parent, nop0 + 2 * prev + 1, nop0 + 2 * cur, nodes, A.flags);
+      }
+      prev = cur;
+      const int64_t nh = cur + 1;
+      const uint64_t nt = nh < em ? A.optime[nh] : 0;
+#pragma unroll
+      for (int s = 0; s < NB; ++s) {
+        if (s == sm) {
+          h[s] = nh;
+          th[s] = nt;
+        }
+      }
+    }
+    // the next event on this subspin inside the slice, or its top node
+    int64_t nxt = -1, bn = 0;
+    uint64_t tn = 0;
+#pragma unroll
+    for (int s = 0; s < NB; ++s) {
+      const int64_t idx = e[s];
+      if (idx < se[s]) {
+        const uint64_t t = A.optime[idx];
+        if (nxt < 0 || t < tn || (t == tn && bnd[s] < bn)) {
+          nxt = idx;
+          tn = t;
+          bn = bnd[s];
+        }
+      }
+    }
+    uf_union(A.parent, nop0 + 2 * prev + 1, nxt >= 0 ? nop0 + 2 * nxt : top, nodes, A.flags);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_slice_init(int64_t* __restrict__ parent, int64_t n) {
+  for (int64_t g = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; g < n;
+       g += static_cast<int64_t>(gridDim.x) * kBlock)
+    parent[g] = g;
+}
+
+// label = smallest node of the slice component (read-only walk, then write)
+__global__ __launch_bounds__(kBlock) void k_slice_compress(int64_t* __restrict__ parent, int64_t n) {
+  for (int64_t g = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; g < n;
+       g += static_cast<int64_t>(gridDim.x) * kBlock) {
+    int64_t r = g, p = parent[g];
+    while (p != r && p >= 0 && p < n) {
+      r = p;
+      p = parent[r];
+    }
+    parent[g] = r;
+  }
+}
+
 }  // namespace lc
 
 // ---------------------------------------------------------------------------
@@ -1744,5 +1862,29 @@ hipError_t lc_launch_init_chain(const ChainDesc* d, int64_t n, hipStream_t s) {
 hipError_t lc_launch_fill_u64(void* p, int64_t n, uint64_t v, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 1024)), dim3(kBlock), 0, s,
                      reinterpret_cast<unsigned long long*>(p), n, static_cast<unsigned long long>(v));
+  return hipGetLastError();
+}
+
+template <int TS>
+static void launch_slice_walk(const LcSliceArgs& A, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((k_slice_walk<TS>), dim3(grid), dim3(kBlock), 0, s, A);
+}
+
+hipError_t lc_launch_slices(const LcSliceArgs& A, hipStream_t s) {
+  const int64_t n = 2 * A.n_sites * A.n_slices + 2 * A.n_ops;
+  hipLaunchKernelGGL(k_slice_init, dim3(grid_for(n, 8192)), dim3(kBlock), 0, s, A.parent, n);
+  const int grid = grid_for(A.n_sites * (int64_t(1) << A.w), 8192);
+  switch (A.two_s) {
+    case 1: launch_slice_walk<1>(A, grid, s); break;
+    case 2: launch_slice_walk<2>(A, grid, s); break;
+    case 3: launch_slice_walk<3>(A, grid, s); break;
+    case 4: launch_slice_walk<4>(A, grid, s); break;
+    case 5: launch_slice_walk<5>(A, grid, s); break;
+    case 6: launch_slice_walk<6>(A, grid, s); break;
+    case 7: launch_slice_walk<7>(A, grid, s); break;
+    case 8: launch_slice_walk<8>(A, grid, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipLaunchKernelGGL(k_slice_compress, dim3(grid_for(n, 8192)), dim3(kBlock), 0, s, A.parent, n);
   return hipGetLastError();
 }
