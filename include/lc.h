@@ -130,6 +130,19 @@ int lc_footprint_parts(int64_t L, double S, double beta, size_t *state, size_t *
 int lc_init_lattice(int64_t L, double S, double beta, uint64_t seed, const lc_alloc *alloc,
                     void *hip_stream, lc_chain **out);
 
+/* Loop-flip rule of the following sweeps.  LC_FLIP_LABEL (default): a loop
+ * flips iff the Philox bit keyed by its smallest node id is 1 (canonical
+ * labels make the decision independent of how the union-find ran).
+ * LC_FLIP_VOTE: the majority-vote trick of Sec. 3.3 -- every loop-graph
+ * node casts a Philox vote in advance and a loop flips iff the XOR of its
+ * nodes' votes is 1, a tally that needs no canonical label.  Both flip each
+ * loop with probability 1/2 independently of the others; they are different
+ * Markov chains with the same stationary distribution.  LC_EINVAL on an
+ * unknown rule. */
+#define LC_FLIP_LABEL 0
+#define LC_FLIP_VOTE 1
+int lc_set_flip_rule(lc_chain *c, int rule);
+
 /* update: n_sweeps loop-cluster updates (Sec. 2 steps 1-8).  With
  * accumulate != 0 each sweep's integers are added to the measurement sums.
  * LC_ESTATE when the chain belongs to a batch. */

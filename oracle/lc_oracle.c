@@ -118,6 +118,28 @@ int orc_window_table(double beta, int *w_out, double *mu_out, uint64_t *T, int *
     return ORC_OK;
 }
 
+/* One bit of a 128-bit Philox block of domain dom: block id/128, bit id
+ * mod 128 of the block read as words 0..3, least significant first. */
+static int domain_bit(uint64_t seed, int64_t sweep, int64_t id, unsigned dom)
+{
+    uint64_t q = (uint64_t)id >> 7;
+    unsigned i = (unsigned)(id & 127);
+    uint32_t ctr[4] = {(uint32_t)q, (dom << 24) | (uint32_t)((q >> 32) & 0xFFFFFFu), 0u,
+                       (uint32_t)sweep},
+             o[4];
+    orc_philox(seed, ctr, o);
+    return (int)((o[i >> 5] >> (i & 31)) & 1u);
+}
+
+/* Majority-vote trick (Sec. 3.3): every node votes in advance; a loop flips
+ * iff the XOR of its nodes' votes is 1.  The tally is order-independent,
+ * and each loop's decision is a fair bit independent of the other loops'
+ * (disjoint sets of independent votes). */
+int orc_vote_bit(uint64_t seed, int64_t sweep, int64_t node)
+{
+    return domain_bit(seed, sweep, node, ORC_DOM_VOTE);
+}
+
 int orc_flip_bit(uint64_t seed, int64_t sweep, int64_t label)
 {
     uint64_t q = (uint64_t)label >> 7;
@@ -146,6 +168,7 @@ struct orc_chain {
     uint64_t *ktime;
     int64_t n_kept;
     int64_t sweep;
+    int flip_rule; /* ORC_FLIP_LABEL or ORC_FLIP_VOTE */
     /* last sweep, for inspection */
     int64_t last_n_ops, last_n_nodes;
     int64_t *last_bond;
@@ -201,6 +224,14 @@ int orc_create(int64_t L, int two_s, double beta, uint64_t seed, orc_chain **out
     c->n_kept = 0;
     c->sweep = 0;
     *out = c;
+    return ORC_OK;
+}
+
+int orc_set_flip_rule(orc_chain *c, int rule)
+{
+    if (!c || (rule != ORC_FLIP_LABEL && rule != ORC_FLIP_VOTE))
+        return ORC_EINVAL;
+    c->flip_rule = rule;
     return ORC_OK;
 }
 
@@ -682,21 +713,35 @@ int orc_sweep(orc_chain *c, orc_stats *st)
         free(len);
 
         /* ---- 7. flip every loop with probability 1/2 (step 7) --------- */
+        /* flip[l] for every loop l (indexed by its label): its label's bit,
+         * or the XOR of its nodes' votes */
+        uint8_t *flip = (uint8_t *)calloc(nn > 0 ? nn : 1, 1);
+        if (!flip)
+            goto out2;
+        for (int64_t v = 0; v < nn; v++) {
+            if (c->flip_rule == ORC_FLIP_VOTE)
+                flip[label[v]] ^= (uint8_t)orc_vote_bit(c->seed, c->sweep, v);
+            else if (label[v] == v)
+                flip[v] = (uint8_t)orc_flip_bit(c->seed, c->sweep, v);
+        }
         int64_t nkept_out = 0;
         uint8_t *type1 = (uint8_t *)malloc(nops > 0 ? nops : 1);
-        if (!type1)
+        if (!type1) {
+            free(flip);
             goto out2;
+        }
         for (int64_t k = 0; k < nops; k++) {
-            int fl = orc_flip_bit(c->seed, c->sweep, label[nbn + 2 * k]);
-            int fu = orc_flip_bit(c->seed, c->sweep, label[nbn + 2 * k + 1]);
+            int fl = flip[label[nbn + 2 * k]];
+            int fu = flip[label[nbn + 2 * k + 1]];
             type1[k] = (uint8_t)(c->last_type0[k] ^ fl ^ fu);
             nkept_out += type1[k];
         }
         int64_t mafter = 0;
         for (int64_t i = 0; i < ns; i++) {
-            c->s0[i] ^= (uint8_t)orc_flip_bit(c->seed, c->sweep, label[i]);
+            c->s0[i] ^= flip[label[i]];
             mafter += 2 * (int64_t)c->s0[i] - 1;
         }
+        free(flip);
         /* the off-diagonal operators are the next world-line configuration */
         uint64_t *nk = (uint64_t *)malloc(sizeof(uint64_t) * (nkept_out > 0 ? nkept_out : 1));
         if (!nk) {

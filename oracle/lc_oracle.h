@@ -42,6 +42,12 @@ extern "C" {
 #define ORC_DOM_INS  1u
 #define ORC_DOM_FLIP 2u
 #define ORC_DOM_SYM  3u
+#define ORC_DOM_VOTE 4u
+
+/* Loop-flip rules: the loop's own Philox bit keyed by its smallest node
+ * (label), or the XOR of the votes of all its nodes (vote, Sec. 3.3). */
+#define ORC_FLIP_LABEL 0
+#define ORC_FLIP_VOTE  1
 
 typedef struct orc_chain orc_chain;
 
@@ -75,6 +81,10 @@ int orc_window_table(double beta, int *w, double *mu, uint64_t *T, int *K);
 
 /* Loop-flip bit of a cluster label in a sweep. */
 int orc_flip_bit(uint64_t seed, int64_t sweep, int64_t label);
+/* Vote of loop-graph node v in a sweep (flip rule ORC_FLIP_VOTE). */
+int orc_vote_bit(uint64_t seed, int64_t sweep, int64_t node);
+/* Select the loop-flip rule of the following sweeps (ORC_FLIP_*). */
+int orc_set_flip_rule(orc_chain *c, int rule);
 
 int  orc_create(int64_t L, int two_s, double beta, uint64_t seed, orc_chain **out);
 void orc_free(orc_chain *c);

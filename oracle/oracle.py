@@ -64,6 +64,8 @@ def lib():
         L.orc_philox.argtypes = [C.c_uint64, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
         L.orc_window_table.argtypes = [C.c_double, pi32, C.POINTER(C.c_double), pu64, pi32]
         L.orc_flip_bit.argtypes = [C.c_uint64, C.c_int64, C.c_int64]
+        L.orc_vote_bit.argtypes = [C.c_uint64, C.c_int64, C.c_int64]
+        L.orc_set_flip_rule.argtypes = [C.c_void_p, C.c_int]
         L.orc_create.argtypes = [C.c_int64, C.c_int, C.c_double, C.c_uint64,
                                  C.POINTER(C.c_void_p)]
         L.orc_free.argtypes = [C.c_void_p]
@@ -103,6 +105,13 @@ def flip_bit(seed: int, sweep: int, label: int) -> int:
     return int(lib().orc_flip_bit(C.c_uint64(seed), sweep, label))
 
 
+def vote_bit(seed: int, sweep: int, node: int) -> int:
+    return int(lib().orc_vote_bit(C.c_uint64(seed), sweep, node))
+
+
+FLIP_LABEL, FLIP_VOTE = 0, 1
+
+
 class Chain:
     """One Markov chain of the oracle."""
 
@@ -120,6 +129,12 @@ class Chain:
         if h is not None and h.value:
             lib().orc_free(h)
             self._h = None
+
+    def set_flip_rule(self, rule: int):
+        """FLIP_LABEL (default) or FLIP_VOTE (XOR of the nodes' votes, Sec. 3.3)."""
+        rc = lib().orc_set_flip_rule(self._h, int(rule))
+        if rc != 0:
+            raise ValueError(f"orc_set_flip_rule rc={rc}")
 
     def sizes(self):
         a, b, c, d = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()

@@ -25,6 +25,7 @@ __all__ = ["load", "Chain", "Batch", "lc_footprint", "lc_strerror", "LcError",
 SO = _build.SO
 
 LC_OK, LC_EINVAL, LC_ENOMEM, LC_ETOOLARGE, LC_ECAPACITY, LC_EDEVICE, LC_ESTATE = 0, -1, -2, -3, -4, -5, -6
+FLIP_LABEL, FLIP_VOTE = 0, 1
 
 
 class LcError(RuntimeError):
@@ -93,6 +94,7 @@ def load():
                              C.POINTER(vp)], C.c_int),
         "lc_update": ([vp, C.c_int64, C.c_int], C.c_int),
         "lc_update_noalloc": ([vp, C.c_int64, C.c_int], C.c_int),
+        "lc_set_flip_rule": ([vp, C.c_int], C.c_int),
         "lc_measure": ([vp, C.POINTER(Measurement)], C.c_int),
         "lc_last_sweep": ([vp, C.POINTER(SweepStats)], C.c_int),
         "lc_reset_measurements": ([vp], C.c_int),
@@ -305,6 +307,10 @@ class Chain:
 
     def update(self, n_sweeps: int = 1, accumulate: bool = True):
         _check(load().lc_update(self._h, int(n_sweeps), int(bool(accumulate))), "lc_update")
+
+    def set_flip_rule(self, rule: int):
+        """FLIP_LABEL (default) or FLIP_VOTE (majority-vote XOR, lc_set_flip_rule)."""
+        _check(load().lc_set_flip_rule(self._h, int(rule)), "lc_set_flip_rule")
 
     def update_noalloc(self, n_sweeps: int = 1, accumulate: bool = True):
         """lc_update_noalloc: the same sweeps with no allocation (static scratch)."""

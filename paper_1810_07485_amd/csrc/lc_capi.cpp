@@ -233,6 +233,7 @@ struct lc_chain {
   int K = 0;
   int64_t n_sites = 0, n_bonds = 0, nwin = 0, nbn = 0;
   int tile_j = 1, tile_k = 1, tile_shrink = 0;  // linking tile (spins x windows)
+  int flip_rule = LC_FLIP_LABEL;
   int64_t ntj = 1, ntk = 1;
   Mem mem;
   hipStream_t stream = nullptr;
@@ -355,6 +356,7 @@ ChainDesc make_desc(const lc_chain* c, int64_t win_base, int64_t site_base, int6
   d.sweep = c->sweep;
   d.cur = c->cur;
   d.tile_j = c->tile_j;
+  d.flip_rule = c->flip_rule;
   d.tile_k = c->tile_k;
   d.ntj = c->ntj;
   std::memcpy(d.T, c->T, sizeof(d.T));
@@ -1165,6 +1167,14 @@ int lc_update_noalloc(lc_chain* c, int64_t n_sweeps, int accumulate) {
   // holds no operators or labels of these sweeps
   if (c->own) c->own->dirty = true;
   c->last_engine = nullptr;
+  return LC_OK;
+}
+
+int lc_set_flip_rule(lc_chain* c, int rule) {
+  if (!c || (rule != LC_FLIP_LABEL && rule != LC_FLIP_VOTE)) return LC_EINVAL;
+  c->flip_rule = rule;
+  if (c->own) c->own->dirty = true;
+  if (c->batch) c->batch->eng.dirty = true;
   return LC_OK;
 }
 

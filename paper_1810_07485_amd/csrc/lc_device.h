@@ -9,7 +9,7 @@
 namespace lc {
 
 // Counter domains: the top 8 bits of counter word 1 name what a draw is for.
-enum : uint32_t { DOM_INIT = 0u, DOM_INS = 1u, DOM_FLIP = 2u, DOM_SYM = 3u };
+enum : uint32_t { DOM_INIT = 0u, DOM_INS = 1u, DOM_FLIP = 2u, DOM_SYM = 3u, DOM_VOTE = 4u };
 
 constexpr int kMaxTable = 64;  // longest Poisson threshold table
 
@@ -70,7 +70,7 @@ struct ChainDesc {
   int32_t cur;         // which of the two state buffers is current
   int32_t tile_j;      // linking tile: spins per tile
   int32_t tile_k;      //               windows per tile
-  int32_t pad;
+  int32_t flip_rule;   // 0: bit of the loop's label, 1: XOR of its nodes' votes
   int64_t ntj;         // tiles along the chain, ceil(L / tile_j)
   uint64_t T[kMaxTable];
 };

@@ -359,17 +359,26 @@ __global__ void k_chain_bases(const ChainDesc* __restrict__ descs, int nchain,
 }
 
 
-// Loop-flip bit of a chain-local label: bit (label mod 128) of the Philox
-// block (label / 128) of the FLIP stream of this sweep.
-__device__ inline uint32_t flip_bit(const ChainDesc& D, int64_t label) {
-  const uint64_t q = static_cast<uint64_t>(label) >> 7;
-  const uint32_t i = static_cast<uint32_t>(label & 127);
+// One bit per id of the 128-bit Philox blocks of a domain: bit (id mod 128)
+// of block id / 128 of this sweep.  The loop-flip bit of a chain-local label
+// (domain FLIP), or the vote of a chain-local node (domain VOTE: a loop
+// flips iff the XOR of its nodes' votes is 1, the majority-vote trick of
+// Sec. 3.3, independent of the order of the unions).
+__device__ inline uint32_t domain_bit(const ChainDesc& D, int64_t id, uint32_t dom) {
+  const uint64_t q = static_cast<uint64_t>(id) >> 7;
+  const uint32_t i = static_cast<uint32_t>(id & 127);
   const u32x4 r = philox10(D.seed, static_cast<uint32_t>(q),
-                           (DOM_FLIP << 24) | static_cast<uint32_t>((q >> 32) & 0xFFFFFFu), 0u,
+                           (dom << 24) | static_cast<uint32_t>((q >> 32) & 0xFFFFFFu), 0u,
                            D.sweep);
   const uint32_t wsel = i >> 5;
   const uint32_t word = wsel == 0 ? r.x : (wsel == 1 ? r.y : (wsel == 2 ? r.z : r.w));
   return (word >> (i & 31)) & 1u;
+}
+__device__ inline uint32_t flip_bit(const ChainDesc& D, int64_t label) {
+  return domain_bit(D, label, DOM_FLIP);
+}
+__device__ inline uint32_t vote_bit(const ChainDesc& D, int64_t node) {
+  return domain_bit(D, node, DOM_VOTE);
 }
 
 constexpr int kScanItems = 16;
@@ -596,6 +605,7 @@ struct TileCfg {
 // word of a rep holds the component's fields:
 constexpr uint32_t kRepFlag = 1u << 31;   // this node is its component's rep
 constexpr uint32_t kRepOpen = 1u << 30;   // the component leaves the tile
+constexpr uint32_t kRepVote = 1u << 29;   // XOR of the votes of a closed component (vote rule)
 constexpr uint32_t kRepSize = 0x1FFFu;    // bits 0..12: nodes of the component
 constexpr int kRepSlotShift = 13;         // bits 13..22: accumulator slot + 1
 constexpr uint32_t kRepSlotMask = 0x3FFu;
@@ -611,6 +621,7 @@ struct TileLds {
   uint8_t lbond[C::kOps];            // owned bond (local index) of each tile operator
   int64_t slot_hi[C::kSlots], slot_lo[C::kSlots];
   uint32_t slot_rep[C::kSlots];
+  uint32_t slot_vote[C::kSlots];     // XOR of the votes of a slotted component
   uint32_t tpre[kTileBonds + 1];     // first local operator of each owned bond
   int64_t tos[kTileBonds];           // first (flat) operator of each owned bond in the tile
   int64_t xsrc[C::kCross], xdst[C::kCross];
@@ -870,6 +881,10 @@ __global__ __launch_bounds__(kBlock) void k_link_tile(
       if (!open && (av & kRepSize) == 2 && (u & 1) && u + 1 < nn &&
           S.lpar[u + 1] == static_cast<uint32_t>(u)) {
         sums.add(2, (S.ltime[(u + 1) >> 1] - S.ltime[u >> 1]) >> 31);  // length 2 (t1 - t0), >> 32
+        if (D.flip_rule) {
+          const int64_t v = nb0 + 2 * tile_op(S, u >> 1) + 1 - dy.node_base;  // upper(q); lower(q + 1) = v + 1
+          if (vote_bit(D, v) ^ vote_bit(D, v + 1)) S.lpar[u] = av | kRepVote;
+        }
         continue;
       }
       const int s = atomicAdd(&S.cnt[1], 1);
@@ -878,6 +893,7 @@ __global__ __launch_bounds__(kBlock) void k_link_tile(
         S.slot_rep[s] = static_cast<uint32_t>(u);
         S.slot_hi[s] = 0;
         S.slot_lo[s] = 0;
+        S.slot_vote[s] = 0;
         if (open) atomicAdd(&S.cnt[2], 1);
       }
     }
@@ -886,7 +902,9 @@ __global__ __launch_bounds__(kBlock) void k_link_tile(
       if (tid == 0) atomicOr(flags, LC_FLAG_TILE);
       break;
     }
-    // length sums of the slotted components: lower nodes +t, upper nodes -t
+    // length sums of the slotted components: lower nodes +t, upper nodes -t;
+    // their nodes' votes under the vote rule
+    const bool votes = D.flip_rule != 0;
     for (int lo = tid; lo < nlo; lo += kBlock) {
       const uint64_t tq = S.ltime[lo];
       const uint64_t th = tq >> 32, tl = tq & 0xFFFFFFFFull;
@@ -898,6 +916,9 @@ __global__ __launch_bounds__(kBlock) void k_link_tile(
                   static_cast<unsigned long long>(hh ? 0 - th : th));
         atomicAdd(reinterpret_cast<unsigned long long*>(S.slot_lo + sl - 1),
                   static_cast<unsigned long long>(hh ? 0 - tl : tl));
+        if (votes &&
+            vote_bit(D, nb0 + 2 * tile_op(S, static_cast<uint32_t>(lo)) + hh - dy.node_base))
+          atomicXor(S.slot_vote + sl - 1, 1u);
       }
     }
     if (tid == 0) {
@@ -926,15 +947,18 @@ __global__ __launch_bounds__(kBlock) void k_link_tile(
         const int64_t f = S.base[1] + atomicAdd(&S.cnt[3], 1);
         if (f < fcap) {
           frag[4 * f + 0] = nb0 + 2 * tile_op(S, u >> 1) + (u & 1);
-          frag[4 * f + 1] = static_cast<int64_t>(size | (static_cast<uint64_t>(c) << 16));
+          frag[4 * f + 1] = static_cast<int64_t>(size | (static_cast<uint64_t>(S.slot_vote[s] & 1u) << 15) |
+                                                 (static_cast<uint64_t>(c) << 16));
           frag[4 * f + 2] = S.slot_hi[s];
           frag[4 * f + 3] = S.slot_lo[s];
         }
       } else {
         sums.add(size, loop_len32(0, static_cast<uint64_t>(S.slot_hi[s]),
                                   static_cast<uint64_t>(S.slot_lo[s])));
+        if (S.slot_vote[s] & 1u) S.lpar[u] = av | kRepVote;
       }
     }
+    __syncthreads();  // vote decisions of closed components are read below
     // parent words: the component's rep; a rep holds itself (open) or
     // kClosedRoot (finished)
     for (int lo = tid; lo < nlo; lo += kBlock) {
@@ -945,7 +969,7 @@ __global__ __launch_bounds__(kBlock) void k_link_tile(
         const uint32_t r = rep_of(static_cast<int>(u));
         const int64_t g = nb0 + 2 * q + hh;
         if (r == u)
-          parent[g] = (S.lpar[u] & kRepOpen) ? g : kClosedRoot;
+          parent[g] = (S.lpar[u] & kRepOpen) ? g : kClosedRoot + ((S.lpar[u] & kRepVote) ? 1 : 0);
         else
           parent[g] = nb0 + 2 * tile_op(S, r >> 1) + (r & 1);
       }
@@ -1222,17 +1246,19 @@ __device__ inline uint32_t wave_max_u32(uint32_t v) {
 }
 
 __device__ inline void flush_carry(unsigned long long* acc, int64_t key, uint64_t v0, uint64_t v1,
-                                   uint64_t v2) {
+                                   uint64_t v2, uint64_t v3) {
   unsigned long long* a = acc + kAccWords * key;
   atomicAdd(a + 0, static_cast<unsigned long long>(v0));
   if (v1) atomicAdd(a + 1, static_cast<unsigned long long>(v1));
   if (v2) atomicAdd(a + 2, static_cast<unsigned long long>(v2));
+  if (v3 & 1) atomicXor(a + 3, 1ull << 63);
 }
 
 // Per-loop records (before the flip) of the open loops, from their items:
 //   [0] nodes + (top nodes << 40)
 //   [1] sum of +-hi32(t), [2] sum of +-lo32(t)  over operator nodes: lower
 //       nodes count +t, upper nodes -t (two vertical segments end / start)
+//   [3] chain, bit 63: XOR of the nodes' votes (vote rule)
 // so the loop length is 2^64 tops + 2 (2^32 [1] + [2]) ticks.  A fragment
 // brings its node count and its sums; a boundary node one node (a top node
 // also 2^64 of length); every word takes plain additions (exact modulo 2^64,
@@ -1252,11 +1278,11 @@ __global__ __launch_bounds__(kBlock) void k_accum_items(
   const int64_t iters = (n + stride - 1) / stride;
   // wave carry: sums of one hot loop (wave-uniform), flushed once
   int64_t ck = -1;
-  uint64_t cv0 = 0, cv1 = 0, cv2 = 0;
+  uint64_t cv0 = 0, cv1 = 0, cv2 = 0, cv3 = 0;
   for (int64_t it = 0; it < iters; ++it) {
     const int64_t i = xcd_block() * kBlock + threadIdx.x + it * stride;
     int64_t r = -1;
-    uint64_t w0 = 0, w1 = 0, w2 = 0;
+    uint64_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;  // w3: XOR of votes (bit 0)
     if (i < n) {
       int c = 0;
       const int64_t g = item_node(i, nf, frag, bn_bases, nchain, dyn, &c);
@@ -1267,7 +1293,8 @@ __global__ __launch_bounds__(kBlock) void k_accum_items(
         atomicOr(flags, LC_FLAG_GRAPH);
         r = -1;
       } else if (i < nf) {
-        w0 = static_cast<uint64_t>(frag[4 * i + 1]) & 0xFFFFull;
+        w0 = static_cast<uint64_t>(frag[4 * i + 1]) & 0x7FFFull;
+        w3 = (static_cast<uint64_t>(frag[4 * i + 1]) >> 15) & 1u;
         w1 = static_cast<uint64_t>(frag[4 * i + 2]);
         w2 = static_cast<uint64_t>(frag[4 * i + 3]);
       } else {
@@ -1277,6 +1304,7 @@ __global__ __launch_bounds__(kBlock) void k_accum_items(
         const bool bottom = v < D.n_sites;
         w0 = 1;
         if (D.two_s == 1 || !bottom) w0 += 1ull << 40;  // a top node: + 2^64
+        if (D.flip_rule) w3 = vote_bit(D, v);
         const int64_t root = (p >= 0 ? p : g) - cb;
         if (bottom && root < D.n_sites)  // always true: the root is a bottom node
           atomicAdd(bacc + D.site_base + root,
@@ -1308,6 +1336,7 @@ __global__ __launch_bounds__(kBlock) void k_accum_items(
     w0 = __shfl(w0, src);
     w1 = __shfl(w1, src);
     w2 = __shfl(w2, src);
+    w3 = __shfl(w3, src);
     // runs of equal loops: head lanes from one ballot, segment id = heads so far
     const int64_t pkey = __shfl_up(key, 1);
     const unsigned long long heads = __ballot(lane == 0 || pkey != key);
@@ -1316,10 +1345,12 @@ __global__ __launch_bounds__(kBlock) void k_accum_items(
     for (int d = 1; d < 64; d <<= 1) {
       const int qs = __shfl_up(seg, d);
       const uint64_t q0 = __shfl_up(w0, d), q1 = __shfl_up(w1, d), q2 = __shfl_up(w2, d);
+      const uint64_t q3 = __shfl_up(w3, d);
       if (lane >= d && qs == seg) {
         w0 += q0;
         w1 += q1;
         w2 += q2;
+        w3 ^= q3;
       }
     }
     const bool last = lane == 63 || ((heads >> (lane + 1)) & 1ull);
@@ -1334,9 +1365,9 @@ __global__ __launch_bounds__(kBlock) void k_accum_items(
       const uint32_t cnt = static_cast<uint32_t>(seglen);
       const uint32_t best = wave_max_u32((cnt << 6) | static_cast<uint32_t>(lane));
       if ((best >> 6) >= 16) {
-        if (ck >= 0 && lane == 0) flush_carry(acc, ck, cv0, cv1, cv2);
+        if (ck >= 0 && lane == 0) flush_carry(acc, ck, cv0, cv1, cv2, cv3);
         ck = __shfl(key, static_cast<int>(best & 63u));
-        cv0 = cv1 = cv2 = 0;
+        cv0 = cv1 = cv2 = cv3 = 0;
         absorbed = lane == static_cast<int>(best & 63u);
         m = __ballot(absorbed);
       }
@@ -1346,15 +1377,17 @@ __global__ __launch_bounds__(kBlock) void k_accum_items(
       cv0 += __shfl(w0, sl);
       cv1 += __shfl(w1, sl);
       cv2 += __shfl(w2, sl);
+      cv3 ^= __shfl(w3, sl);
     }
     if (seg_end && !absorbed) {
       unsigned long long* a = acc + kAccWords * key;
       atomicAdd(a + 0, static_cast<unsigned long long>(w0));
       if (w1) atomicAdd(a + 1, static_cast<unsigned long long>(w1));
       if (w2) atomicAdd(a + 2, static_cast<unsigned long long>(w2));
+      if (w3 & 1) atomicXor(a + 3, 1ull << 63);
     }
   }
-  if (ck >= 0 && lane_id() == 0) flush_carry(acc, ck, cv0, cv1, cv2);
+  if (ck >= 0 && lane_id() == 0) flush_carry(acc, ck, cv0, cv1, cv2, cv3);
 }
 
 // Per-loop squares of the open loops summed into the chain statistics (the
@@ -1369,7 +1402,7 @@ __global__ __launch_bounds__(kBlock) void k_cluster_sums(
   for (int64_t i = xcd_block() * kBlock + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * kBlock) {
     const unsigned long long* a = acc + kAccWords * i;
-    sums.at(static_cast<int>(a[3]), stats, nchain);
+    sums.at(static_cast<int>(a[3] & ~(1ull << 63)), stats, nchain);
     const uint64_t sz = a[0] & ((1ull << 40) - 1), tops = a[0] >> 40;
     // the loop was counted when its root was numbered
     sums.add(sz, loop_len32(tops, a[1], a[2]), false);
@@ -1377,12 +1410,31 @@ __global__ __launch_bounds__(kBlock) void k_cluster_sums(
   sums.flush(stats, nchain);
 }
 
+// Flip decision of the loop through node g.  Label rule: the bit of its
+// label.  Vote rule: the XOR of its nodes' votes, found through the loop's
+// code -- kClosedRoot + decision for a loop finished in its tile, else the
+// record's bit 63 -- from g's word, its parent's, or the root's.
+__device__ inline uint32_t node_flip(const ChainDesc& D, int64_t node_base,
+                                     const int64_t* __restrict__ parent,
+                                     const unsigned long long* __restrict__ acc, int64_t g) {
+  if (!D.flip_rule) return flip_bit(D, node_label(parent, g) - node_base);
+  const int64_t p = parent[g];
+  int64_t code = p;
+  if (p >= 0) {
+    const int64_t pp = parent[p];
+    code = pp < 0 ? pp : parent[pp];
+  }
+  if (code <= kClosedRoot + 1) return static_cast<uint32_t>(code - kClosedRoot);
+  return static_cast<uint32_t>(acc[kAccWords * (-1 - code) + 3] >> 63);
+}
+
 // Cluster flip (step 7): the type of an operator changes when exactly one of
 // its two loops flips; kept (off-diagonal) operators are counted per window.
 __global__ __launch_bounds__(kBlock) void k_flip_ops(
     const ChainDesc* __restrict__ descs, const int64_t* __restrict__ win_bases, int nchain,
     int64_t nwin, const ChainDyn* __restrict__ dyn, const int64_t* __restrict__ opstart,
-    const int64_t* __restrict__ parent, uint8_t* __restrict__ optype, int64_t* __restrict__ kcnt,
+    const int64_t* __restrict__ parent, const unsigned long long* __restrict__ acc,
+    uint8_t* __restrict__ optype, int64_t* __restrict__ kcnt,
     unsigned long long* __restrict__ stats, const uint32_t* __restrict__ flags) {
   if (*flags) return;
   constexpr int kIdx[1] = {ST_KEPT_OUT};
@@ -1398,9 +1450,8 @@ __global__ __launch_bounds__(kBlock) void k_flip_ops(
     for (int64_t q = opstart[i]; q < opstart[i + 1]; ++q) {
       const int64_t lo = nb0 + 2 * q;
       const uint8_t v = optype[q];
-      const uint8_t ty = static_cast<uint8_t>(
-          (v & 1) ^ flip_bit(D, node_label(parent, lo) - dy.node_base) ^
-          flip_bit(D, node_label(parent, lo + 1) - dy.node_base));
+      const uint8_t ty = static_cast<uint8_t>((v & 1) ^ node_flip(D, dy.node_base, parent, acc, lo) ^
+                                              node_flip(D, dy.node_base, parent, acc, lo + 1));
       optype[q] = static_cast<uint8_t>(ty | (v & 2));
       kept += ty;
     }
@@ -1416,7 +1467,7 @@ __global__ __launch_bounds__(kBlock) void k_flip_ops(
 __global__ __launch_bounds__(kBlock) void k_flip_sites(
     const ChainDesc* __restrict__ descs, const int64_t* __restrict__ site_bases, int nchain,
     int64_t nsites, const ChainDyn* __restrict__ dyn, const int64_t* __restrict__ parent,
-    const unsigned long long* __restrict__ bacc,
+    const unsigned long long* __restrict__ acc, const unsigned long long* __restrict__ bacc,
     unsigned long long* __restrict__ stats, const uint32_t* __restrict__ flags) {
   if (*flags) return;
   constexpr int kIdx[3] = {ST_MAFTER, ST_M2, ST_N0SQ};
@@ -1428,7 +1479,8 @@ __global__ __launch_bounds__(kBlock) void k_flip_sites(
     const ChainDesc& D = descs[c];
     const int64_t x = gi - D.site_base;
     const int64_t p = parent[dyn[c].node_base + x];
-    const uint8_t s = D.s0[D.cur][x] ^ static_cast<uint8_t>(flip_bit(D, p >= 0 ? p - dyn[c].node_base : x));
+    const uint8_t s =
+        D.s0[D.cur][x] ^ static_cast<uint8_t>(node_flip(D, dyn[c].node_base, parent, acc, dyn[c].node_base + x));
     D.s0[D.cur ^ 1][x] = s;
     part.v[0] += static_cast<uint64_t>(2 * static_cast<int64_t>(s) - 1);
     if (p < 0) {  // root of its loop
@@ -1833,10 +1885,10 @@ hipError_t lc_launch_sweep(const LcSweepArgs& A, hipStream_t s) {
                      A.rcnt + nchunks, A.root_cap, A.acc, st, A.flags);
   mark(LC_PH_FLIP);
   hipLaunchKernelGGL(k_flip_ops, dim3(grid_for(A.nwin, G)), dim3(kBlock), 0, s, A.descs,
-                     A.win_bases, A.nchain, A.nwin, A.dyn, A.opstart, A.parent, A.optype,
+                     A.win_bases, A.nchain, A.nwin, A.dyn, A.opstart, A.parent, A.acc, A.optype,
                      A.kflat, st, A.flags);
   hipLaunchKernelGGL(k_flip_sites, dim3(grid_for(A.nsites, G)), dim3(kBlock), 0, s, A.descs,
-                     A.site_bases, A.nchain, A.nsites, A.dyn, A.parent, A.bacc, st, A.flags);
+                     A.site_bases, A.nchain, A.nsites, A.dyn, A.parent, A.acc, A.bacc, st, A.flags);
   // 7. next world lines
   mark(LC_PH_SCAN_KEPT);
   (void)lc_launch_scan(A.kflat, A.nwin, A.scan_tmp, s);

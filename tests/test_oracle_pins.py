@@ -376,3 +376,64 @@ def test_flip_bits_fair_and_independent(orc):
     for other in (f1, f128, fs):
         tab = np.array([[np.sum((f0 == a) & (other == b)) for b in (0, 1)] for a in (0, 1)])
         assert stats.chi2_contingency(tab, correction=False)[1] > 1e-4, tab
+
+
+# ------------------------------------------------ majority-vote flip rule ----
+def py_domain_bit(seed: int, sweep: int, ident: int, dom: int) -> int:
+    q, i = ident >> 7, ident & 127
+    words = py_philox(seed, (q & M32, (dom << 24) | ((q >> 32) & 0xFFFFFF), 0, sweep & M32))
+    return (words[i >> 5] >> (i & 31)) & 1
+
+
+def test_vote_bits_against_independent_philox(orc):
+    for seed, sweep in ((1, 0), (77, 3)):
+        for v in list(range(300)) + [1 << 33, (1 << 40) + 5]:
+            assert orc.vote_bit(seed, sweep, v) == py_domain_bit(seed, sweep, v, 4)
+
+
+@pytest.mark.parametrize("L,S,beta,seed", [(16, 0.5, 8.0, 1), (8, 1.0, 3.0, 2), (4, 4.0, 0.7, 4)])
+def test_vote_rule_flips_the_xor_of_each_loops_votes(orc, L, S, beta, seed):
+    """Sec. 3.3's majority-vote trick: a loop flips iff the XOR of its nodes'
+    votes is 1.  Checked on the oracle's exported operators and labels against
+    votes recomputed with the independent Philox and loops rebuilt by scipy."""
+    two_s = int(round(2 * S))
+    ch = orc.Chain(L, S, beta, seed)
+    ch.set_flip_rule(orc.FLIP_VOTE)
+    for _ in range(20):
+        ch.sweep()
+    for _ in range(3):
+        s0, off, kt, sw = ch.export_state()
+        st = ch.sweep()
+        b, t, ty0 = ch.export_ops()
+        lab = ch.export_labels()
+        perm = ch.export_perm() if two_s > 1 else None
+        U, V, LEN, n, nbn = wl.loop_graph(L, two_s, b, t, perm)
+        np.testing.assert_array_equal(lab, wl.min_labels(U, V, n))
+        dec = {}
+        for v in range(n):
+            dec[int(lab[v])] = dec.get(int(lab[v]), 0) ^ py_domain_bit(seed, sw, v, 4)
+        s1, off1, kt1, _ = ch.export_state()
+        key_after = set(zip(np.repeat(np.arange(len(off1) - 1), np.diff(off1)).tolist(), kt1.tolist()))
+        ty1 = np.array([(int(bb), int(tt)) in key_after for bb, tt in zip(b, t)], dtype=np.uint8)
+        for k in range(len(b)):
+            assert ty1[k] == ty0[k] ^ dec[int(lab[nbn + 2 * k])] ^ dec[int(lab[nbn + 2 * k + 1])]
+        for x in range(len(s0)):
+            assert s1[x] == s0[x] ^ dec[int(lab[x])]
+        assert st["n_kept_out"] == int(ty1.sum())
+
+
+@pytest.mark.parametrize("L,S,beta,seed,meas", [(8, 0.5, 8.0, 31, 20000), (6, 1.0, 4.0, 32, 8000)])
+def test_vote_rule_vs_exact_diagonalization(orc, L, S, beta, seed, meas):
+    """The vote rule is another Markov chain with the same stationary
+    distribution: energy and susceptibility agree with exact diagonalization."""
+    from oracle import ed
+    ref = ed.thermal(L, S, beta, vectors=False) if S == 0.5 else _golden(L, S, beta)
+    ch = orc.Chain(L, S, beta, seed)
+    ch.set_flip_rule(orc.FLIP_VOTE)
+    for _ in range(500):
+        ch.sweep()
+    st = [ch.sweep() for _ in range(meas)]
+    ser = _series(st, L, S, beta)
+    for k in ("e", "chi_u"):
+        m, e = _mean_err(ser[k])
+        assert abs(m - ref[k]) < 4 * e, (k, m, e, ref[k])
