@@ -43,6 +43,8 @@ extern "C" {
 #define ORC_DOM_FLIP 2u
 #define ORC_DOM_SYM  3u
 #define ORC_DOM_VOTE 4u
+#define ORC_DOM_SWBOND 5u  /* Swendsen-Wang bonds (sw_oracle.c) */
+#define ORC_DOM_SWFLIP 6u  /* Swendsen-Wang cluster flips */
 
 /* Loop-flip rules: the loop's own Philox bit keyed by its smallest node
  * (label), or the XOR of the votes of all its nodes (vote, Sec. 3.3). */
@@ -111,6 +113,29 @@ int orc_export_labels(const orc_chain *c, int64_t *labels, int64_t *cap);
  * perm[n_sites]: top(j,a) is joined to bottom(j, perm[2S*j+a]) -- stored as
  * the global subspin index. */
 int orc_export_perm(const orc_chain *c, int64_t *perm, int64_t *cap);
+
+/* ---- Swendsen-Wang update of the 2D Ising model (sw_oracle.c; the
+ * union-find benchmark of Sec. 4.1) -------------------------------------- */
+typedef struct orc_sw orc_sw;
+
+/* Per sweep: energy -sum_<ij> s_i s_j and magnetization sum_i s_i of the
+ * configuration the sweep starts from; active bonds; clusters; sum of the
+ * squared cluster sizes (128-bit); largest cluster. */
+typedef struct {
+    int64_t sweep, energy, magnetization, n_active, n_clusters;
+    uint64_t size2_lo, size2_hi;
+    int64_t max_size;
+} orc_sw_stats;
+
+/* floor(p 2^32) with p = 1 - exp(-2K): a bond is active iff its 32-bit
+ * draw is below it (and its spins are equal). */
+uint64_t orc_sw_threshold(double K);
+int  orc_sw_create(int64_t L, double K, uint64_t seed, orc_sw **out); /* all spins up */
+void orc_sw_free(orc_sw *c);
+int  orc_sw_sweep(orc_sw *c, orc_sw_stats *st);
+/* spins[L*L] (1 = up) now; labels[L*L] of the last sweep's clusters (each
+ * the cluster's smallest site, row-major site ids). */
+int  orc_sw_export(const orc_sw *c, uint8_t *spins, int64_t *labels);
 
 #ifdef __cplusplus
 }

@@ -17,6 +17,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SO = os.path.join(HERE, "liblc_oracle.so")
 SRC = os.path.join(HERE, "lc_oracle.c")
+SRCS = [SRC, os.path.join(HERE, "sw_oracle.c")]
 
 ORC_DOM_INIT, ORC_DOM_INS, ORC_DOM_FLIP, ORC_DOM_SYM = 0, 1, 2, 3
 
@@ -26,7 +27,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(SO):
         tmp = SO + ".tmp"
         cmd = ["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fPIC", "-shared",
-               "-Wall", "-Wextra", "-o", tmp, SRC, "-lm"]
+               "-Wall", "-Wextra", "-o", tmp, *SRCS, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, SO)
     return SO
@@ -47,6 +48,17 @@ class Stats(C.Structure):
         d = {k: getattr(self, k) for k, _ in self._fields_}
         d["sum_size2"] = d.pop("sum_size2_lo") | (d.pop("sum_size2_hi") << 64)
         d["sum_len2"] = d.pop("sum_len2_lo") | (d.pop("sum_len2_hi") << 64)
+        return d
+
+
+class SwStats(C.Structure):
+    _fields_ = [("sweep", C.c_int64), ("energy", C.c_int64), ("magnetization", C.c_int64),
+                ("n_active", C.c_int64), ("n_clusters", C.c_int64), ("size2_lo", C.c_uint64),
+                ("size2_hi", C.c_uint64), ("max_size", C.c_int64)]
+
+    def as_dict(self) -> dict:
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["size2"] = d.pop("size2_lo") | (d.pop("size2_hi") << 64)
         return d
 
 
@@ -77,6 +89,13 @@ def lib():
         L.orc_export_ops.argtypes = [C.c_void_p, p64, pu64, pu8, p64]
         L.orc_export_labels.argtypes = [C.c_void_p, p64, p64]
         L.orc_export_perm.argtypes = [C.c_void_p, p64, p64]
+        L.orc_sw_threshold.argtypes = [C.c_double]
+        L.orc_sw_threshold.restype = C.c_uint64
+        L.orc_sw_create.argtypes = [C.c_int64, C.c_double, C.c_uint64, C.POINTER(C.c_void_p)]
+        L.orc_sw_free.argtypes = [C.c_void_p]
+        L.orc_sw_free.restype = None
+        L.orc_sw_sweep.argtypes = [C.c_void_p, C.POINTER(SwStats)]
+        L.orc_sw_export.argtypes = [C.c_void_p, pu8, p64]
         _lib = L
     return _lib
 
@@ -232,3 +251,44 @@ def observables(stats_list, L: int, S: float, beta: float) -> dict:
         s_pi=(sn0 / n) / (4.0 * L),
         chi_s=beta / (4.0 * L) * (sl2 / 2.0**64 / n),
     )
+
+
+def sw_threshold(K: float) -> int:
+    return int(lib().orc_sw_threshold(float(K)))
+
+
+class SwChain:
+    """Swendsen-Wang update of the L x L Ising model (sw_oracle.c)."""
+
+    def __init__(self, L: int, K: float, seed: int):
+        self.L, self.K, self.seed = int(L), float(K), int(seed)
+        h = C.c_void_p()
+        rc = lib().orc_sw_create(self.L, self.K, C.c_uint64(self.seed), C.byref(h))
+        if rc != 0:
+            raise ValueError(f"orc_sw_create rc={rc}")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().orc_sw_free(h)
+            self._h = None
+
+    def sweep(self) -> dict:
+        st = SwStats()
+        rc = lib().orc_sw_sweep(self._h, C.byref(st))
+        if rc != 0:
+            raise RuntimeError(f"orc_sw_sweep rc={rc}")
+        return st.as_dict()
+
+    def spins(self):
+        s = np.zeros(self.L * self.L, np.uint8)
+        lib().orc_sw_export(self._h, _ptr(s, C.c_uint8), None)
+        return s
+
+    def labels(self):
+        lab = np.zeros(self.L * self.L, np.int64)
+        rc = lib().orc_sw_export(self._h, None, _ptr(lab, C.c_int64))
+        if rc != 0:
+            raise RuntimeError(f"orc_sw_export rc={rc}")
+        return lab
