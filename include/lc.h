@@ -298,6 +298,48 @@ int lc_profile(const lc_chain *c, double *ms, int n, int64_t *sweeps);
 int lc_batch_set_profiling(lc_batch *b, int on);
 int lc_batch_profile(const lc_batch *b, double *ms, int n, int64_t *sweeps);
 
+/* ---- Swendsen-Wang update of the 2D Ising model --------------------------
+ * The benchmark the paper runs its union-find on by itself (Sec. 4.1): the
+ * L x L square lattice with periodic boundaries at coupling K (energy
+ * -sum over nearest-neighbour pairs of s_i s_j, weight exp(-K E)).  One sweep
+ * activates each bond between equal spins with probability
+ * p = 1 - exp(-2K), finds the clusters of active bonds with the library's
+ * lock-free union-find, and flips every cluster with probability 1/2.
+ * Sites are numbered i = y L + x.  Random numbers: Philox4x32-10 keyed by the
+ * seed; site i draws one block at counter (i lo 32, 5 << 24 | i >> 32, 0,
+ * sweep): word 0 < T activates the bond to (x + 1 mod L, y), word 1 < T the
+ * bond to (x, y + 1 mod L), T = floor(p 2^32) from FP64 p (2^32 when p = 1);
+ * the cluster whose smallest site is c flips with bit c mod 128 of the block
+ * at counter (c / 128 lo 32, 6 << 24 | (c / 128) >> 32, 0, sweep).
+ * lc_sw_init: L in 2..2^20, K >= 0 finite (LC_EINVAL otherwise); every spin
+ * up; alloc may be NULL (hipMalloc), hip_stream may be NULL; about 33 bytes
+ * of device memory per site.  lc_sw_update runs n_sweeps sweeps on the
+ * stream and returns after they finished; the host reads the statistics once
+ * per 64 sweeps.  lc_sw_last: the most recent sweep's integers (LC_ESTATE
+ * before the first).  lc_sw_export: spins[L L] (1 = up) now and, if labels
+ * is not NULL, labels[L L] of the most recent sweep's clusters, each the
+ * cluster's smallest site (host arrays; either may be NULL).  Profiling:
+ * every sweep timed with HIP events (tile phase, cross-tile unions, rest). */
+typedef struct lc_sw lc_sw;
+typedef struct {
+  int64_t sweep;
+  int64_t energy;        /* of the configuration the sweep started from */
+  int64_t magnetization; /* sum of s_i, same configuration */
+  int64_t n_active;      /* active bonds */
+  int64_t n_clusters;
+  uint64_t size2_lo, size2_hi; /* sum over clusters of size^2, 128 bit */
+  int64_t max_size;
+} lc_sw_stats;
+int lc_sw_init(int64_t L, double K, uint64_t seed, const lc_alloc *alloc, void *hip_stream,
+               lc_sw **out);
+int lc_sw_update(lc_sw *c, int64_t n_sweeps);
+int lc_sw_last(const lc_sw *c, lc_sw_stats *out);
+int lc_sw_export(const lc_sw *c, uint8_t *spins, int64_t *labels);
+int lc_sw_set_profiling(lc_sw *c, int on);
+int lc_sw_profile(const lc_sw *c, double *ms_tiles, double *ms_cross, double *ms_rest,
+                  int64_t *sweeps);
+void lc_sw_free(lc_sw *c);
+
 /* ---- measurement probes (ceilings of this device) -----------------------
  * lc_probe_cas: random 8-byte compare-and-swap on an array of 2^log2_words
  * words (10..34), the access of a lock-free union-find hook (Sec. 3.2); about

@@ -19,7 +19,7 @@ import numpy as np
 
 from . import build as _build
 
-__all__ = ["load", "Chain", "Batch", "lc_footprint", "lc_strerror", "LcError",
+__all__ = ["load", "Chain", "Batch", "SwIsing", "lc_footprint", "lc_strerror", "LcError",
            "lc_debug_philox", "lc_debug_window_table", "SweepStats", "Measurement"]
 
 SO = _build.SO
@@ -49,6 +49,17 @@ class SweepStats(C.Structure):
         d = {k: getattr(self, k) for k, _ in self._fields_}
         d["sum_size2"] = d.pop("sum_size2_lo") | (d.pop("sum_size2_hi") << 64)
         d["sum_len2"] = d.pop("sum_len2_lo") | (d.pop("sum_len2_hi") << 64)
+        return d
+
+
+class SwStats(C.Structure):
+    _fields_ = [("sweep", C.c_int64), ("energy", C.c_int64), ("magnetization", C.c_int64),
+                ("n_active", C.c_int64), ("n_clusters", C.c_int64), ("size2_lo", C.c_uint64),
+                ("size2_hi", C.c_uint64), ("max_size", C.c_int64)]
+
+    def as_dict(self) -> dict:
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["size2"] = d.pop("size2_lo") | (d.pop("size2_hi") << 64)
         return d
 
 
@@ -127,6 +138,15 @@ def load():
         "lc_debug_philox": ([C.c_uint64, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)], C.c_int),
         "lc_debug_window_table": ([C.c_double, pi, C.POINTER(C.c_double), pu64, pi], C.c_int),
         "lc_debug_work": ([vp, p64, p64], C.c_int),
+        "lc_sw_init": ([C.c_int64, C.c_double, C.c_uint64, C.POINTER(Alloc), vp, C.POINTER(vp)],
+                       C.c_int),
+        "lc_sw_update": ([vp, C.c_int64], C.c_int),
+        "lc_sw_last": ([vp, C.POINTER(SwStats)], C.c_int),
+        "lc_sw_export": ([vp, pu8, p64], C.c_int),
+        "lc_sw_set_profiling": ([vp, C.c_int], C.c_int),
+        "lc_sw_profile": ([vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                           C.POINTER(C.c_double), p64], C.c_int),
+        "lc_sw_free": ([vp], None),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -406,6 +426,58 @@ class Chain:
         n = C.c_int64(p.size)
         _check(lib.lc_export_perm(self._h, _p(p, C.c_int64), C.byref(n)), "lc_export_perm")
         return p[:k].copy()
+
+
+class SwIsing:
+    """Swendsen-Wang update of the L x L periodic Ising model at coupling K on
+    the library's union-find (``lc_sw_init`` / ``lc_sw_update``)."""
+
+    def __init__(self, L: int, K: float, seed: int, stream=None):
+        lib = load()
+        self.L, self.K, self.seed = int(L), float(K), int(seed)
+        self._mem = _torch_memory(stream)
+        h = C.c_void_p()
+        _check(lib.lc_sw_init(self.L, self.K, C.c_uint64(self.seed), C.byref(self._mem.alloc),
+                              self._mem.handle, C.byref(h)), "lc_sw_init")
+        self._h = h
+        self._lib = lib
+        _LIVE.add(self)
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.lc_sw_free(h)
+        self._h = None
+
+    __del__ = close
+
+    def update(self, n_sweeps: int = 1):
+        _check(self._lib.lc_sw_update(self._h, int(n_sweeps)), "lc_sw_update")
+
+    def last_sweep(self) -> dict:
+        st = SwStats()
+        _check(self._lib.lc_sw_last(self._h, C.byref(st)), "lc_sw_last")
+        return st.as_dict()
+
+    def spins(self) -> np.ndarray:
+        s = np.zeros(self.L * self.L, np.uint8)
+        _check(self._lib.lc_sw_export(self._h, _p(s, C.c_uint8), None), "lc_sw_export")
+        return s
+
+    def labels(self) -> np.ndarray:
+        lab = np.zeros(self.L * self.L, np.int64)
+        _check(self._lib.lc_sw_export(self._h, None, _p(lab, C.c_int64)), "lc_sw_export")
+        return lab
+
+    def set_profiling(self, on: bool):
+        _check(self._lib.lc_sw_set_profiling(self._h, int(bool(on))), "lc_sw_set_profiling")
+
+    def profile(self) -> tuple:
+        """(ms tile phase, ms cross-tile unions, ms rest) summed, and sweeps."""
+        a, b, c, n = C.c_double(), C.c_double(), C.c_double(), C.c_int64()
+        _check(self._lib.lc_sw_profile(self._h, C.byref(a), C.byref(b), C.byref(c), C.byref(n)),
+               "lc_sw_profile")
+        return (a.value, b.value, c.value), n.value
 
 
 def slice_tables(chain, n_slices: int):

@@ -1,0 +1,89 @@
+// lc_uf.h -- lock-free union-find of the library (device side): the same
+// algorithm on parent words in HBM (uf_find / uf_union, 64-bit ids) and on
+// an LDS forest (lfind / lunion, 32-bit local indices).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#ifndef LC_FLAG_GRAPH
+#define LC_FLAG_GRAPH 256u  // a union-find word outside the graph (internal error)
+#endif
+
+namespace lc {
+
+// Union-find, lock-free: roots are hooked to the smaller root with a CAS on
+// the parent word (parent[x] <= x always, so no cycle can form; leaves never
+// become roots again, which is what makes the finds safe without locks,
+// Sec. 3.2).  Finds halve the path as they go.  The same algorithm runs on
+// the LDS forest of a linking tile (lfind / lunion, 32-bit local indices)
+// and on the parent words in HBM (uf_find / uf_union).
+// Every word met on the way must be a node id below `n` (a finished loop's
+// negative word or anything else is an inconsistent graph): the find then
+// returns -1 and the union raises LC_FLAG_GRAPH instead of reading outside
+// the parent words.
+__device__ inline int64_t uf_find(int64_t* parent, int64_t x, int64_t n) {
+  if (x < 0 || x >= n) return -1;
+  int64_t p = parent[x];
+  while (p != x) {
+    if (p < 0 || p >= n) return -1;
+    const int64_t gp = parent[p];
+    if (gp != p && gp >= 0 && gp < n) parent[x] = gp;  // path halving; gp is an ancestor of x
+    x = p;
+    p = gp;
+  }
+  return x;
+}
+
+__device__ inline void uf_union(int64_t* parent, int64_t a, int64_t b, int64_t n, uint32_t* flags) {
+  a = uf_find(parent, a, n);
+  b = uf_find(parent, b, n);
+  while (a != b) {
+    if (a < 0 || b < 0) {
+      atomicOr(flags, LC_FLAG_GRAPH);
+      return;
+    }
+    if (a < b) {
+      const int64_t t = a;
+      a = b;
+      b = t;
+    }
+    // hook root a (larger) below b (smaller)
+    const unsigned long long old =
+        atomicCAS(reinterpret_cast<unsigned long long*>(parent + a), static_cast<unsigned long long>(a),
+                  static_cast<unsigned long long>(b));
+    if (static_cast<int64_t>(old) == a) return;
+    a = uf_find(parent, static_cast<int64_t>(old), n);
+    b = uf_find(parent, b, n);
+  }
+}
+
+__device__ inline uint32_t lfind(uint32_t* lp, uint32_t x) {
+  volatile uint32_t* v = lp;
+  uint32_t p = v[x];
+  while (p != x) {
+    const uint32_t gp = v[p];
+    if (gp != p) v[x] = gp;
+    x = p;
+    p = gp;
+  }
+  return x;
+}
+
+__device__ inline void lunion(uint32_t* lp, uint32_t a, uint32_t b) {
+  a = lfind(lp, a);
+  b = lfind(lp, b);
+  while (a != b) {
+    if (a < b) {
+      const uint32_t t = a;
+      a = b;
+      b = t;
+    }
+    const uint32_t old = atomicCAS(lp + a, a, b);
+    if (old == a) return;
+    a = lfind(lp, old);
+    b = lfind(lp, b);
+  }
+}
+
+}  // namespace lc
