@@ -20,6 +20,9 @@ and as footprint-packed, autotuned batches.  --workload serve runs the
 request loop on a Poisson stream of jobs (S in {1/2, 4}, L in {1024, 4096,
 16384}, beta in {L/2, L}; sweep counts scaled by --serve-sweep-scale) with
 continuous batching, and reports p50/p99 per-sweep latency and throughput.
+--workload sw runs the paper's union-find benchmark, the Swendsen-Wang update
+of the 2D Ising model (L=8,192 periodic, K=K_c, 128 burn-in and 128 timed
+sweeps; vertices are lattice sites).
 
 Prints one JSON line: operators ("graph vertices") per second over exactly
 --steps sweeps after --warmup untimed sweeps, the per-phase HIP-event timing
@@ -130,7 +133,7 @@ PHASE_KERNELS = {
     "gen_count": ["k_gen<false>"], "gen_write": ["k_gen<true>"],
     "link_tiles": ["k_init_bnodes", "k_link_tile<1>"], "link_cross": ["k_link_cross"],
     "compress": ["k_compress_items"], "roots": ["k_roots_items"], "accum": ["k_accum_items"],
-    "cluster_sums": ["k_cluster_sums"], "flip": ["k_flip_ops", "k_flip_sites"],
+    "cluster_sums": ["k_cluster_sums"], "flip": ["k_flip_tiles", "k_flip_sites"],
     "compact": ["k_compact"],
 }
 TRAFFIC_FILES = {"medium": os.path.join(ROOT, "profiles", "hbm_traffic_L65536_beta4096.txt"),
@@ -326,6 +329,114 @@ def bench_serve(args, lc):
     print(json.dumps(out), flush=True)
 
 
+SW_KC = 0.44068679350977147  # ln(1 + sqrt 2) / 2
+SW_L = 8192
+
+
+def sw_phase_bytes(n, n_records, L):
+    """Algorithmic HBM bytes of each Swendsen-Wang kernel for one sweep of n
+    sites whose tiles left n_records local components (64 x 64-site tiles)."""
+    R, X = n_records, 2 * L * -(-L // 64)   # X: bonds leaving a tile
+    return {
+        "tiles": n + 2 * n // 64 + 8 * n + 16 * R,   # spins and halo, parent words, records
+        "cross": 2 * X + 16 * X,                     # both spins, both endpoints' parent words
+        "compress": 8 * R + 8 * R + 8 * R + 8 * R,   # record site, root walk, parent, size cleared
+        "sizes": 16 * R + 8 * R + 8 * R,             # records, parent of the site, size add
+        "roots": 8 * R + 8 * R + 8 * R,              # record site, parent, size
+        "flip": 8 * n + 8 * n + 2 * n,               # parent, label's parent, spin read and written
+    }
+
+
+def sw_cpu_baseline(budget_s=12.0):
+    """The Swendsen-Wang oracle's rate on a bounded sample: L=2048 at K_c, one
+    untimed sweep from the all-up start, then whole timed sweeps up to about
+    budget_s seconds.  Single-threaded C."""
+    from oracle import oracle
+
+    L = 2048
+    o = oracle.SwChain(L, SW_KC, 1)
+    o.sweep()
+    k, t0 = 0, time.perf_counter()
+    while True:
+        o.sweep()
+        k += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    model, ncpu = host_cpu()
+    return {"value": k * L * L / el, "unit": "vertices/s", "cores": 1, "kind": "oracle",
+            "cpu_model": model, "host_cores": ncpu,
+            "sample": f"oracle Swendsen-Wang sweeps 1..{k} of an L={L} lattice at K_c from the "
+                      f"all-up start (same coupling, fewer sites): {k * L * L} site updates in "
+                      f"{el:.1f} s, single-threaded C on one core of {ncpu} ({model})"}
+
+
+def bench_sw(args, lc):
+    """Swendsen-Wang 2D Ising on the library's union-find (the paper's
+    union-find benchmark): L=8192 periodic, K=K_c, seed 1."""
+    import torch
+
+    g = lc.SwIsing(SW_L, SW_KC, 1)
+    g.update(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.update(args.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    last = g.last_sweep()
+    n = SW_L * SW_L
+    g.set_profiling(True)
+    E, C2 = [], []
+    for _ in range(args.profile_sweeps):
+        g.update(1)
+        st = g.last_sweep()
+        E.append(st["energy"] / n)
+        C2.append(st["size2"] / n)
+    prof, nsw = g.profile()
+    g.set_profiling(False)
+    R = g.work()
+    pb = sw_phase_bytes(n, R, SW_L)
+    phase_ms = {k: v / nsw for k, v in prof.items()}
+    dom = max(phase_ms, key=phase_ms.get)
+    achieved = pb[dom] / (phase_ms[dom] * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": n * args.steps / el,
+        "unit": "vertices/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": f"Swendsen-Wang 2D Ising L={SW_L} periodic, K=K_c, seed 1, all-up "
+                               f"start, {args.warmup} burn-in + {args.steps} timed sweeps "
+                               "(vertices = lattice sites)", "L": SW_L, "K": SW_KC},
+        "sweeps_per_s": args.steps / el,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": pb[dom], "avg_ms": phase_ms[dom],
+                     "timing": f"HIP events around each kernel on the library stream, {nsw} "
+                               "directly launched sweeps after the timed region"},
+        "path_bytes_per_sweep": sum(pb.values()),
+        "hbm_gbs_algorithmic": sum(pb.values()) * args.steps / el / 1e9,
+        "work": {"tile_components_per_site": R / n},
+        "phase_ms": phase_ms,
+        "profiled_ms_per_sweep": sum(phase_ms.values()),
+        "observables": {"e_per_site": sum(E) / len(E), "mean_cluster_size": sum(C2) / len(C2),
+                        "last_timed_sweep": last["sweep"],
+                        "note": "means over the profiled sweeps after the timed region"},
+    }
+    g.close()
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = sw_cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -336,9 +447,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ceilings", action="store_true",
                     help="skip the random-CAS and copy probes")
-    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["batch", "serve"], default="largest",
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["batch", "serve", "sw"],
+                    default="largest",
                     help="largest: L=262144 beta=16384 (default); medium: L=65536 beta=4096; "
-                         "split: S=4 L=4096 beta=2048; batch: 512 chains; serve: request loop")
+                         "split: S=4 L=4096 beta=2048; batch: 512 chains; serve: request loop; "
+                         "sw: Swendsen-Wang 2D Ising L=8192 at K_c")
     ap.add_argument("--calibrate-atomics", action="store_true",
                     help="only measure the random-CAS and copy ceilings and exit")
     ap.add_argument("--profile-sweeps", type=int, default=None,
@@ -350,9 +463,9 @@ def main():
     ap.add_argument("--serve-sweep-scale", type=float, default=0.1)
     args = ap.parse_args()
     dflt = {"medium": (20, 10), "largest": (10, 4), "split": (5, 4), "batch": (3, 2),
-            "serve": (0, 0)}[args.workload]
+            "serve": (0, 0), "sw": (128, 128)}[args.workload]
     if args.profile_sweeps is None:
-        args.profile_sweeps = 10 if args.workload == "medium" else 2
+        args.profile_sweeps = {"medium": 10, "sw": 32}.get(args.workload, 2)
     if args.steps is None:
         args.steps = dflt[0]
     if args.warmup is None:
@@ -382,6 +495,9 @@ def main():
         return
     if args.workload == "serve":
         bench_serve(args, lc)
+        return
+    if args.workload == "sw":
+        bench_sw(args, lc)
         return
     w = WORKLOADS[args.workload]
     chain = lc.Chain(w["L"], w["S"], w["beta"], w["seed"])

@@ -319,7 +319,12 @@ int lc_batch_profile(const lc_batch *b, double *ms, int n, int64_t *sweeps);
  * before the first).  lc_sw_export: spins[L L] (1 = up) now and, if labels
  * is not NULL, labels[L L] of the most recent sweep's clusters, each the
  * cluster's smallest site (host arrays; either may be NULL).  Profiling:
- * every sweep timed with HIP events (tile phase, cross-tile unions, rest). */
+ * with it on, lc_sw_update synchronises after every sweep and times each of
+ * its lc_sw_phase_count() kernels (names from lc_sw_phase_name) with HIP
+ * events; lc_sw_profile returns their summed milliseconds (n >= the phase
+ * count) and the sweep count.  lc_sw_work: tile-local components of the most
+ * recent sweep (the records the global phase reads; synchronous device
+ * read, LC_ESTATE before the first sweep). */
 typedef struct lc_sw lc_sw;
 typedef struct {
   int64_t sweep;
@@ -336,8 +341,10 @@ int lc_sw_update(lc_sw *c, int64_t n_sweeps);
 int lc_sw_last(const lc_sw *c, lc_sw_stats *out);
 int lc_sw_export(const lc_sw *c, uint8_t *spins, int64_t *labels);
 int lc_sw_set_profiling(lc_sw *c, int on);
-int lc_sw_profile(const lc_sw *c, double *ms_tiles, double *ms_cross, double *ms_rest,
-                  int64_t *sweeps);
+int lc_sw_phase_count(void);
+const char *lc_sw_phase_name(int phase);
+int lc_sw_profile(const lc_sw *c, double *ms, int n, int64_t *sweeps);
+int lc_sw_work(const lc_sw *c, int64_t *n_records);
 void lc_sw_free(lc_sw *c);
 
 /* ---- measurement probes (ceilings of this device) -----------------------

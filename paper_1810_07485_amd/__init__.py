@@ -144,8 +144,10 @@ def load():
         "lc_sw_last": ([vp, C.POINTER(SwStats)], C.c_int),
         "lc_sw_export": ([vp, pu8, p64], C.c_int),
         "lc_sw_set_profiling": ([vp, C.c_int], C.c_int),
-        "lc_sw_profile": ([vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
-                           C.POINTER(C.c_double), p64], C.c_int),
+        "lc_sw_phase_count": ([], C.c_int),
+        "lc_sw_phase_name": ([C.c_int], C.c_char_p),
+        "lc_sw_profile": ([vp, C.POINTER(C.c_double), C.c_int, p64], C.c_int),
+        "lc_sw_work": ([vp, p64], C.c_int),
         "lc_sw_free": ([vp], None),
     }
     for name, (args, res) in sig.items():
@@ -473,11 +475,18 @@ class SwIsing:
         _check(self._lib.lc_sw_set_profiling(self._h, int(bool(on))), "lc_sw_set_profiling")
 
     def profile(self) -> tuple:
-        """(ms tile phase, ms cross-tile unions, ms rest) summed, and sweeps."""
-        a, b, c, n = C.c_double(), C.c_double(), C.c_double(), C.c_int64()
-        _check(self._lib.lc_sw_profile(self._h, C.byref(a), C.byref(b), C.byref(c), C.byref(n)),
-               "lc_sw_profile")
-        return (a.value, b.value, c.value), n.value
+        """({kernel phase: summed ms}, profiled sweeps)."""
+        lib = self._lib
+        k = lib.lc_sw_phase_count()
+        ms, n = (C.c_double * k)(), C.c_int64()
+        _check(lib.lc_sw_profile(self._h, ms, k, C.byref(n)), "lc_sw_profile")
+        return {lib.lc_sw_phase_name(i).decode(): ms[i] for i in range(k)}, n.value
+
+    def work(self) -> int:
+        """Tile-local components (records) of the most recent sweep."""
+        v = C.c_int64()
+        _check(self._lib.lc_sw_work(self._h, C.byref(v)), "lc_sw_work")
+        return v.value
 
 
 def slice_tables(chain, n_slices: int):

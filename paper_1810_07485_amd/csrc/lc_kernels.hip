@@ -504,7 +504,9 @@ struct LoopSums {
 // smallest node (rep), its size, and whether it is open (a node with fewer
 // than two local edges: the loop continues outside the tile).  A closed
 // component is a whole loop: the tile finishes it -- loop count, size^2,
-// length^2 into the chain statistics, its rep gets kClosedRoot -- without
+// length^2 into the chain statistics, its rep gets kClosedRoot plus the
+// loop's flip decision (the bit of its label, or the XOR of its nodes'
+// votes under the vote rule) -- without
 // any global work (closed two-node loops directly from the two times, larger
 // ones through an LDS accumulator slot).  An open component is a fragment:
 // its rep, size and length sums go to the fragment list, which is all the
@@ -531,7 +533,7 @@ struct TileCfg {
 // word of a rep holds the component's fields:
 constexpr uint32_t kRepFlag = 1u << 31;   // this node is its component's rep
 constexpr uint32_t kRepOpen = 1u << 30;   // the component leaves the tile
-constexpr uint32_t kRepVote = 1u << 29;   // XOR of the votes of a closed component (vote rule)
+constexpr uint32_t kRepFlip = 1u << 29;   // flip decision of a closed component
 constexpr uint32_t kRepSize = 0x1FFFu;    // bits 0..12: nodes of the component
 constexpr int kRepSlotShift = 13;         // bits 13..22: accumulator slot + 1
 constexpr uint32_t kRepSlotMask = 0x3FFu;
@@ -541,6 +543,7 @@ struct TileLds {
   using C = TileCfg<TS>;
   static_assert(C::kNodes <= static_cast<int>(kRepSize), "component size field");
   static_assert(C::kSlots < static_cast<int>(kRepSlotMask), "slot field");
+  static_assert(C::kNodes / 2 <= 2 * C::kOps, "closed-component list fits the times' LDS");
   uint32_t lpar[C::kNodes];          // local forest, then reps and their fields
   uint32_t deg[C::kNodes / 16];      // 2-bit counts of the edges of each node inside the tile
   uint64_t ltime[C::kOps];           // times of the tile's operators
@@ -554,6 +557,7 @@ struct TileLds {
   int64_t scan[kWaves + 1];
   int64_t base[2];                   // reserved positions: cross edges, fragments
   int cnt[4];                        // staged cross edges, slots, open slots, fragment cursor
+  int ncl;                           // closed components whose flip decision is drawn last
   uint32_t fl;
 };
 
@@ -750,6 +754,7 @@ __global__ __launch_bounds__(kBlock) void k_link_tile(
     if (tid == 0) {
       S.tpre[nbt] = static_cast<uint32_t>(total);
       S.cnt[0] = S.cnt[1] = S.cnt[2] = S.cnt[3] = 0;
+      S.ncl = 0;
     }
     const int nlo = static_cast<int>(total);
     const int nn = 2 * nlo;
@@ -807,11 +812,7 @@ __global__ __launch_bounds__(kBlock) void k_link_tile(
       if (!open && (av & kRepSize) == 2 && (u & 1) && u + 1 < nn &&
           S.lpar[u + 1] == static_cast<uint32_t>(u)) {
         sums.add(2, (S.ltime[(u + 1) >> 1] - S.ltime[u >> 1]) >> 31);  // length 2 (t1 - t0), >> 32
-        if (D.flip_rule) {
-          const int64_t v = nb0 + 2 * tile_op(S, u >> 1) + 1 - dy.node_base;  // upper(q); lower(q + 1) = v + 1
-          if (vote_bit(D, v) ^ vote_bit(D, v + 1)) S.lpar[u] = av | kRepVote;
-        }
-        continue;
+        continue;  // its flip decision is drawn below
       }
       const int s = atomicAdd(&S.cnt[1], 1);
       if (s < C::kSlots) {
@@ -881,10 +882,29 @@ __global__ __launch_bounds__(kBlock) void k_link_tile(
       } else {
         sums.add(size, loop_len32(0, static_cast<uint64_t>(S.slot_hi[s]),
                                   static_cast<uint64_t>(S.slot_lo[s])));
-        if (S.slot_vote[s] & 1u) S.lpar[u] = av | kRepVote;
+        if (votes && (S.slot_vote[s] & 1u)) S.lpar[u] = av | kRepFlip;
       }
     }
-    __syncthreads();  // vote decisions of closed components are read below
+    __syncthreads();
+    // flip decisions still to draw: every closed component's under the label
+    // rule (the bit of its rep, its smallest node), the two-node loops' under
+    // the vote rule (the XOR of their two nodes' votes).  Listed first, so
+    // that the draws fill whole waves; the list reuses the times' LDS.
+    uint32_t* const clist = reinterpret_cast<uint32_t*>(S.ltime);
+    for (int u = tid; u < nn; u += kBlock) {
+      const uint32_t av = S.lpar[u];
+      if ((av & kRepFlag) && !(av & kRepOpen) &&
+          (!votes || ((av >> kRepSlotShift) & kRepSlotMask) == 0))
+        clist[atomicAdd(&S.ncl, 1)] = static_cast<uint32_t>(u);
+    }
+    __syncthreads();
+    for (int k = tid; k < S.ncl; k += kBlock) {
+      const uint32_t u = clist[k];
+      const int64_t v = nb0 + 2 * tile_op(S, u >> 1) + (u & 1) - dy.node_base;
+      // two-node loop: v is the upper node of an operator, v + 1 the lower of the next
+      if (votes ? (vote_bit(D, v) ^ vote_bit(D, v + 1)) : flip_bit(D, v)) S.lpar[u] |= kRepFlip;
+    }
+    __syncthreads();  // flip decisions of closed components are read below
     // parent words: the component's rep; a rep holds itself (open) or
     // kClosedRoot (finished)
     for (int lo = tid; lo < nlo; lo += kBlock) {
@@ -895,7 +915,7 @@ __global__ __launch_bounds__(kBlock) void k_link_tile(
         const uint32_t r = rep_of(static_cast<int>(u));
         const int64_t g = nb0 + 2 * q + hh;
         if (r == u)
-          parent[g] = (S.lpar[u] & kRepOpen) ? g : kClosedRoot + ((S.lpar[u] & kRepVote) ? 1 : 0);
+          parent[g] = (S.lpar[u] & kRepOpen) ? g : kClosedRoot + ((S.lpar[u] & kRepFlip) ? 1 : 0);
         else
           parent[g] = nb0 + 2 * tile_op(S, r >> 1) + (r & 1);
       }
@@ -1033,17 +1053,6 @@ __device__ inline int64_t items_count(const unsigned long long* __restrict__ dyn
   return *nf + nbn;
 }
 
-// Loop label of node g: its loop's smallest node.  A node whose parent word
-// is negative is that node (a loop code, or kClosedRoot); otherwise its
-// parent p is a rep, a boundary node or the root, and p's word is the root
-// (items are fully compressed) or negative (p is the root).
-__device__ inline int64_t node_label(const int64_t* __restrict__ parent, int64_t g) {
-  const int64_t p = parent[g];
-  if (p < 0) return g;
-  const int64_t pp = parent[p];
-  return pp >= 0 ? pp : p;
-}
-
 // Full path compression of the items: parent = root (smallest node of the
 // loop).  Roots are counted per chunk of 4,096 items (each wave covers 64
 // consecutive items of one chunk): rcnt feeds the numbering of the loops.
@@ -1152,7 +1161,10 @@ __global__ __launch_bounds__(kBlock) void k_roots_items(
         a[0] = 0;
         a[1] = 0;
         a[2] = 0;
-        a[3] = static_cast<unsigned long long>(c);
+        // the loop's label is its root: its flip bit now (label rule); the
+        // vote rule XORs the nodes' votes into bit 63 later
+        a[3] = static_cast<unsigned long long>(c) |
+               (D.flip_rule ? 0ull : static_cast<unsigned long long>(flip_bit(D, v)) << 63);
         if (v < D.n_sites) bacc[D.site_base + v] = 0;
       }
       idx += tot;
@@ -1184,7 +1196,8 @@ __device__ inline void flush_carry(unsigned long long* acc, int64_t key, uint64_
 //   [0] nodes + (top nodes << 40)
 //   [1] sum of +-hi32(t), [2] sum of +-lo32(t)  over operator nodes: lower
 //       nodes count +t, upper nodes -t (two vertical segments end / start)
-//   [3] chain, bit 63: XOR of the nodes' votes (vote rule)
+//   [3] chain, bit 63: the loop's flip decision -- the bit of its label
+//       (set when the root is numbered), or the XOR of its nodes' votes
 // so the loop length is 2^64 tops + 2 (2^32 [1] + [2]) ticks.  A fragment
 // brings its node count and its sums; a boundary node one node (a top node
 // also 2^64 of length); every word takes plain additions (exact modulo 2^64,
@@ -1336,14 +1349,13 @@ __global__ __launch_bounds__(kBlock) void k_cluster_sums(
   sums.flush(stats, nchain);
 }
 
-// Flip decision of the loop through node g.  Label rule: the bit of its
-// label.  Vote rule: the XOR of its nodes' votes, found through the loop's
-// code -- kClosedRoot + decision for a loop finished in its tile, else the
-// record's bit 63 -- from g's word, its parent's, or the root's.
-__device__ inline uint32_t node_flip(const ChainDesc& D, int64_t node_base,
-                                     const int64_t* __restrict__ parent,
+// Flip decision of the loop through node g, found through the loop's code
+// -- kClosedRoot + decision for a loop finished in its tile, else the
+// record's bit 63 -- from g's word, its rep's, or the root's.  The decision
+// was taken once per loop (label rule: the bit of its smallest node; vote
+// rule: the XOR of its nodes' votes).
+__device__ inline uint32_t node_flip(const int64_t* __restrict__ parent,
                                      const unsigned long long* __restrict__ acc, int64_t g) {
-  if (!D.flip_rule) return flip_bit(D, node_label(parent, g) - node_base);
   const int64_t p = parent[g];
   int64_t code = p;
   if (p >= 0) {
@@ -1356,33 +1368,107 @@ __device__ inline uint32_t node_flip(const ChainDesc& D, int64_t node_base,
 
 // Cluster flip (step 7): the type of an operator changes when exactly one of
 // its two loops flips; kept (off-diagonal) operators are counted per window.
-__global__ __launch_bounds__(kBlock) void k_flip_ops(
-    const ChainDesc* __restrict__ descs, const int64_t* __restrict__ win_bases, int nchain,
-    int64_t nwin, const ChainDyn* __restrict__ dyn, const int64_t* __restrict__ opstart,
-    const int64_t* __restrict__ parent, const unsigned long long* __restrict__ acc,
-    uint8_t* __restrict__ optype, int64_t* __restrict__ kcnt,
-    unsigned long long* __restrict__ stats, const uint32_t* __restrict__ flags) {
-  if (*flags) return;
+// The operators are taken tile by tile (the linking tiles: bonds x windows),
+// one workgroup per tile and one thread per operator, so the reads of the
+// operators' words are coalesced along each bond's run and the lookups of
+// reps (always in the node's own tile) and of the roots of long loops
+// (shared by many nodes) hit lines the workgroup has just read.  Kept
+// operators are counted per window in LDS through an operator -> window map.
+constexpr int kFlipWin = LC_TILE_BONDS * LC_MAX_TS;  // windows of a tile: its bonds x windows <= 256 TS
+
+__global__ __launch_bounds__(kBlock) void k_flip_tiles(
+    const ChainDesc* __restrict__ descs, const ChainDyn* __restrict__ dyn, int nchain,
+    const int* __restrict__ grp_chain, const int64_t* __restrict__ grp_tile_base, int ngrp,
+    int64_t ntiles, const int64_t* __restrict__ opstart, const int64_t* __restrict__ parent,
+    const unsigned long long* __restrict__ acc, uint8_t* __restrict__ optype,
+    int64_t* __restrict__ kcnt, unsigned long long* __restrict__ stats, uint32_t* __restrict__ flags) {
+  __shared__ uint32_t wstart[kFlipWin + 1];   // first local operator of each window
+  __shared__ uint32_t wkept[kFlipWin];
+  __shared__ uint16_t wop[LC_TILE_OPS];       // window of each local operator
+  __shared__ int64_t bfirst[kTileBonds];      // first flat operator of each bond's run
+  __shared__ int64_t scan[kWaves + 1];
+  __shared__ uint32_t fl;
+  const int tid = threadIdx.x;
+  if (tid == 0) fl = *flags;
+  __syncthreads();
+  if (fl) return;
   constexpr int kIdx[1] = {ST_KEPT_OUT};
   Partial<1> part;
-  for (int64_t i = xcd_block() * kBlock + threadIdx.x; i < nwin;
-       i += static_cast<int64_t>(gridDim.x) * kBlock) {
-    const int c = chain_of(win_bases, nchain, i);
+  for (int64_t t = xcd_block(); t < ntiles; t += gridDim.x) {
+    const int p = chain_of(grp_tile_base, ngrp, t);
+    const int c = grp_chain[p];
     part.at(c, stats, nchain, kIdx);
     const ChainDesc& D = descs[c];
     const ChainDyn dy = dyn[c];
+    const int64_t lt = t - grp_tile_base[p];
+    const int64_t W = int64_t(1) << D.w;
+    const int64_t tj = lt % D.ntj, tk = lt / D.ntj;
+    const int64_t j0 = tj * D.tile_j, k0 = tk * D.tile_k;
+    const int nj = static_cast<int>(min(static_cast<int64_t>(D.tile_j), D.L - j0));
+    const int nk = static_cast<int>(min(static_cast<int64_t>(D.tile_k), W - k0));
+    const int64_t B0 = j0 * D.two_s * D.two_s;
+    const int nbt = nj * D.two_s * D.two_s;
+    const int nwt = nbt * nk;
     const int64_t nb0 = dy.node_base + D.nbn - 2 * dy.op_base;
-    uint64_t kept = 0;
-    for (int64_t q = opstart[i]; q < opstart[i + 1]; ++q) {
-      const int64_t lo = nb0 + 2 * q;
-      const uint8_t v = optype[q];
-      const uint8_t ty = static_cast<uint8_t>((v & 1) ^ node_flip(D, dy.node_base, parent, acc, lo) ^
-                                              node_flip(D, dy.node_base, parent, acc, lo + 1));
-      optype[q] = static_cast<uint8_t>(ty | (v & 2));
-      kept += ty;
+    // the linking of these tiles succeeded, so they fit; checked all the same
+    if (nbt > kTileBonds || nwt > kFlipWin) {  // block-uniform
+      if (tid == 0) atomicOr(flags, LC_FLAG_TILE);
+      break;
     }
-    kcnt[i] = static_cast<int64_t>(kept);
-    part.v[0] += kept;
+    // windows in (bond, window) order are the tile's operators in local order;
+    // each thread scans a contiguous chunk of them
+    const int per = (nwt + kBlock - 1) / kBlock;
+    int64_t cnt = 0;
+    for (int m = 0; m < per; ++m) {
+      const int wi = tid * per + m;
+      if (wi < nwt) {
+        const int lb = wi / nk, kk = wi - lb * nk;
+        const int64_t i = D.win_base + (B0 + lb) * W + k0 + kk;
+        const int64_t a = opstart[i];
+        cnt += opstart[i + 1] - a;
+        if (kk == 0) bfirst[lb] = a;
+      }
+    }
+    int64_t total;
+    int64_t run = block_exclusive_scan(cnt, scan, total);
+    if (total > LC_TILE_OPS) {  // block-uniform
+      if (tid == 0) atomicOr(flags, LC_FLAG_TILE);
+      break;
+    }
+    for (int m = 0; m < per; ++m) {
+      const int wi = tid * per + m;
+      if (wi < nwt) {
+        const int lb = wi / nk, kk = wi - lb * nk;
+        const int64_t i = D.win_base + (B0 + lb) * W + k0 + kk;
+        wstart[wi] = static_cast<uint32_t>(run);
+        wkept[wi] = 0;
+        run += opstart[i + 1] - opstart[i];
+      }
+    }
+    if (tid == 0) wstart[nwt] = static_cast<uint32_t>(total);
+    __syncthreads();
+    for (int wi = tid; wi < nwt; wi += kBlock)
+      for (uint32_t lo = wstart[wi]; lo < wstart[wi + 1]; ++lo) wop[lo] = static_cast<uint16_t>(wi);
+    __syncthreads();
+    const int nlo = static_cast<int>(total);
+    for (int lo = tid; lo < nlo; lo += kBlock) {
+      const int wi = wop[lo];
+      const int lb = wi / nk;
+      const int64_t q = bfirst[lb] + (lo - static_cast<int64_t>(wstart[lb * nk]));
+      const int64_t g = nb0 + 2 * q;
+      const uint8_t v = optype[q];
+      const uint8_t ty = static_cast<uint8_t>((v & 1) ^ node_flip(parent, acc, g) ^ node_flip(parent, acc, g + 1));
+      optype[q] = static_cast<uint8_t>(ty | (v & 2));
+      if (ty) atomicAdd(wkept + wi, 1u);
+    }
+    __syncthreads();
+    for (int wi = tid; wi < nwt; wi += kBlock) {
+      const int lb = wi / nk, kk = wi - lb * nk;
+      const uint32_t k = wkept[wi];
+      kcnt[D.win_base + (B0 + lb) * W + k0 + kk] = k;
+      part.v[0] += k;
+    }
+    __syncthreads();  // the LDS is reused by the next tile
   }
   part.flush(stats, nchain, kIdx);
 }
@@ -1406,7 +1492,7 @@ __global__ __launch_bounds__(kBlock) void k_flip_sites(
     const int64_t x = gi - D.site_base;
     const int64_t p = parent[dyn[c].node_base + x];
     const uint8_t s =
-        D.s0[D.cur][x] ^ static_cast<uint8_t>(node_flip(D, dyn[c].node_base, parent, acc, dyn[c].node_base + x));
+        D.s0[D.cur][x] ^ static_cast<uint8_t>(node_flip(parent, acc, dyn[c].node_base + x));
     D.s0[D.cur ^ 1][x] = s;
     part.v[0] += static_cast<uint64_t>(2 * static_cast<int64_t>(s) - 1);
     if (p < 0) {  // root of its loop
@@ -1810,9 +1896,13 @@ hipError_t lc_launch_sweep(const LcSweepArgs& A, hipStream_t s) {
   hipLaunchKernelGGL(k_cluster_sums, dim3(G < 2048 ? G : 2048), dim3(kBlock), 0, s, A.nchain,
                      A.rcnt + nchunks, A.root_cap, A.acc, st, A.flags);
   mark(LC_PH_FLIP);
-  hipLaunchKernelGGL(k_flip_ops, dim3(grid_for(A.nwin, G)), dim3(kBlock), 0, s, A.descs,
-                     A.win_bases, A.nchain, A.nwin, A.dyn, A.opstart, A.parent, A.acc, A.optype,
-                     A.kflat, st, A.flags);
+  for (int gi = 0; gi < A.ngroups; ++gi) {
+    const LcTileGroup& g = A.groups[gi];
+    const int grid = static_cast<int>(g.ntiles < G ? (g.ntiles > 0 ? g.ntiles : 1) : G);
+    hipLaunchKernelGGL(k_flip_tiles, dim3(grid), dim3(kBlock), 0, s, A.descs, A.dyn, A.nchain,
+                       A.grp_chain + g.offset, A.grp_tile_base + g.offset, g.nchain, g.ntiles,
+                       A.opstart, A.parent, A.acc, A.optype, A.kflat, st, A.flags);
+  }
   hipLaunchKernelGGL(k_flip_sites, dim3(grid_for(A.nsites, G)), dim3(kBlock), 0, s, A.descs,
                      A.site_bases, A.nchain, A.nsites, A.dyn, A.parent, A.acc, A.bacc, st, A.flags);
   // 7. next world lines

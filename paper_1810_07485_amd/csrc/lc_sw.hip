@@ -43,6 +43,7 @@ constexpr int kT = 64;               // tile side
 constexpr int kTile = kT * kT;       // sites per tile
 constexpr int kSwBlock = 256;
 constexpr int kRing = 64;            // sweeps per host synchronisation
+constexpr int kSwPhases = 6;         // timed kernels of a sweep
 
 enum SwStat { SW_E = 0, SW_M, SW_ACT, SW_NCL, SW_S2LO, SW_S2HI, SW_MAX, SW_FLAGS, SW_WORDS };
 
@@ -53,7 +54,7 @@ struct SwDev {
   uint32_t sweep;
   uint8_t* spin;           // n, 1 = up
   int64_t* parent;         // n
-  int32_t* size;           // n: cluster size at its smallest site
+  unsigned long long* size;  // n: cluster size at its smallest site
   int64_t* rec;            // 2 n: (smallest site of a tile component, size)
   unsigned long long* nrec;
   unsigned long long* st;  // SW_WORDS
@@ -206,11 +207,36 @@ __global__ __launch_bounds__(kSwBlock) void k_sw_compress(SwDev S) {
   }
 }
 
+// Cluster sizes: every record adds its tile component's size at its
+// cluster's smallest site.  Near K_c one cluster spans most tiles, and its
+// records would all add to one word: a wave first sums the records of the
+// cluster of its first pending lane (a few rounds), then the rest add
+// alone.
+constexpr int kSizeRounds = 4;
+
 __global__ __launch_bounds__(kSwBlock) void k_sw_sizes(SwDev S) {
   const int64_t nr = static_cast<int64_t>(*S.nrec);
-  for (int64_t k = static_cast<int64_t>(blockIdx.x) * kSwBlock + threadIdx.x; k < nr;
-       k += static_cast<int64_t>(gridDim.x) * kSwBlock)
-    atomicAdd(S.size + S.parent[S.rec[2 * k]], static_cast<int32_t>(S.rec[2 * k + 1]));
+  const int lane = __lane_id();
+  for (int64_t base = static_cast<int64_t>(blockIdx.x) * kSwBlock; base < nr;
+       base += static_cast<int64_t>(gridDim.x) * kSwBlock) {
+    const int64_t k = base + threadIdx.x;
+    bool pending = k < nr;
+    const int64_t key = pending ? S.parent[S.rec[2 * k]] : -1;
+    const uint32_t val = pending ? static_cast<uint32_t>(S.rec[2 * k + 1]) : 0u;
+#pragma unroll
+    for (int r = 0; r < kSizeRounds; ++r) {
+      const unsigned long long m = __ballot(pending);
+      if (!m) break;  // wave-uniform
+      const int lead = __ffsll(static_cast<long long>(m)) - 1;
+      const int64_t k0 = __shfl(key, lead);
+      const bool mine = pending && key == k0;
+      uint32_t v = mine ? val : 0u;  // <= 64 * 4096
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+      if (lane == lead) atomicAdd(S.size + k0, static_cast<unsigned long long>(v));
+      pending = pending && !mine;
+    }
+    if (pending) atomicAdd(S.size + key, static_cast<unsigned long long>(val));
+  }
 }
 
 __global__ __launch_bounds__(kSwBlock) void k_sw_roots(SwDev S) {
@@ -220,11 +246,11 @@ __global__ __launch_bounds__(kSwBlock) void k_sw_roots(SwDev S) {
        k += static_cast<int64_t>(gridDim.x) * kSwBlock) {
     const int64_t g = S.rec[2 * k];
     if (S.parent[g] != g) continue;  // not a cluster's smallest site
-    const uint64_t sz = static_cast<uint64_t>(S.size[g]);
+    const uint64_t sz = S.size[g];
     cnt += 1;
-    const uint64_t q = sz * sz;  // sizes < 2^32
+    const uint64_t q = sz * sz, qh = __umul64hi(sz, sz);
     s2lo += q;
-    s2hi += s2lo < q ? 1u : 0u;
+    s2hi += qh + (s2lo < q ? 1u : 0u);
     mx = sz > mx ? sz : mx;
   }
   for (int o = 32; o > 0; o >>= 1) {
@@ -277,12 +303,12 @@ struct lc_sw {
   bool user = false;
   uint8_t* spin = nullptr;
   int64_t* parent = nullptr;
-  int32_t* size = nullptr;
+  unsigned long long* size = nullptr;
   int64_t* rec = nullptr;
   unsigned long long* dev = nullptr;  // nrec, stats, ring
   lc_sw_stats last{};
   bool has_last = false;
-  double phase_ms[3] = {0, 0, 0};     // tiles, cross unions, rest (profiling)
+  double phase_ms[kSwPhases] = {};   // per kernel, summed (profiling)
   int64_t prof_sweeps = 0;
   bool profiling = false;
 };
@@ -346,7 +372,7 @@ int lc_sw_init(int64_t L, double K, uint64_t seed, const lc_alloc* alloc, void* 
   }
   c->spin = static_cast<uint8_t*>(sw_get(c, c->n));
   c->parent = static_cast<int64_t*>(sw_get(c, c->n * sizeof(int64_t)));
-  c->size = static_cast<int32_t*>(sw_get(c, c->n * sizeof(int32_t)));
+  c->size = static_cast<unsigned long long*>(sw_get(c, c->n * sizeof(unsigned long long)));
   c->rec = static_cast<int64_t*>(sw_get(c, 2 * c->n * sizeof(int64_t)));
   c->dev = static_cast<unsigned long long*>(sw_get(c, kDevWords * sizeof(unsigned long long)));
   if (!c->spin || !c->parent || !c->size || !c->rec || !c->dev) {
@@ -363,32 +389,43 @@ int lc_sw_init(int64_t L, double K, uint64_t seed, const lc_alloc* alloc, void* 
 
 int lc_sw_update(lc_sw* c, int64_t n_sweeps) {
   if (!c || n_sweeps < 0) return LC_EINVAL;
-  hipEvent_t ev[4] = {};
+  hipEvent_t ev[kSwPhases + 1] = {};
   if (c->profiling)
     for (auto& e : ev)
-      if (hipEventCreate(&e) != hipSuccess) return LC_EDEVICE;
+      if (hipEventCreate(&e) != hipSuccess) {
+        for (auto& f : ev)
+          if (f) (void)hipEventDestroy(f);
+        return LC_EDEVICE;
+      }
   int rc = LC_OK;
   std::vector<unsigned long long> h(static_cast<size_t>(kRing) * SW_WORDS);
+  const int64_t ntx = (c->L + kT - 1) / kT;
   for (int64_t done = 0; done < n_sweeps && rc == LC_OK;) {
     const int chunk = static_cast<int>(std::min<int64_t>(c->profiling ? 1 : kRing, n_sweeps - done));
     for (int q = 0; q < chunk; ++q) {
       SwDev d = sw_dev(c);
       d.sweep = c->sweep + static_cast<uint32_t>(q);
-      const int64_t ntx = (c->L + kT - 1) / kT;
+      int e = 0;
+      auto mark = [&]() {
+        if (c->profiling) (void)hipEventRecord(ev[e++], c->s);
+      };
       hipLaunchKernelGGL(k_sw_fill, dim3(1), dim3(64), 0, c->s, c->dev, int64_t(1 + SW_WORDS), 0ull);
-      if (c->profiling) (void)hipEventRecord(ev[0], c->s);
+      mark();
       hipLaunchKernelGGL(k_sw_tile, dim3(static_cast<int>(std::min<int64_t>(ntx * ntx, 8192))),
                          dim3(kSwBlock), 0, c->s, d);
-      if (c->profiling) (void)hipEventRecord(ev[1], c->s);
+      mark();
       hipLaunchKernelGGL(k_sw_cross, dim3(grid_of(2 * ntx * c->L, 8192)), dim3(kSwBlock), 0, c->s, d);
-      if (c->profiling) (void)hipEventRecord(ev[2], c->s);
+      mark();
       hipLaunchKernelGGL(k_sw_compress, dim3(grid_of(c->n, 8192)), dim3(kSwBlock), 0, c->s, d);
+      mark();
       hipLaunchKernelGGL(k_sw_sizes, dim3(grid_of(c->n, 8192)), dim3(kSwBlock), 0, c->s, d);
+      mark();
       hipLaunchKernelGGL(k_sw_roots, dim3(grid_of(c->n, 2048)), dim3(kSwBlock), 0, c->s, d);
+      mark();
       hipLaunchKernelGGL(k_sw_flip, dim3(grid_of(c->n, 8192)), dim3(kSwBlock), 0, c->s, d);
+      mark();
       hipLaunchKernelGGL(k_sw_record, dim3(1), dim3(64), 0, c->s, c->dev + 1,
                          c->dev + 1 + SW_WORDS, static_cast<uint32_t>(q));
-      if (c->profiling) (void)hipEventRecord(ev[3], c->s);
     }
     if (hipGetLastError() != hipSuccess ||
         hipMemcpyAsync(h.data(), c->dev + 1 + SW_WORDS, chunk * SW_WORDS * sizeof(unsigned long long),
@@ -417,15 +454,14 @@ int lc_sw_update(lc_sw* c, int64_t n_sweeps) {
       ++done;
     }
     if (c->profiling && rc == LC_OK) {
-      float a = 0, b = 0, e = 0;
-      if (hipEventElapsedTime(&a, ev[0], ev[1]) != hipSuccess || hipEventElapsedTime(&b, ev[1], ev[2]) != hipSuccess ||
-          hipEventElapsedTime(&e, ev[2], ev[3]) != hipSuccess) {
-        rc = LC_EDEVICE;
-        break;
+      for (int k = 0; k < kSwPhases; ++k) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, ev[k], ev[k + 1]) != hipSuccess) {
+          rc = LC_EDEVICE;
+          break;
+        }
+        c->phase_ms[k] += ms;
       }
-      c->phase_ms[0] += a;
-      c->phase_ms[1] += b;
-      c->phase_ms[2] += e;
       c->prof_sweeps += 1;
     }
   }
@@ -461,17 +497,33 @@ int lc_sw_export(const lc_sw* c, uint8_t* spins, int64_t* labels) {
 int lc_sw_set_profiling(lc_sw* c, int on) {
   if (!c) return LC_EINVAL;
   c->profiling = on != 0;
-  c->phase_ms[0] = c->phase_ms[1] = c->phase_ms[2] = 0;
+  for (double& v : c->phase_ms) v = 0;
   c->prof_sweeps = 0;
   return LC_OK;
 }
 
-int lc_sw_profile(const lc_sw* c, double* ms_tiles, double* ms_cross, double* ms_rest, int64_t* sweeps) {
-  if (!c || !ms_tiles || !ms_cross || !ms_rest) return LC_EINVAL;
-  *ms_tiles = c->phase_ms[0];
-  *ms_cross = c->phase_ms[1];
-  *ms_rest = c->phase_ms[2];
+int lc_sw_phase_count(void) { return kSwPhases; }
+
+const char* lc_sw_phase_name(int phase) {
+  static const char* const names[kSwPhases] = {"tiles", "cross", "compress", "sizes", "roots", "flip"};
+  return phase >= 0 && phase < kSwPhases ? names[phase] : nullptr;
+}
+
+int lc_sw_profile(const lc_sw* c, double* ms, int n, int64_t* sweeps) {
+  if (!c || !ms || n < kSwPhases) return LC_EINVAL;
+  for (int k = 0; k < kSwPhases; ++k) ms[k] = c->phase_ms[k];
   if (sweeps) *sweeps = c->prof_sweeps;
+  return LC_OK;
+}
+
+int lc_sw_work(const lc_sw* c, int64_t* n_records) {
+  if (!c || !n_records) return LC_EINVAL;
+  if (!c->has_last) return LC_ESTATE;
+  unsigned long long v = 0;
+  if (hipMemcpyAsync(&v, c->dev, sizeof(v), hipMemcpyDeviceToHost, c->s) != hipSuccess ||
+      hipStreamSynchronize(c->s) != hipSuccess)
+    return LC_EDEVICE;
+  *n_records = static_cast<int64_t>(v);
   return LC_OK;
 }
 
@@ -480,7 +532,7 @@ void lc_sw_free(lc_sw* c) {
   (void)hipStreamSynchronize(c->s);
   sw_put(c, c->spin, c->n);
   sw_put(c, c->parent, c->n * sizeof(int64_t));
-  sw_put(c, c->size, c->n * sizeof(int32_t));
+  sw_put(c, c->size, c->n * sizeof(unsigned long long));
   sw_put(c, c->rec, 2 * c->n * sizeof(int64_t));
   sw_put(c, c->dev, kDevWords * sizeof(unsigned long long));
   delete c;
