@@ -270,6 +270,14 @@ int lc_batch_set_schedule(lc_batch *b, int grid_blocks, int use_graph);
 int lc_batch_scratch_bytes(const lc_batch *b, size_t *bytes);
 void lc_batch_free(lc_batch *b);
 
+/* Capacities a chain run alone holds: *kept_cap kept operators per world-line
+ * buffer (grown when a sweep keeps more) and *scratch bytes of the per-sweep
+ * scratch arena of its engine (0 before its first lone sweep).  Both grow,
+ * with headroom, while the chain equilibrates (each growth reallocates and
+ * replays a sweep); callers timing sweeps can wait until they stop changing.
+ * Host-only; LC_EINVAL on NULL. */
+int lc_capacity(const lc_chain *c, int64_t *kept_cap, size_t *scratch);
+
 /* Same launch configuration for a chain run alone. */
 int lc_set_schedule(lc_chain *c, int grid_blocks, int use_graph);
 

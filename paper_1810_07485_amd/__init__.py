@@ -126,6 +126,7 @@ def load():
         "lc_batch_scratch_bytes": ([vp, C.POINTER(C.c_size_t)], C.c_int),
         "lc_batch_free": ([vp], None),
         "lc_set_schedule": ([vp, C.c_int, C.c_int], C.c_int),
+        "lc_capacity": ([vp, p64, C.POINTER(C.c_size_t)], C.c_int),
         "lc_phase_count": ([], C.c_int),
         "lc_phase_name": ([C.c_int], C.c_char_p),
         "lc_set_profiling": ([vp, C.c_int], C.c_int),
@@ -338,6 +339,12 @@ class Chain:
         """lc_update_noalloc: the same sweeps with no allocation (static scratch)."""
         _check(load().lc_update_noalloc(self._h, int(n_sweeps), int(bool(accumulate))),
                "lc_update_noalloc")
+
+    def capacity(self) -> tuple:
+        """(kept operators per world-line buffer, scratch arena bytes), lc_capacity."""
+        k, b = C.c_int64(), C.c_size_t()
+        _check(load().lc_capacity(self._h, C.byref(k), C.byref(b)), "lc_capacity")
+        return k.value, b.value
 
     def measure(self) -> dict:
         m = Measurement()

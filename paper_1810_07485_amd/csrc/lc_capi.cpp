@@ -1053,6 +1053,13 @@ static Engine* own_engine(lc_chain* c) {
   return c->own;
 }
 
+int lc_capacity(const lc_chain* c, int64_t* kept_cap, size_t* scratch) {
+  if (!c || !kept_cap || !scratch) return LC_EINVAL;
+  *kept_cap = c->kept_cap;
+  *scratch = c->own && c->own->ar ? static_cast<size_t>(c->own->ar->bytes()) : 0;
+  return LC_OK;
+}
+
 int lc_set_schedule(lc_chain* c, int grid_blocks, int use_graph) {
   if (!c || grid_blocks < 0) return LC_EINVAL;
   Engine* E = own_engine(c);
