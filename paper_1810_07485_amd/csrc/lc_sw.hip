@@ -208,34 +208,46 @@ __global__ __launch_bounds__(kSwBlock) void k_sw_compress(SwDev S) {
 }
 
 // Cluster sizes: every record adds its tile component's size at its
-// cluster's smallest site.  Near K_c one cluster spans most tiles, and its
-// records would all add to one word: a wave first sums the records of the
-// cluster of its first pending lane (a few rounds), then the rest add
-// alone.
-constexpr int kSizeRounds = 4;
+// cluster's smallest site.  Near K_c one cluster spans most tiles: its
+// records are a few in every wave, and one global atomic per wave to one
+// word serialises (device-scope atomics execute at the memory side).  A
+// block therefore sums a chunk of records per cluster in an LDS hash table
+// (open addressing, 64-bit CAS on the key), then adds each distinct
+// cluster's sum once.
+constexpr int kHash = 2048;                 // slots; a chunk fills at most half
+constexpr int kHashChunk = kHash / 2;       // records per block and step
+constexpr unsigned long long kEmpty = ~0ull;
 
 __global__ __launch_bounds__(kSwBlock) void k_sw_sizes(SwDev S) {
+  __shared__ unsigned long long hkey[kHash];
+  __shared__ unsigned long long hval[kHash];
   const int64_t nr = static_cast<int64_t>(*S.nrec);
-  const int lane = __lane_id();
-  for (int64_t base = static_cast<int64_t>(blockIdx.x) * kSwBlock; base < nr;
-       base += static_cast<int64_t>(gridDim.x) * kSwBlock) {
-    const int64_t k = base + threadIdx.x;
-    bool pending = k < nr;
-    const int64_t key = pending ? S.parent[S.rec[2 * k]] : -1;
-    const uint32_t val = pending ? static_cast<uint32_t>(S.rec[2 * k + 1]) : 0u;
-#pragma unroll
-    for (int r = 0; r < kSizeRounds; ++r) {
-      const unsigned long long m = __ballot(pending);
-      if (!m) break;  // wave-uniform
-      const int lead = __ffsll(static_cast<long long>(m)) - 1;
-      const int64_t k0 = __shfl(key, lead);
-      const bool mine = pending && key == k0;
-      uint32_t v = mine ? val : 0u;  // <= 64 * 4096
-      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-      if (lane == lead) atomicAdd(S.size + k0, static_cast<unsigned long long>(v));
-      pending = pending && !mine;
+  for (int64_t base = static_cast<int64_t>(blockIdx.x) * kHashChunk; base < nr;
+       base += static_cast<int64_t>(gridDim.x) * kHashChunk) {
+    for (int h = threadIdx.x; h < kHash; h += kSwBlock) {
+      hkey[h] = kEmpty;
+      hval[h] = 0;
     }
-    if (pending) atomicAdd(S.size + key, static_cast<unsigned long long>(val));
+    __syncthreads();
+    const int64_t end = base + kHashChunk < nr ? base + kHashChunk : nr;
+    for (int64_t k = base + threadIdx.x; k < end; k += kSwBlock) {
+      const unsigned long long key = static_cast<unsigned long long>(S.parent[S.rec[2 * k]]);
+      const unsigned long long val = static_cast<unsigned long long>(S.rec[2 * k + 1]);
+      // Fibonacci hash of the site; at most kHashChunk keys, so a free slot exists
+      uint32_t h = static_cast<uint32_t>((key * 0x9E3779B97F4A7C15ull) >> 53) & (kHash - 1);
+      for (;;) {
+        const unsigned long long old = atomicCAS(hkey + h, kEmpty, key);
+        if (old == kEmpty || old == key) {
+          atomicAdd(hval + h, val);
+          break;
+        }
+        h = (h + 1) & (kHash - 1);
+      }
+    }
+    __syncthreads();
+    for (int h = threadIdx.x; h < kHash; h += kSwBlock)
+      if (hkey[h] != kEmpty) atomicAdd(S.size + hkey[h], hval[h]);
+    __syncthreads();  // the table is cleared for the next chunk
   }
 }
 
@@ -418,7 +430,8 @@ int lc_sw_update(lc_sw* c, int64_t n_sweeps) {
       mark();
       hipLaunchKernelGGL(k_sw_compress, dim3(grid_of(c->n, 8192)), dim3(kSwBlock), 0, c->s, d);
       mark();
-      hipLaunchKernelGGL(k_sw_sizes, dim3(grid_of(c->n, 8192)), dim3(kSwBlock), 0, c->s, d);
+      hipLaunchKernelGGL(k_sw_sizes, dim3(static_cast<int>(std::min<int64_t>((c->n + kHashChunk - 1) / kHashChunk, 4096))),
+                         dim3(kSwBlock), 0, c->s, d);
       mark();
       hipLaunchKernelGGL(k_sw_roots, dim3(grid_of(c->n, 2048)), dim3(kSwBlock), 0, c->s, d);
       mark();
