@@ -222,9 +222,14 @@ def bench_batch(args, lc):
         for c in cs:
             c.update(1)
 
+    def note(m):
+        print(f"[bench batch] {m}", file=sys.stderr, flush=True)
+
     for _ in range(args.warmup):
         plain_pass()
+    note("warm-up done")
     el_p, ops_p = _timed_passes(plain_pass, chains, args.steps)
+    note(f"plain: {el_p / args.steps * 1e3:.1f} ms per step")
     # small-chain subset (launch overhead dominates): plain vs one batch
     small = sorted(chains, key=lambda c: c.L * c.beta)[:256]
     el_sp, ops_sp = _timed_passes(lambda: plain_pass(small), small, args.steps)
@@ -235,6 +240,7 @@ def bench_batch(args, lc):
     sgrid, _ = sb.autotune((512, 2048, 8192), 1)
     el_sb, ops_sb = _timed_passes(lambda: sb.update(1), small, args.steps)
     sb.close()
+    note("small chains done")
 
     runner = batching.BatchRunner(chains, budget)
     tune = runner.autotune((2048, 8192, 16384), 1)
