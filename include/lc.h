@@ -243,6 +243,30 @@ int lc_export_perm(const lc_chain *c, int64_t *perm, int64_t *n);
 int lc_slice_tables(const lc_chain *c, int n_slices, int64_t *bottom, int64_t *top,
                     int64_t *op_labels, int64_t *n_ops);
 
+/* Fourier-mode improved estimators of the most recent sweep: the
+ * second-moment estimators of the correlation length and the gap, which the
+ * paper cites for its S = 1 results (Sec. 5).  Along a loop the staggered
+ * spin (-1)^j S^z_j is one value +-1/2, so with Q_c(d, w) the sum over the
+ * loop's vertical segments (site j, tau_a to tau_b) of
+ * e^{i d j} int e^{i w tau} dtau, chi(pi + d, w) = <sum_c |Q_c|^2> / (4 beta L)
+ * and S(pi + d) = <sum_c |P_c|^2> / (4 L), P_c = sum over the loop's nodes at
+ * tau = 0+ of e^{i d j}.  Single-sweep estimates (average them over sweeps):
+ *   chi_pi    = chi(pi, 0)            (the staggered susceptibility)
+ *   chi_pi_q1 = chi(pi + 2 pi / L, 0)
+ *   chi_pi_w1 = chi(pi, 2 pi / beta)
+ *   s_pi_q1   = S(pi + 2 pi / L)
+ * and then xi = (L / 2 pi) sqrt(chi_pi / chi_pi_q1 - 1) and
+ * 1 / gap = (beta / 2 pi) sqrt(chi_pi / chi_pi_w1 - 1) from the averages.
+ * FP64 sums in a device-dependent order (agree with the oracle to ~1e-10
+ * relative, not bit for bit).  Valid as lc_export_labels; allocates and
+ * frees 8 bytes per loop-graph node plus 56 per loop of device memory
+ * through the chain's allocator (LC_ENOMEM when it cannot), synchronous. */
+typedef struct {
+  double chi_pi, chi_pi_q1, chi_pi_w1, s_pi_q1;
+  int64_t n_loops;
+} lc_fourier;
+int lc_fourier_last(const lc_chain *c, lc_fourier *out);
+
 void lc_free(lc_chain *c);
 const char *lc_strerror(int code);
 

@@ -91,3 +91,47 @@ def thermal(L: int, S: float, beta: float, vectors: bool = True) -> dict:
         out["s_pi"] = Ms2 / Z / L
         out["chi_s"] = Xs / Z / L
     return out
+
+
+def fourier(L: int, S: float, beta: float) -> dict:
+    """Dynamical susceptibility chi(q, w_n) = (1/(beta L)) int int e^{i w (tau -
+    tau')} <S^z_q(tau) S^z_-q(tau')>, S^z_q = sum_j e^{i q j} S^z_j, at
+    (q, w) = (pi, 0), (pi + 2 pi/L, 0), (pi, 2 pi/beta), and the equal-time
+    S(pi + 2 pi/L) = <S^z_q S^z_-q> / L, by the Lehmann sum over the
+    eigenstates of each total-S^z sector (S^z_q is diagonal in the S^z basis,
+    so it keeps the sector):
+      chi(q, w) = (1/(Z L)) sum_{m,n} |<m|S^z_q|n>|^2 (e^{-beta E_n} - e^{-beta E_m})
+                  (E_m - E_n) / ((E_m - E_n)^2 + w^2),
+    with beta e^{-beta E_m} for E_m = E_n at w = 0 (and 0 at w != 0)."""
+    two_s = int(round(2 * S))
+    j = np.arange(L)
+    qs = {"chi_pi": (np.pi, 0.0), "chi_pi_q1": (np.pi + 2 * np.pi / L, 0.0),
+          "chi_pi_w1": (np.pi, 2 * np.pi / beta)}
+    secs, emin = [], np.inf
+    for m2 in range(-two_s * L, two_s * L + 1, 2):
+        H, st = sector_hamiltonian(L, two_s, m2)
+        w, V = sla.eigh(H)
+        secs.append((w, V, st))
+        emin = min(emin, w.min())
+    Z = 0.0
+    acc = {k: 0.0 for k in qs}
+    sq1 = 0.0
+    for w, V, st in secs:
+        b = np.exp(-beta * (w - emin))
+        Z += b.sum()
+        dE = w[:, None] - w[None, :]                      # E_m - E_n
+        num = np.exp(-beta * (w[None, :] - emin)) - np.exp(-beta * (w[:, None] - emin))
+        same = np.abs(dE) < 1e-12
+        for k, (q, om) in qs.items():
+            d = (st / 2.0) @ np.exp(1j * q * j)           # S^z_q on each basis state
+            A = V.T @ (d[:, None] * V)
+            A2 = np.abs(A) ** 2
+            with np.errstate(divide="ignore", invalid="ignore"):
+                K = num * dE / (dE * dE + om * om)
+            K[same] = (beta * np.exp(-beta * (w[:, None] - emin)) * np.ones_like(dE))[same] if om == 0 else 0.0
+            acc[k] += (A2 * K).sum()
+            if k == "chi_pi_q1":
+                sq1 += (b * A2.sum(axis=1)).sum()
+    out = {k: v / Z / L for k, v in acc.items()}
+    out["s_pi_q1"] = sq1 / Z / L
+    return out

@@ -169,6 +169,9 @@ struct orc_chain {
     int64_t n_kept;
     int64_t sweep;
     int flip_rule; /* ORC_FLIP_LABEL or ORC_FLIP_VOTE */
+    int fourier;   /* compute the Fourier-mode estimators of each sweep */
+    double last_fourier[4];
+    int has_fourier;
     /* last sweep, for inspection */
     int64_t last_n_ops, last_n_nodes;
     int64_t *last_bond;
@@ -358,21 +361,30 @@ static void shuffle_site(const orc_chain *c, int64_t site, int64_t *idx, int n, 
     }
 }
 
-/* graph of world-line fragments: every node has exactly two edge ends */
+/* graph of world-line fragments: every node has exactly two edge ends.
+ * Every edge is a vertical segment of one subspin's world line (esub, from
+ * tick et0 to et0 + elen), or a zero-length symmetrization edge (esub -1);
+ * esub and et0 are kept only when the Fourier-mode estimators are on. */
 typedef struct {
     int64_t *nb;   /* nb[2v], nb[2v+1]: neighbours */
     int64_t n_nodes, n_edges;
     int64_t *eu, *ev;
     u128 *elen;
     uint8_t *fill;
+    int64_t *esub;
+    uint64_t *et0;
 } graph;
 
-static void add_edge(graph *g, int64_t u, int64_t v, u128 len)
+static void add_edge(graph *g, int64_t u, int64_t v, u128 len, int64_t sub, uint64_t t0)
 {
     int64_t e = g->n_edges++;
     g->eu[e] = u;
     g->ev[e] = v;
     g->elen[e] = len;
+    if (g->esub) {
+        g->esub[e] = sub;
+        g->et0[e] = t0;
+    }
     g->nb[2 * u + g->fill[u]++] = v;
     g->nb[2 * v + g->fill[v]++] = u;
 }
@@ -388,6 +400,96 @@ static int64_t uf_find(int64_t *parent, int64_t x)
         x = nx;
     }
     return r;
+}
+
+/*
+ * Fourier-mode improved estimators of the sweep's loops: the second-moment
+ * estimators of the correlation length and the gap (the paper cites them
+ * for Table 3).  Along a loop the staggered spin (-1)^j S^z_j is one value
+ * +-1/2 (every operator joins antiparallel spins), so S^z at momentum
+ * pi + d, frequency w, is a sum over loops of +-1/2 times
+ *   Q_c(d, w) = sum over the loop's vertical segments (subspin x of site
+ *               j = x / 2S, from tau_a to tau_b) of e^{i d j} int e^{i w tau},
+ * and with independent signs chi(pi + d, w) = <sum_c |Q_c|^2> / (4 beta L).
+ * Three points: (d, w) = (0, 0), (2 pi / L, 0), (0, 2 pi / beta); and the
+ * equal-time structure factor S(pi + 2 pi / L) = <sum_c |P_c|^2> / (4 L),
+ * P_c = sum over the loop's bottom (tau = 0+) nodes of e^{i d j}.
+ * Symmetrization edges have zero length and add nothing.
+ */
+static int fourier_sums(orc_chain *c, const graph *g, const int64_t *label, int64_t nn, int64_t ns)
+{
+    const double beta = c->beta, two_pi = 2.0 * acos(-1.0);
+    const double d = two_pi / (double)c->L, w = two_pi / beta;
+    double *q0 = (double *)calloc(nn > 0 ? nn : 1, sizeof(double));
+    double *qd = (double *)calloc(2 * (nn > 0 ? nn : 1), sizeof(double));
+    double *qw = (double *)calloc(2 * (nn > 0 ? nn : 1), sizeof(double));
+    double *pd = (double *)calloc(2 * (nn > 0 ? nn : 1), sizeof(double));
+    if (!q0 || !qd || !qw || !pd) {
+        free(q0);
+        free(qd);
+        free(qw);
+        free(pd);
+        return ORC_ENOMEM;
+    }
+    for (int64_t e = 0; e < g->n_edges; e++) {
+        if (g->esub[e] < 0)
+            continue;
+        const int64_t l = label[g->eu[e]];
+        const int64_t j = g->esub[e] / c->two_s;
+        const u128 t1 = (u128)g->et0[e] + g->elen[e];
+        const double fa = ldexp((double)g->et0[e], -64), fb = ldexp((double)t1, -64);
+        const double len = ldexp((double)g->elen[e], -64) * beta;
+        q0[l] += len;
+        qd[2 * l] += cos(d * (double)j) * len;
+        qd[2 * l + 1] += sin(d * (double)j) * len;
+        /* (e^{i w tau_b} - e^{i w tau_a}) / (i w), w tau = 2 pi f */
+        qw[2 * l] += (sin(two_pi * fb) - sin(two_pi * fa)) / w;
+        qw[2 * l + 1] -= (cos(two_pi * fb) - cos(two_pi * fa)) / w;
+    }
+    for (int64_t i = 0; i < ns; i++) {
+        const int64_t l = label[i], j = i / c->two_s;
+        pd[2 * l] += cos(d * (double)j);
+        pd[2 * l + 1] += sin(d * (double)j);
+    }
+    double s0 = 0, sd = 0, sw = 0, sp = 0;
+    for (int64_t v = 0; v < nn; v++) {
+        if (label[v] != v)
+            continue;
+        s0 += q0[v] * q0[v];
+        sd += qd[2 * v] * qd[2 * v] + qd[2 * v + 1] * qd[2 * v + 1];
+        sw += qw[2 * v] * qw[2 * v] + qw[2 * v + 1] * qw[2 * v + 1];
+        sp += pd[2 * v] * pd[2 * v] + pd[2 * v + 1] * pd[2 * v + 1];
+    }
+    const double L = (double)c->L;
+    c->last_fourier[0] = s0 / (4.0 * beta * L);
+    c->last_fourier[1] = sd / (4.0 * beta * L);
+    c->last_fourier[2] = sw / (4.0 * beta * L);
+    c->last_fourier[3] = sp / (4.0 * L);
+    c->has_fourier = 1;
+    free(q0);
+    free(qd);
+    free(qw);
+    free(pd);
+    return ORC_OK;
+}
+
+int orc_set_fourier(orc_chain *c, int on)
+{
+    if (!c)
+        return ORC_EINVAL;
+    c->fourier = on != 0;
+    return ORC_OK;
+}
+
+int orc_fourier_last(const orc_chain *c, double out[4])
+{
+    if (!c || !out)
+        return ORC_EINVAL;
+    if (!c->has_fourier)
+        return ORC_ESTATE;
+    for (int k = 0; k < 4; k++)
+        out[k] = c->last_fourier[k];
+    return ORC_OK;
 }
 
 int orc_sweep(orc_chain *c, orc_stats *st)
@@ -513,8 +615,13 @@ int orc_sweep(orc_chain *c, orc_stats *st)
     int64_t *last_at = (int64_t *)malloc(sizeof(int64_t) * ns);
     uint64_t *last_t = (uint64_t *)malloc(sizeof(uint64_t) * ns);
     c->last_perm = (int64_t *)malloc(sizeof(int64_t) * ns);
+    c->has_fourier = 0;
+    if (c->fourier) {
+        g.esub = (int64_t *)malloc(sizeof(int64_t) * ne_max);
+        g.et0 = (uint64_t *)malloc(sizeof(uint64_t) * ne_max);
+    }
     if (!g.nb || !g.eu || !g.ev || !g.elen || !g.fill || !last_at || !last_t ||
-        !c->last_perm)
+        !c->last_perm || (c->fourier && (!g.esub || !g.et0)))
         goto out2;
     for (int64_t i = 0; i < ns; i++)
         last_at[i] = -1;
@@ -528,10 +635,10 @@ int orc_sweep(orc_chain *c, orc_stats *st)
         for (int q = 0; q < 2; q++) {
             int64_t i = site[q];
             if (last_at[i] < 0)
-                add_edge(&g, i /* bottom / boundary node */, nbn + 2 * k, (u128)ev[e].t);
+                add_edge(&g, i /* bottom / boundary node */, nbn + 2 * k, (u128)ev[e].t, i, 0);
             else
                 add_edge(&g, nbn + 2 * last_at[i] + 1, nbn + 2 * k,
-                         (u128)(ev[e].t - last_t[i]));
+                         (u128)(ev[e].t - last_t[i]), i, last_t[i]);
             last_at[i] = k;
             last_t[i] = ev[e].t;
         }
@@ -539,9 +646,10 @@ int orc_sweep(orc_chain *c, orc_stats *st)
     for (int64_t i = 0; i < ns; i++) {
         int64_t top = split ? ns + i : i;
         if (last_at[i] < 0)
-            add_edge(&g, i, top, (u128)1 << 64);
+            add_edge(&g, i, top, (u128)1 << 64, i, 0);
         else
-            add_edge(&g, nbn + 2 * last_at[i] + 1, top, ((u128)1 << 64) - (u128)last_t[i]);
+            add_edge(&g, nbn + 2 * last_at[i] + 1, top, ((u128)1 << 64) - (u128)last_t[i], i,
+                     last_t[i]);
     }
     /* symmetrization of the subspins of each spin (split-spin only):
      * top(j,a) is joined to bottom(j, pi_j(a)), pi_j drawn uniformly among
@@ -575,7 +683,7 @@ int orc_sweep(orc_chain *c, orc_stats *st)
                 c->last_perm[dn_t[q]] = dn_b[q];
         }
         for (int64_t i = 0; i < ns; i++)
-            add_edge(&g, ns + i, c->last_perm[i], (u128)0);
+            add_edge(&g, ns + i, c->last_perm[i], (u128)0, -1, 0);
     } else {
         for (int64_t i = 0; i < ns; i++)
             c->last_perm[i] = i;
@@ -672,6 +780,10 @@ int orc_sweep(orc_chain *c, orc_stats *st)
             goto out2;
         }
         c->last_label = label;
+
+        /* ---- 6a. Fourier-mode estimators (optional) -------------------- */
+        if (c->fourier && fourier_sums(c, &g, label, nn, ns) != ORC_OK)
+            goto out2;
 
         /* ---- 6. improved estimators per loop (before the flip) --------- */
         int64_t *size = (int64_t *)calloc(nn, sizeof(int64_t));
@@ -787,6 +899,8 @@ int orc_sweep(orc_chain *c, orc_stats *st)
         rc = ORC_OK;
     }
 out2:
+    free(g.esub);
+    free(g.et0);
     free(g.nb);
     free(g.eu);
     free(g.ev);

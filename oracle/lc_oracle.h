@@ -87,6 +87,12 @@ int orc_flip_bit(uint64_t seed, int64_t sweep, int64_t label);
 int orc_vote_bit(uint64_t seed, int64_t sweep, int64_t node);
 /* Select the loop-flip rule of the following sweeps (ORC_FLIP_*). */
 int orc_set_flip_rule(orc_chain *c, int rule);
+/* Fourier-mode estimators (on/off for the following sweeps), and those of
+ * the most recent sweep: out = chi(pi, 0), chi(pi + 2 pi/L, 0),
+ * chi(pi, 2 pi/beta), S(pi + 2 pi/L) (single-sweep improved estimates;
+ * ORC_ESTATE when the last sweep did not compute them). */
+int orc_set_fourier(orc_chain *c, int on);
+int orc_fourier_last(const orc_chain *c, double out[4]);
 
 int  orc_create(int64_t L, int two_s, double beta, uint64_t seed, orc_chain **out);
 void orc_free(orc_chain *c);

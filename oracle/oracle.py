@@ -78,6 +78,8 @@ def lib():
         L.orc_flip_bit.argtypes = [C.c_uint64, C.c_int64, C.c_int64]
         L.orc_vote_bit.argtypes = [C.c_uint64, C.c_int64, C.c_int64]
         L.orc_set_flip_rule.argtypes = [C.c_void_p, C.c_int]
+        L.orc_set_fourier.argtypes = [C.c_void_p, C.c_int]
+        L.orc_fourier_last.argtypes = [C.c_void_p, C.POINTER(C.c_double)]
         L.orc_create.argtypes = [C.c_int64, C.c_int, C.c_double, C.c_uint64,
                                  C.POINTER(C.c_void_p)]
         L.orc_free.argtypes = [C.c_void_p]
@@ -154,6 +156,21 @@ class Chain:
         rc = lib().orc_set_flip_rule(self._h, int(rule))
         if rc != 0:
             raise ValueError(f"orc_set_flip_rule rc={rc}")
+
+    def set_fourier(self, on: bool = True):
+        """Compute the Fourier-mode estimators in the following sweeps."""
+        rc = lib().orc_set_fourier(self._h, int(bool(on)))
+        if rc != 0:
+            raise ValueError(f"orc_set_fourier rc={rc}")
+
+    def fourier(self) -> dict:
+        """Single-sweep improved estimates of the most recent sweep:
+        chi(pi, 0), chi(pi + 2 pi/L, 0), chi(pi, 2 pi/beta), S(pi + 2 pi/L)."""
+        o = (C.c_double * 4)()
+        rc = lib().orc_fourier_last(self._h, o)
+        if rc != 0:
+            raise RuntimeError(f"orc_fourier_last rc={rc}")
+        return dict(chi_pi=o[0], chi_pi_q1=o[1], chi_pi_w1=o[2], s_pi_q1=o[3])
 
     def sizes(self):
         a, b, c, d = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()

@@ -63,6 +63,14 @@ class SwStats(C.Structure):
         return d
 
 
+class Fourier(C.Structure):
+    _fields_ = [("chi_pi", C.c_double), ("chi_pi_q1", C.c_double), ("chi_pi_w1", C.c_double),
+                ("s_pi_q1", C.c_double), ("n_loops", C.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Measurement(C.Structure):
     _fields_ = [("n_sweeps", C.c_int64), ("e", C.c_double), ("chi_u", C.c_double),
                 ("chi_u_plain", C.c_double), ("s_pi", C.c_double), ("chi_s", C.c_double),
@@ -114,6 +122,7 @@ def load():
         "lc_export_ops": ([vp, p64, pu64, pu8, pu8, p64], C.c_int),
         "lc_export_labels": ([vp, p64, p64], C.c_int),
         "lc_export_perm": ([vp, p64, p64], C.c_int),
+        "lc_fourier_last": ([vp, C.POINTER(Fourier)], C.c_int),
         "lc_slice_tables": ([vp, C.c_int, p64, p64, p64, p64], C.c_int),
         "lc_free": ([vp], None),
         "lc_strerror": ([C.c_int], C.c_char_p),
@@ -339,6 +348,13 @@ class Chain:
         """lc_update_noalloc: the same sweeps with no allocation (static scratch)."""
         _check(load().lc_update_noalloc(self._h, int(n_sweeps), int(bool(accumulate))),
                "lc_update_noalloc")
+
+    def fourier(self) -> dict:
+        """Fourier-mode estimators of the most recent sweep (lc_fourier_last):
+        chi(pi, 0), chi(pi + 2 pi/L, 0), chi(pi, 2 pi/beta), S(pi + 2 pi/L)."""
+        f = Fourier()
+        _check(load().lc_fourier_last(self._h, C.byref(f)), "lc_fourier_last")
+        return f.as_dict()
 
     def capacity(self) -> tuple:
         """(kept operators per world-line buffer, scratch arena bytes), lc_capacity."""

@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 SO = os.path.join(PKG, "liblc.so")
-SOURCES = ["lc_kernels.hip", "lc_capi.cpp", "lc_probe.hip", "lc_static.hip", "lc_sw.hip"]
+SOURCES = ["lc_kernels.hip", "lc_capi.cpp", "lc_probe.hip", "lc_static.hip", "lc_sw.hip", "lc_fourier.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

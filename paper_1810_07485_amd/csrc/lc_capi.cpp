@@ -1431,6 +1431,74 @@ int lc_slice_tables(const lc_chain* c, int n_slices, int64_t* bottom, int64_t* t
   return LC_OK;
 }
 
+int lc_fourier_last(const lc_chain* c, lc_fourier* out) {
+  if (!c || !out) return LC_EINVAL;
+  if (!c->last_engine) return LC_ESTATE;
+  Arena* R = c->last_engine->ar;
+  std::lock_guard<std::mutex> hold(R->mu);
+  ChainDyn d;
+  int64_t wb;
+  int rc = last_ranges(c, &d, &wb);
+  if (rc != LC_OK) return rc;
+  LcFourierArgs A;
+  A.L = c->L;
+  A.n_sites = c->n_sites;
+  A.n_bonds = c->n_bonds;
+  A.two_s = c->two_s;
+  A.w = c->w;
+  A.win_base = wb;
+  A.op_base = d.op_base;
+  A.node_base = d.node_base;
+  A.nbn = c->nbn;
+  A.n_nodes = d.n_nodes;
+  A.beta = c->beta;
+  A.opstart = R->opstart.p;
+  A.optime = R->optime.p;
+  A.parent = R->parent.p;
+  const size_t idx_bytes = static_cast<size_t>(d.n_nodes + 1) * sizeof(int64_t);
+  const size_t scan_bytes = (LC_SCAN_BLOCKS + 1) * sizeof(int64_t);
+  A.loopidx = static_cast<int64_t*>(c->mem.get(idx_bytes));
+  A.scan_tmp = static_cast<int64_t*>(c->mem.get(scan_bytes));
+  A.out = static_cast<double*>(c->mem.get(4 * sizeof(double)));
+  A.acc = nullptr;
+  hipStream_t s = c->stream;
+  int64_t n_loops = 0;
+  double sums[4] = {0, 0, 0, 0};
+  size_t acc_bytes = 0;
+  rc = LC_OK;
+  if (!A.loopidx || !A.scan_tmp || !A.out) {
+    rc = LC_ENOMEM;
+  } else if (lc_launch_fourier_index(A, s) != hipSuccess ||
+             hipMemcpyAsync(&n_loops, A.loopidx + d.n_nodes, sizeof(n_loops), hipMemcpyDeviceToHost, s) != hipSuccess ||
+             hipStreamSynchronize(s) != hipSuccess) {
+    rc = LC_EDEVICE;
+  } else if (n_loops < 1 || n_loops > d.n_nodes) {
+    rc = LC_EDEVICE;  // every loop has a smallest node: an inconsistent forest
+  } else {
+    acc_bytes = static_cast<size_t>(n_loops) * 7 * sizeof(double);
+    A.acc = static_cast<double*>(c->mem.get(acc_bytes));
+    if (!A.acc)
+      rc = LC_ENOMEM;
+    else if (lc_launch_fourier_sums(A, n_loops, s) != hipSuccess ||
+             hipMemcpyAsync(sums, A.out, sizeof(sums), hipMemcpyDeviceToHost, s) != hipSuccess ||
+             hipStreamSynchronize(s) != hipSuccess)
+      rc = LC_EDEVICE;
+  }
+  c->mem.put(A.acc, acc_bytes);
+  c->mem.put(A.out, 4 * sizeof(double));
+  c->mem.put(A.scan_tmp, scan_bytes);
+  c->mem.put(A.loopidx, idx_bytes);
+  if (rc != LC_OK) return rc;
+  const double L = static_cast<double>(c->L), beta = c->beta;
+  const double w = 2.0 * 3.14159265358979323846 / beta;  // i w Q was summed
+  out->chi_pi = sums[0] / (4.0 * beta * L);
+  out->chi_pi_q1 = sums[1] / (4.0 * beta * L);
+  out->chi_pi_w1 = sums[2] / (w * w) / (4.0 * beta * L);
+  out->s_pi_q1 = sums[3] / (4.0 * L);
+  out->n_loops = n_loops;
+  return LC_OK;
+}
+
 int lc_export_perm(const lc_chain* c, int64_t* perm, int64_t* n) {
   if (!c || !n) return LC_EINVAL;
   const int64_t have = *n;

@@ -112,6 +112,26 @@ struct LcSliceArgs {
   uint32_t* flags;            // LC_FLAG_GRAPH on an inconsistent graph
 };
 
+// Fourier-mode estimators of one chain's most recent sweep (lc_fourier.hip).
+struct LcFourierArgs {
+  int64_t L, n_sites, n_bonds;
+  int two_s, w;
+  int64_t win_base;           // flat window of the chain's bond 0, window 0
+  int64_t op_base;            // the chain's first flat operator
+  int64_t node_base, nbn;     // the chain's first flat node; its boundary nodes
+  int64_t n_nodes;
+  double beta;
+  const int64_t* opstart;
+  const uint64_t* optime;
+  const int64_t* parent;      // the sweep's union-find words
+  int64_t* loopidx;           // n_nodes + 1: loop index of each loop's smallest node (scan)
+  int64_t* scan_tmp;          // LC_SCAN_BLOCKS + 1
+  double* acc;                // 7 per loop
+  double* out;                // 4 sums
+};
+hipError_t lc_launch_fourier_index(const LcFourierArgs& a, hipStream_t s);
+hipError_t lc_launch_fourier_sums(const LcFourierArgs& a, int64_t n_loops, hipStream_t s);
+
 hipError_t lc_launch_sweep(const LcSweepArgs& a, hipStream_t s);
 hipError_t lc_launch_slices(const LcSliceArgs& a, hipStream_t s);
 hipError_t lc_launch_scan(int64_t* a, int64_t n, int64_t* bsum, hipStream_t s);

@@ -101,3 +101,21 @@ def cluster_stats(L, two_s, s0, labels, U, LEN, nbn):
         sum_len2=sum((v >> 32) ** 2 for v in ln.values()),
         max_size=max(size.values()),
     )
+
+
+def segments(L, two_s, op_bond, op_time):
+    """Vertical segments of the world lines: (first node, subspin, start tick,
+    end tick), end 2^64 at beta, in the order loop_graph lists its edges."""
+    ns = two_s * L
+    nbn = ns if two_s == 1 else 2 * ns
+    ev = site_events(L, two_s, op_bond, op_time)
+    out = []
+    for i, lst in enumerate(ev):
+        if not lst:
+            out.append((i, i, 0, 1 << 64))
+            continue
+        out.append((i, i, 0, int(op_time[lst[0]])))
+        for a, b in zip(lst[:-1], lst[1:]):
+            out.append((nbn + 2 * a + 1, i, int(op_time[a]), int(op_time[b])))
+        out.append((nbn + 2 * lst[-1] + 1, i, int(op_time[lst[-1]]), 1 << 64))
+    return out
