@@ -538,6 +538,26 @@ constexpr uint32_t kRepSize = 0x1FFFu;    // bits 0..12: nodes of the component
 constexpr int kRepSlotShift = 13;         // bits 13..22: accumulator slot + 1
 constexpr uint32_t kRepSlotMask = 0x3FFu;
 
+// Per-subspin event lists of a split-spin tile's walk (tile_walk_lists),
+// held in the LDS of the accumulator slots, which are not in use until the
+// walk is over.  A run is the operators of one (walker, bond slot): one
+// bond's window.  S = 1/2 tiles walk serially and keep these minimal.
+template <int TS>
+struct TileLists {
+  static constexpr int kRuns = TS == 1 ? 1 : 512;    // walkers x 2 (2S) bond slots
+  static constexpr int kItems = TS == 1 ? 1 : 3584;  // events of all walkers
+  int64_t rstart[kRuns];     // first flat operator of each run
+  int64_t wnxt[kBlock];      // first event after each walker's window (flat), or -1
+  uint16_t wlist[kItems];    // each walker's events in (time, bond) order, as their index
+                             // in the walker's runs taken one after another
+  uint16_t rlen[kRuns];      // operators of each run
+  uint16_t roff[kRuns];      // first event of each run in its walker's concatenated runs
+  int16_t rloc[kRuns];       // local index of the run's first operator, -1 if not owned
+  uint16_t woff[kBlock + 1]; // first list entry of each walker
+  int16_t wnl[kBlock];       // local index of wnxt, or -1
+  uint8_t wflag[kBlock];     // bit 0: events before the window; bit 1: no event at all
+};
+
 template <int TS>
 struct TileLds {
   using C = TileCfg<TS>;
@@ -548,9 +568,14 @@ struct TileLds {
   uint32_t deg[C::kNodes / 16];      // 2-bit counts of the edges of each node inside the tile
   uint64_t ltime[C::kOps];           // times of the tile's operators
   uint8_t lbond[C::kOps];            // owned bond (local index) of each tile operator
-  int64_t slot_hi[C::kSlots], slot_lo[C::kSlots];
-  uint32_t slot_rep[C::kSlots];
-  uint32_t slot_vote[C::kSlots];     // XOR of the votes of a slotted component
+  union {
+    struct {
+      int64_t slot_hi[C::kSlots], slot_lo[C::kSlots];
+      uint32_t slot_rep[C::kSlots];
+      uint32_t slot_vote[C::kSlots];  // XOR of the votes of a slotted component
+    };
+    TileLists<TS> wl;                 // the walk's event lists (split spins)
+  };
   uint32_t tpre[kTileBonds + 1];     // first local operator of each owned bond
   int64_t tos[kTileBonds];           // first (flat) operator of each owned bond in the tile
   int64_t xsrc[C::kCross], xdst[C::kCross];
@@ -560,6 +585,8 @@ struct TileLds {
   int ncl;                           // closed components whose flip decision is drawn last
   uint32_t fl;
 };
+static_assert(sizeof(TileLists<2>) <= sizeof(int64_t) * 2 * TileCfg<2>::kSlots + 8 * TileCfg<2>::kSlots,
+              "split-spin event lists fit the slots' LDS");
 
 // Local operator index of flat operator e on bond bb, or -1 if the tile does
 // not own it.
@@ -701,6 +728,170 @@ __device__ inline void tile_walk(TileLds<TS>& S, const ChainDesc& D, int64_t x, 
   }
 }
 
+// The walk of every (subspin, window) of a split-spin tile at once.  A
+// serial walker merges its 2 (2S) time-sorted bond runs one event at a
+// time; here every event takes its place in its walker's list directly:
+// its position in its own run plus, for every other run, the number of
+// that run's operators preceding it in (time, bond) order (a binary search).
+// Consecutive list entries then give the same edges as the serial walk
+// (tile_walk), emitted in parallel.  Block-cooperative; returns false,
+// block-uniformly and before any edge, when the tile has more runs or more
+// events than the lists hold (the caller flags the tile as too large).
+template <int TS>
+__device__ bool tile_walk_lists(TileLds<TS>& S, const ChainDesc& D, int64_t j0, int64_t k0, int nj,
+                                int nthr, int64_t nb0, int64_t node_base, int64_t B0, int nbt,
+                                const int64_t* __restrict__ opstart,
+                                const uint64_t* __restrict__ optime) {
+  constexpr int NB = 2 * TS;
+  using WL = TileLists<TS>;
+  WL& Lw = S.wl;
+  const int tid = threadIdx.x;
+  const int64_t W = int64_t(1) << D.w;
+  const int nx = nj * TS;  // subspins of the tile
+  // bond slot q of walker w (as in tile_walk)
+  auto bond_of = [&](int w, int q) -> int64_t {
+    const int64_t x = j0 * TS + w % nx;
+    const int64_t j = x / TS, a = x - j * TS, jl = j == 0 ? D.L - 1 : j - 1;
+    return q < TS ? (jl * TS + q) * TS + a : (j * TS + a) * TS + (q - TS);
+  };
+  auto run_time = [&](int r, int p) -> uint64_t {
+    return Lw.rloc[r] >= 0 ? S.ltime[Lw.rloc[r] + p] : optime[Lw.rstart[r] + p];
+  };
+  // the run holding a walker's event `within`: the last run starting at or before it
+  auto run_of = [&](int r0, int within) -> int {
+    int s = 0;
+    for (int q = 1; q < NB; ++q)
+      if (Lw.roff[r0 + q] <= within) s = q;
+    return s;
+  };
+  // 1. runs of every walker; the event after its window; the empty subspin
+  int64_t m = 0;
+  int fits = nthr * NB <= WL::kRuns ? 1 : 0;
+  if (tid < nthr && fits) {
+    const int kk = tid / nx;
+    const int64_t x = j0 * TS + tid % nx, k = k0 + kk;
+    bool before = false, empty = true;
+    int64_t nxt = -1, bn = 0;
+    uint64_t tn = 0;
+    for (int q = 0; q < NB; ++q) {
+      const int64_t bnd = bond_of(tid, q);
+      const int64_t i0 = D.win_base + bnd * W;
+      const int64_t h = opstart[i0 + k], e = opstart[i0 + k + 1];
+      const int64_t b0 = opstart[i0], bw = opstart[i0 + W];
+      before = before || b0 < h;
+      empty = empty && bw == b0;
+      const int r = tid * NB + q;
+      const int64_t lb = bnd - B0;
+      Lw.rstart[r] = h;
+      Lw.rlen[r] = static_cast<uint16_t>(e - h);
+      Lw.roff[r] = static_cast<uint16_t>(m);
+      Lw.rloc[r] = static_cast<int16_t>((lb >= 0 && lb < nbt) ? S.tpre[lb] + (h - S.tos[lb]) : -1);
+      m += e - h;
+      if (e < bw) {
+        const int li = tile_local(S, B0, nbt, bnd, e);
+        const uint64_t t = li >= 0 ? S.ltime[li] : optime[e];
+        if (nxt < 0 || t < tn || (t == tn && bnd < bn)) {
+          nxt = e;
+          tn = t;
+          bn = bnd;
+        }
+      }
+    }
+    fits = fits && m <= WL::kItems;
+    Lw.wnxt[tid] = nxt;
+    Lw.wnl[tid] = static_cast<int16_t>(nxt >= 0 ? tile_local(S, B0, nbt, bn, nxt) : -1);
+    Lw.wflag[tid] = static_cast<uint8_t>((before ? 1 : 0) | (empty ? 2 : 0));
+    (void)x;
+  }
+  int64_t total;
+  const int64_t ex = block_exclusive_scan(m, S.scan, total);
+  if (!__syncthreads_and(fits) || total > WL::kItems) return false;  // block-uniform
+  if (tid < nthr) {
+    Lw.woff[tid] = static_cast<uint16_t>(ex);
+    // a subspin without any event: its bottom joins its top
+    if (m == 0 && k0 + tid / nx == 0 && (Lw.wflag[tid] & 2)) {
+      const int64_t x = j0 * TS + tid % nx;
+      tile_edge(S, node_base + x, -1, node_base + D.n_sites + x, -1);
+    }
+  }
+  if (tid == 0) Lw.woff[nthr] = static_cast<uint16_t>(total);
+  __syncthreads();
+  const int nev = static_cast<int>(total);
+  auto walker_of = [&](int g) -> int {
+    int lo = 0, hi = nthr - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (Lw.woff[mid] <= g)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    return lo;
+  };
+  // 2. every event's place in its walker's list
+  for (int g = tid; g < nev; g += kBlock) {
+    const int w = walker_of(g);
+    const int within = g - Lw.woff[w];
+    const int r0 = w * NB;
+    const int s = run_of(r0, within);
+    const int r = r0 + s, p = within - Lw.roff[r];
+    const int64_t bnd = bond_of(w, s);
+    const uint64_t t = run_time(r, p);
+    int rank = p;
+    for (int q = 0; q < NB; ++q) {
+      const int rq = r0 + q;
+      const int n = Lw.rlen[rq];
+      if (q == s || n == 0) continue;
+      const bool tie_before = bond_of(w, q) < bnd;  // equal times: smaller bond first
+      int a = 0, b = n;
+      while (a < b) {
+        const int mid = (a + b) >> 1;
+        const uint64_t tm = run_time(rq, mid);
+        if (tm < t || (tie_before && tm == t))
+          a = mid + 1;
+        else
+          b = mid;
+      }
+      rank += a;
+    }
+    Lw.wlist[Lw.woff[w] + rank] = static_cast<uint16_t>(within);
+  }
+  __syncthreads();
+  // 3. edges between consecutive events (the serial walk's edges)
+  for (int g = tid; g < nev; g += kBlock) {
+    const int w = walker_of(g);
+    const int within = g - Lw.woff[w];
+    const int mw = Lw.woff[w + 1] - Lw.woff[w];
+    const int64_t x = j0 * TS + w % nx;
+    auto node = [&](int entry, int h, int64_t* gn, int* ln) {
+      const int r = w * NB + run_of(w * NB, entry), p = entry - Lw.roff[r];
+      *gn = nb0 + 2 * (Lw.rstart[r] + p) + h;
+      *ln = Lw.rloc[r] >= 0 ? 2 * (Lw.rloc[r] + p) + h : -1;
+    };
+    int64_t gl;
+    int ll;
+    node(Lw.wlist[g], 0, &gl, &ll);
+    if (within == 0) {
+      if (!(Lw.wflag[w] & 1)) tile_edge(S, node_base + x, -1, gl, ll);
+    } else {
+      int64_t gu;
+      int lu;
+      node(Lw.wlist[g - 1], 1, &gu, &lu);
+      tile_edge(S, gu, lu, gl, ll);
+    }
+    if (within == mw - 1) {
+      int64_t gu;
+      int lu;
+      node(Lw.wlist[g], 1, &gu, &lu);
+      if (Lw.wnxt[w] >= 0)
+        tile_edge(S, gu, lu, nb0 + 2 * Lw.wnxt[w], Lw.wnl[w] >= 0 ? 2 * Lw.wnl[w] : -1);
+      else
+        tile_edge(S, gu, lu, node_base + D.n_sites + x, -1);
+    }
+  }
+  return true;
+}
+
 template <int TS>
 __global__ __launch_bounds__(kBlock) void k_link_tile(
     const ChainDesc* __restrict__ descs, const ChainDyn* __restrict__ dyn, int nchain,
@@ -764,10 +955,17 @@ __global__ __launch_bounds__(kBlock) void k_link_tile(
     // the tile's operator times, coalesced
     for (int lo = tid; lo < nlo; lo += kBlock) S.ltime[lo] = optime[tile_op(S, static_cast<uint32_t>(lo))];
     __syncthreads();
-    if (tid < nthr) {
-      const int xs = tid % (nj * TS);
-      const int kk = tid / (nj * TS);
-      tile_walk<TS>(S, D, j0 * TS + xs, k0 + kk, nb0, dy.node_base, B0, nbt, opstart, optime);
+    // S = 1/2: a serial walker per (subspin, window) merges two bond runs;
+    // split spins merge 2 (2S) runs through the per-subspin event lists
+    if constexpr (TS > 1) {
+      if (!tile_walk_lists<TS>(S, D, j0, k0, nj, nthr, nb0, dy.node_base, B0, nbt, opstart, optime)) {
+        if (tid == 0) atomicOr(flags, LC_FLAG_TILE);  // block-uniform: the tile is too large
+        break;
+      }
+    } else if (tid < nthr) {
+      const int xs = tid % nj;
+      const int kk = tid / nj;
+      tile_walk<TS>(S, D, j0 + xs, k0 + kk, nb0, dy.node_base, B0, nbt, opstart, optime);
     }
     __syncthreads();
     // full compression in two steps: every root is found by read-only walks
