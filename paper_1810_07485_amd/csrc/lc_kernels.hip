@@ -213,6 +213,18 @@ __device__ inline uint32_t antiparallel_mask(const ChainDesc& D, const uint8_t* 
   return ((base & 1u) ? ~flips : flips) & live;
 }
 
+// A uniform 64-bit draw placed in window k.
+__device__ inline uint64_t in_window(const ChainDesc& D, uint64_t k, uint64_t v) {
+  return D.w == 0 ? v : ((k << (64 - D.w)) | (v >> D.w));
+}
+
+// Philox call i >= 1 of window (b, k): its lower half is draw 2i-1, its
+// upper half draw 2i.
+__device__ inline u32x4 cand_call(const ChainDesc& D, int64_t b, uint64_t k, uint32_t i) {
+  return philox10(D.seed, static_cast<uint32_t>(k), (DOM_INS << 24) | i, static_cast<uint32_t>(b),
+                  D.sweep);
+}
+
 // Candidate j of window (b, k): the j-th uniform 64-bit draw placed in the
 // window.  Draw 0 is the upper half of call 0 (its lower half decides the
 // count); draws 2i-1 and 2i are the halves of call i.
@@ -272,15 +284,36 @@ __global__ __launch_bounds__(kBlock) void k_gen(const ChainDesc* __restrict__ de
       const bool known = WRITE && n <= 32;
       uint64_t accm = known ? accmask[i] : 0;
       if (known) {
-        if (inlds)
-          for (int j = 0; j < n; ++j) slot[j * kBlock + tid] = cand_time(D, b, k, j, v0);
+        if (inlds) {
+          if (n > 0) slot[tid] = in_window(D, k, v0);
+          for (int j = 1; j < n; j += 2) {  // draws 2i-1, 2i from call i
+            const u32x4 r = cand_call(D, b, k, static_cast<uint32_t>((j + 1) >> 1));
+            slot[j * kBlock + tid] = in_window(D, k, lo64(r));
+            if (j + 1 < n) slot[(j + 1) * kBlock + tid] = in_window(D, k, hi64(r));
+          }
+        }
       } else {
         // n > kCap here whenever WRITE, so no candidate goes to LDS
         for (int j0 = 0; j0 < n; j0 += kChunk) {
           const int m = (n - j0 < kChunk) ? n - j0 : kChunk;
+          // one Philox call per pair of draws (2i-1, 2i); a chunk starts at an
+          // even draw, so only its first (draw j0 > 0) needs a call of its own
           uint64_t tc[kChunk];
 #pragma unroll
-          for (int j = 0; j < kChunk; ++j) tc[j] = (j < m) ? cand_time(D, b, k, j0 + j, v0) : 0;
+          for (int j = 0; j < kChunk; ++j) {
+            const int jj = j0 + j;
+            if (j >= m) {
+              tc[j] = 0;
+            } else if (jj == 0) {
+              tc[j] = in_window(D, k, v0);
+            } else if (jj & 1) {
+              const u32x4 r = cand_call(D, b, k, static_cast<uint32_t>((jj + 1) >> 1));
+              tc[j] = in_window(D, k, lo64(r));
+              if (j + 1 < kChunk) tc[j + 1] = j + 1 < m ? in_window(D, k, hi64(r)) : 0;
+            } else if (j == 0) {
+              tc[j] = in_window(D, k, hi64(cand_call(D, b, k, static_cast<uint32_t>(jj >> 1))));
+            }
+          }
           accm |= static_cast<uint64_t>(antiparallel_mask(D, s0, kstart, ktime, b, k, tc, m)) << j0;
         }
       }
@@ -293,6 +326,39 @@ __global__ __launch_bounds__(kBlock) void k_gen(const ChainDesc* __restrict__ de
         const int64_t base = opstart[i];
         if (opstart[i + 1] > op_cap) {
           atomicOr(flags, 1u);
+        } else if (inlds) {
+          // accepted candidates in draw order, then a stable insertion sort
+          // (equal times keep draw order), then one merge with the kept
+          // operators (a kept operator first at equal times)
+          int na = 0;
+          for (int j = 0; j < n; ++j)
+            if ((accm >> j) & 1) slot[(na++) * kBlock + tid] = slot[j * kBlock + tid];
+          for (int a1 = 1; a1 < na; ++a1) {
+            const uint64_t t = slot[a1 * kBlock + tid];
+            int a2 = a1 - 1;
+            while (a2 >= 0 && slot[a2 * kBlock + tid] > t) {
+              slot[(a2 + 1) * kBlock + tid] = slot[a2 * kBlock + tid];
+              --a2;
+            }
+            slot[(a2 + 1) * kBlock + tid] = t;
+          }
+          int64_t o = base, q = kb;
+          int ia = 0;
+          uint64_t tk = q < ke ? ktime[q] : 0;
+          while (ia < na || q < ke) {
+            const uint64_t ta = ia < na ? slot[ia * kBlock + tid] : 0;
+            if (q < ke && (ia >= na || tk <= ta)) {
+              optime[o] = tk;
+              optype[o] = 3;
+              ++q;
+              tk = q < ke ? ktime[q] : 0;
+            } else {
+              optime[o] = ta;
+              optype[o] = 0;
+              ++ia;
+            }
+            ++o;
+          }
         } else {
           auto tj = [&](int j) -> uint64_t {
             return inlds ? slot[j * kBlock + tid] : cand_time(D, b, k, j, v0);
@@ -1704,7 +1770,15 @@ __global__ __launch_bounds__(kBlock) void k_flip_sites(
   part.flush(stats, nchain, kIdx);
 }
 
-// The off-diagonal operators become the next sweep's world lines.
+// Next world lines (step 7): the kept operators of every window, in order.
+// They keep the operator array's own (window, operator) order, so this is a
+// stream compaction: a workgroup takes 256 windows, writes their starts, and
+// moves their kept operators with a block scan of the kept flags over the
+// windows' operator range (8 consecutive operators per thread), reading and
+// writing contiguous memory.  Windows of different chains (a batch) are
+// taken chain by chain.
+constexpr int kCompactPer = 8;
+
 __global__ __launch_bounds__(kBlock) void k_compact(const ChainDesc* __restrict__ descs,
                                                      const int64_t* __restrict__ win_bases,
                                                      int nchain, int64_t nwin,
@@ -1713,26 +1787,58 @@ __global__ __launch_bounds__(kBlock) void k_compact(const ChainDesc* __restrict_
                                                      const uint8_t* __restrict__ optype,
                                                      const int64_t* __restrict__ kflat,
                                                      uint32_t* __restrict__ flags) {
+  __shared__ int64_t sh[kWaves + 1];
+  __shared__ uint32_t fl;
   // a sweep with any overflow or error is discarded: kflat may be stale
-  if (*flags) return;
-  for (int64_t i = xcd_block() * kBlock + threadIdx.x; i < nwin;
-       i += static_cast<int64_t>(gridDim.x) * kBlock) {
-    const int c = chain_of(win_bases, nchain, i);
-    const ChainDesc& D = descs[c];
-    const int64_t li = i - D.win_base;
-    const int64_t nw = D.n_bonds << D.w;
-    const int64_t kb = kflat[D.win_base];
-    if (kflat[D.win_base + nw] - kb > D.kept_cap) {
-      atomicOr(flags, 8u);
-      continue;
+  // (read once per block: blocks of this kernel may raise the kept flag)
+  if (threadIdx.x == 0) fl = *flags;
+  __syncthreads();
+  if (fl) return;
+  const int tid = threadIdx.x;
+  for (int64_t c0 = xcd_block() * kBlock; c0 < nwin; c0 += static_cast<int64_t>(gridDim.x) * kBlock) {
+    const int64_t cend = c0 + kBlock < nwin ? c0 + kBlock : nwin;
+    for (int64_t w = c0; w < cend;) {  // block-uniform: the chains of the 256 windows
+      const int c = chain_of(win_bases, nchain, w);
+      const ChainDesc& D = descs[c];
+      const int64_t nw = D.n_bonds << D.w;
+      const int64_t wend = cend < D.win_base + nw ? cend : D.win_base + nw;
+      const int64_t kb = kflat[D.win_base];
+      if (kflat[D.win_base + nw] - kb > D.kept_cap) {
+        if (tid == 0) atomicOr(flags, 8u);
+        w = wend;
+        continue;
+      }
+      int64_t* __restrict__ ks = D.kstart[D.cur ^ 1];
+      uint64_t* __restrict__ kt = D.ktime[D.cur ^ 1];
+      const int64_t i = w + tid;
+      if (i < wend) {
+        const int64_t li = i - D.win_base;
+        ks[li] = kflat[i] - kb;
+        if (li == nw - 1) ks[nw] = kflat[i + 1] - kb;
+      }
+      const int64_t qb = opstart[wend];
+      int64_t out = kflat[w] - kb;
+      for (int64_t base = opstart[w]; base < qb; base += kBlock * kCompactPer) {
+        const int64_t q0 = base + static_cast<int64_t>(tid) * kCompactPer;
+        uint32_t bits = 0;
+        int64_t cnt = 0;
+#pragma unroll
+        for (int m = 0; m < kCompactPer; ++m) {
+          const int64_t q = q0 + m;
+          if (q < qb && (optype[q] & 1)) {
+            bits |= 1u << m;
+            ++cnt;
+          }
+        }
+        int64_t tot;
+        int64_t o = out + block_exclusive_scan(cnt, sh, tot);
+#pragma unroll
+        for (int m = 0; m < kCompactPer; ++m)
+          if ((bits >> m) & 1u) kt[o++] = optime[q0 + m];
+        out += tot;
+      }
+      w = wend;
     }
-    int64_t* __restrict__ ks = D.kstart[D.cur ^ 1];
-    uint64_t* __restrict__ kt = D.ktime[D.cur ^ 1];
-    int64_t o = kflat[i] - kb;
-    ks[li] = o;
-    if (li == nw - 1) ks[nw] = kflat[i + 1] - kb;
-    for (int64_t q = opstart[i]; q < opstart[i + 1]; ++q)
-      if (optype[q] & 1) kt[o++] = optime[q];
   }
 }
 
