@@ -316,6 +316,24 @@ int lc_batch_autotune(lc_batch *b, const int *grids, int n_grids, int trial_swee
 int lc_autotune(lc_chain *c, const int *grids, int n_grids, int trial_sweeps, int *best_grid,
                 double *ms_per_sweep);
 
+/* Linking-tile shape (schedule only: results do not depend on it).  The
+ * loop graph is linked and union-found in tiles of spins x windows, local
+ * first, then globally (Secs. 3.1-3.2); a tile takes at most max_windows
+ * windows per bond (a power of two up to 16; 0: 8 for S = 1/2, 1 for split
+ * spins) and about target_ops operators (64..2,048; 0: 1,500 for
+ * S = 1/2, 1,400 for split spins), within the LDS capacities.  LC_EINVAL
+ * otherwise.  lc_autotune_tiles / lc_batch_autotune_tiles time every shape
+ * i (windows[i], targets[i]) with every grid as lc_autotune does (the
+ * sweeps advance the chains) and keep the fastest pair: *best_shape (index),
+ * *best_grid, *ms_per_sweep (each may be NULL). */
+int lc_set_tile(lc_chain *c, int max_windows, int target_ops);
+int lc_autotune_tiles(lc_chain *c, const int *windows, const int *targets, int n_shapes,
+                      const int *grids, int n_grids, int trial_sweeps, int *best_shape,
+                      int *best_grid, double *ms_per_sweep);
+int lc_batch_autotune_tiles(lc_batch *b, const int *windows, const int *targets, int n_shapes,
+                            const int *grids, int n_grids, int trial_sweeps, int *best_shape,
+                            int *best_grid, double *ms_per_sweep);
+
 /* ---- timing -------------------------------------------------------------
  * With profiling on, every sweep is launched directly (no graph) with a HIP
  * event recorded on the chain's (or batch's) stream between its phases, and

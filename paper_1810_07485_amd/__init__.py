@@ -135,6 +135,11 @@ def load():
         "lc_batch_scratch_bytes": ([vp, C.POINTER(C.c_size_t)], C.c_int),
         "lc_batch_free": ([vp], None),
         "lc_set_schedule": ([vp, C.c_int, C.c_int], C.c_int),
+        "lc_set_tile": ([vp, C.c_int, C.c_int], C.c_int),
+        "lc_autotune_tiles": ([vp, pi, pi, C.c_int, pi, C.c_int, C.c_int, pi, pi,
+                               C.POINTER(C.c_double)], C.c_int),
+        "lc_batch_autotune_tiles": ([vp, pi, pi, C.c_int, pi, C.c_int, C.c_int, pi, pi,
+                                     C.POINTER(C.c_double)], C.c_int),
         "lc_capacity": ([vp, p64, C.POINTER(C.c_size_t)], C.c_int),
         "lc_phase_count": ([], C.c_int),
         "lc_phase_name": ([C.c_int], C.c_char_p),
@@ -182,6 +187,21 @@ def _check(rc: int, what: str):
 
 def _p(a: np.ndarray, ct):
     return a.ctypes.data_as(C.POINTER(ct))
+
+
+# linking-tile shapes the tile tuner tries: (max windows per tile, operator target)
+DEFAULT_TILE_SHAPES = ((0, 0), (4, 1500), (8, 1100), (16, 1500), (1, 1100))
+
+
+def _autotune_tiles(fn, h, shapes, grids, trial_sweeps):
+    shapes = list(shapes)
+    win = (C.c_int * len(shapes))(*[int(w) for w, _ in shapes])
+    tgt = (C.c_int * len(shapes))(*[int(t) for _, t in shapes])
+    g = (C.c_int * len(grids))(*[int(x) for x in grids])
+    bs, bg, ms = C.c_int(), C.c_int(), C.c_double()
+    _check(fn(h, win, tgt, len(shapes), g, len(grids), int(trial_sweeps), C.byref(bs), C.byref(bg),
+              C.byref(ms)), fn.__name__)
+    return shapes[bs.value], bg.value, ms.value
 
 
 def lc_footprint(L: int, S: float, beta: float) -> int:
@@ -386,6 +406,14 @@ class Chain:
         """Pick the fastest grid size (runs real, unaccumulated sweeps)."""
         return _autotune(load().lc_autotune, self._h, grids, trial_sweeps)
 
+    def set_tile(self, max_windows: int = 0, target_ops: int = 0):
+        """Linking-tile shape (lc_set_tile; 0, 0: the default)."""
+        _check(load().lc_set_tile(self._h, int(max_windows), int(target_ops)), "lc_set_tile")
+
+    def autotune_tiles(self, shapes=DEFAULT_TILE_SHAPES, grids=DEFAULT_GRIDS, trial_sweeps: int = 2):
+        """Fastest (tile shape, grid) pair: ((max_windows, target_ops), grid, ms per sweep)."""
+        return _autotune_tiles(load().lc_autotune_tiles, self._h, shapes, grids, trial_sweeps)
+
     def profile(self) -> tuple:
         """(dict phase -> summed ms, sweeps) since profiling was switched on."""
         return _profile(load().lc_profile, self._h)
@@ -582,6 +610,11 @@ class Batch:
     def autotune(self, grids=DEFAULT_GRIDS, trial_sweeps: int = 2) -> tuple:
         """Pick the fastest grid size (runs real, unaccumulated sweeps)."""
         return _autotune(load().lc_batch_autotune, self._h, grids, trial_sweeps)
+
+    def autotune_tiles(self, shapes=DEFAULT_TILE_SHAPES, grids=DEFAULT_GRIDS, trial_sweeps: int = 2):
+        """Fastest (tile shape, grid) pair for every member: ((max_windows,
+        target_ops), grid, ms per sweep)."""
+        return _autotune_tiles(load().lc_batch_autotune_tiles, self._h, shapes, grids, trial_sweeps)
 
     def profile(self) -> tuple:
         return _profile(load().lc_batch_profile, self._h)

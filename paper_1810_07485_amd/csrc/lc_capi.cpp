@@ -233,6 +233,7 @@ struct lc_chain {
   int K = 0;
   int64_t n_sites = 0, n_bonds = 0, nwin = 0, nbn = 0;
   int tile_j = 1, tile_k = 1, tile_shrink = 0;  // linking tile (spins x windows)
+  int tile_kmax = 0, tile_target = 0;            // tile shape preference (0: default)
   int flip_rule = LC_FLIP_LABEL;
   int64_t ntj = 1, ntk = 1;
   Mem mem;
@@ -442,12 +443,15 @@ int ensure_scratch(Arena& A, int64_t ops, int64_t nodes, int64_t xe, int64_t fe,
 
 // Linking tile of a chain: spins x windows with at most LC_TILE_THREADS
 // (subspin, window) walkers and LC_TILE_BONDS owned bonds, sized for about
-// 1,500 operators at S = 1/2 and 1,100 for split spins (LC_TILE_OPS and
-// LC_TILE_OPS_SPLIT are the hard limits: a tile beyond one makes the sweep
-// replay with tiles half as large, tile_shrink).  S = 1/2 tiles are
-// 4 windows tall: a site crosses a window boundary once, a tile side on
-// about half of its events.  Split-spin tiles are one window tall: 2S bonds
-// wide at each side, they need all the spins they can get.
+// 1,500 operators at S = 1/2 and 1,400 for split spins by the density bound
+// rho (the split-spin density is below it: about 1,300 in practice;
+// LC_TILE_OPS and LC_TILE_OPS_SPLIT are the hard limits: a tile beyond one
+// makes the sweep replay with tiles half as large, tile_shrink).  S = 1/2
+// tiles are up to 8 windows tall: a site crosses a window boundary once, a
+// tile side on about half of its events.  Split-spin tiles are one window
+// tall: 2S bonds wide at each side, they need all the spins they can get.
+// lc_set_tile overrides both (measured on the MI355X: 8 windows and 1,400
+// were the fastest of the shapes tried at the benchmark sizes).
 void choose_tile(lc_chain* c) {
   const int ts = c->two_s;
   const int64_t W = int64_t(1) << c->w;
@@ -456,12 +460,16 @@ void choose_tile(lc_chain* c) {
   // the bound (N_b/4 + L S(S+1)) / N_b otherwise
   const double rho = ts == 1 ? 0.72 : (ts + 1.0) / (2.0 * ts);
   const double per_spin_window = std::max(rho * ts * ts * win_tau, 1e-9);
-  const double target = (ts == 1 ? 1500.0 : 1100.0) / static_cast<double>(int64_t(1) << c->tile_shrink);
-  int64_t tk = std::min<int64_t>(W, ts == 1 ? 4 : 1);
+  const double base = c->tile_target > 0 ? c->tile_target : (ts == 1 ? 1500.0 : 1400.0);
+  const double target = base / static_cast<double>(int64_t(1) << c->tile_shrink);
+  int64_t tk = std::min<int64_t>(W, c->tile_kmax > 0 ? c->tile_kmax : (ts == 1 ? 8 : 1));
+  // split spins: the walk's event lists hold 2 (2S) runs per walker, at most
+  // 2 LC_TILE_BONDS runs: (2S)^2 bonds per spin times the windows
+  while (tk > 1 && ts > 1 && ts * ts * tk > LC_TILE_BONDS) tk >>= 1;
   while (tk > 1 && per_spin_window * static_cast<double>(tk) > target) tk >>= 1;
   int64_t tj = static_cast<int64_t>(target / (per_spin_window * static_cast<double>(tk)));
   tj = std::min<int64_t>(tj, LC_TILE_THREADS / (ts * tk));
-  tj = std::min<int64_t>(tj, LC_TILE_BONDS / (ts * ts));
+  tj = std::min<int64_t>(tj, LC_TILE_BONDS / (ts * ts * (ts > 1 ? tk : 1)));
   tj = std::min<int64_t>(tj, c->L);
   tj = std::max<int64_t>(tj, 1);
   c->tile_j = static_cast<int>(tj);
@@ -1100,6 +1108,70 @@ static int autotune(Engine& E, const int* grids, int n, int trials, int* best, d
   return LC_OK;
 }
 
+// Every tile shape with every grid: the fastest pair is kept.
+static int autotune_tiles(Engine& E, const int* windows, const int* targets, int n_shapes,
+                          const int* grids, int n_grids, int trials, int* best_shape, int* best_grid,
+                          double* ms) {
+  if (!windows || !targets || n_shapes < 1) return LC_EINVAL;
+  for (int i = 0; i < n_shapes; ++i) {
+    const bool pow2 = windows[i] > 0 && (windows[i] & (windows[i] - 1)) == 0;
+    if ((windows[i] != 0 && (!pow2 || windows[i] > 16)) ||
+        (targets[i] != 0 && (targets[i] < 64 || targets[i] > LC_TILE_OPS)))
+      return LC_EINVAL;
+  }
+  double best_ms = 0.0;
+  int bs = 0, bg = E.grid, rc;
+  for (int i = 0; i < n_shapes; ++i) {
+    for (lc_chain* c : E.chains) {
+      c->tile_kmax = windows[i];
+      c->tile_target = targets[i];
+      c->tile_shrink = 0;
+    }
+    E.dirty = true;
+    int g = 0;
+    double t = 0.0;
+    if ((rc = autotune(E, grids, n_grids, trials, &g, &t)) != LC_OK) return rc;
+    if (i == 0 || t < best_ms) {
+      best_ms = t;
+      bs = i;
+      bg = g;
+    }
+  }
+  for (lc_chain* c : E.chains) {
+    c->tile_kmax = windows[bs];
+    c->tile_target = targets[bs];
+    c->tile_shrink = 0;
+  }
+  E.dirty = true;
+  E.grid = bg;
+  E.drop_graph();
+  if (best_shape) *best_shape = bs;
+  if (best_grid) *best_grid = bg;
+  if (ms) *ms = best_ms;
+  return LC_OK;
+}
+
+int lc_autotune_tiles(lc_chain* c, const int* windows, const int* targets, int n_shapes,
+                      const int* grids, int n_grids, int trial_sweeps, int* best_shape,
+                      int* best_grid, double* ms_per_sweep) {
+  if (!c) return LC_EINVAL;
+  if (c->batch) return LC_ESTATE;
+  Engine* E = own_engine(c);
+  if (!E) return LC_ENOMEM;
+  return autotune_tiles(*E, windows, targets, n_shapes, grids, n_grids, trial_sweeps, best_shape,
+                        best_grid, ms_per_sweep);
+}
+
+int lc_batch_autotune_tiles(lc_batch* b, const int* windows, const int* targets, int n_shapes,
+                            const int* grids, int n_grids, int trial_sweeps, int* best_shape,
+                            int* best_grid, double* ms_per_sweep) {
+  if (!b) return LC_EINVAL;
+  for (lc_chain* c : b->eng.chains)
+    if (c->stream != b->eng.stream && hipStreamSynchronize(c->stream) != hipSuccess) return LC_EDEVICE;
+  return autotune_tiles(b->eng, windows, targets, n_shapes, grids, n_grids, trial_sweeps,
+                        best_shape, best_grid, ms_per_sweep);
+}
+
 int lc_autotune(lc_chain* c, const int* grids, int n_grids, int trial_sweeps, int* best_grid,
                 double* ms_per_sweep) {
   if (!c) return LC_EINVAL;
@@ -1174,6 +1246,19 @@ int lc_update_noalloc(lc_chain* c, int64_t n_sweeps, int accumulate) {
   // holds no operators or labels of these sweeps
   if (c->own) c->own->dirty = true;
   c->last_engine = nullptr;
+  return LC_OK;
+}
+
+int lc_set_tile(lc_chain* c, int max_windows, int target_ops) {
+  if (!c) return LC_EINVAL;
+  const bool pow2 = max_windows > 0 && (max_windows & (max_windows - 1)) == 0;
+  if (max_windows != 0 && (!pow2 || max_windows > 16)) return LC_EINVAL;
+  if (target_ops != 0 && (target_ops < 64 || target_ops > LC_TILE_OPS)) return LC_EINVAL;
+  c->tile_kmax = max_windows;
+  c->tile_target = target_ops;
+  c->tile_shrink = 0;
+  if (c->own) c->own->dirty = true;
+  if (c->batch) c->batch->eng.dirty = true;
   return LC_OK;
 }
 

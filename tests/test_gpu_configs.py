@@ -136,3 +136,37 @@ def test_largest_window_count(lc, orc):
     for s in range(3):
         g.update(1)
         compare_sweep(g, o, g.last_sweep(), o.sweep(), tag=f"w=11 sweep {s}")
+
+
+@pytest.mark.parametrize("L,S,beta,seed,shape", [
+    (1024, 0.5, 256.0, 3, (1, 300)),     # one window per tile, small tiles
+    (1024, 0.5, 256.0, 3, (16, 2000)),   # sixteen windows per tile
+    (1024, 0.5, 256.0, 3, (2, 64)),      # the smallest target
+    (64, 0.5, 64.0, 6, (8, 1500)),
+    (8, 1.0, 16.5, 4, (2, 200)),         # split spins, two windows per tile
+    (16, 4.0, 9.0, 5, (4, 1500)),        # S = 4: (2S)^2 x windows bounded by the lists
+])
+def test_tile_shapes_lockstep(lc, orc, L, S, beta, seed, shape):
+    """The linking-tile shape is schedule only: every sweep equals the
+    oracle's under any shape lc_set_tile accepts."""
+    g = lc.Chain(L, S, beta, seed)
+    g.set_tile(*shape)
+    o = orc.Chain(L, S, beta, seed)
+    for s in range(3):
+        g.update(1)
+        compare_sweep(g, o, g.last_sweep(), o.sweep(), tag=f"shape {shape} sweep {s}")
+
+
+def test_tile_autotune_keeps_results(lc):
+    shapes, grids = ((0, 0), (1, 400), (8, 1500)), (128, 512)
+    a, b = lc.Chain(256, 0.5, 64.0, 7), lc.Chain(256, 0.5, 64.0, 7)
+    shape, grid, ms = a.autotune_tiles(shapes, grids, trial_sweeps=1)
+    assert shape in shapes and grid in grids and ms > 0
+    b.update(len(shapes) * len(grids) * 2)
+    for x, y in zip(a.export_state(), b.export_state()):
+        np.testing.assert_array_equal(np.asarray(x), np.asarray(y))
+    assert a.last_sweep() == b.last_sweep()
+    with pytest.raises(lc.LcError):
+        a.set_tile(3, 0)        # not a power of two
+    with pytest.raises(lc.LcError):
+        a.set_tile(4, 5000)     # beyond the LDS capacity
