@@ -58,12 +58,22 @@ __device__ inline void uf_union(int64_t* parent, int64_t a, int64_t b, int64_t n
   }
 }
 
+// Words of the LDS forest change under other threads' unions and path
+// halving: every read and write is a relaxed workgroup-scope atomic, so it
+// is really performed (and stays an LDS instruction: a volatile pointer
+// would lose the address space and go through flat memory instructions).
+__device__ inline uint32_t lload(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ inline void lstore(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 __device__ inline uint32_t lfind(uint32_t* lp, uint32_t x) {
-  volatile uint32_t* v = lp;
-  uint32_t p = v[x];
+  uint32_t p = lload(lp + x);
   while (p != x) {
-    const uint32_t gp = v[p];
-    if (gp != p) v[x] = gp;
+    const uint32_t gp = lload(lp + p);
+    if (gp != p) lstore(lp + x, gp);
     x = p;
     p = gp;
   }
