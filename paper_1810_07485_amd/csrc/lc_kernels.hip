@@ -23,6 +23,19 @@
 namespace lc {
 
 constexpr int kBlock = 256;
+
+// Chain arrays reached through pointers held in the chain descriptors are
+// in HBM; the compiler cannot know it, and would use flat memory
+// instructions (which also wait on LDS traffic).  These casts say it.
+#define LC_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ inline const LC_GLOBAL T* gin(const T* p) {
+  return (const LC_GLOBAL T*)p;
+}
+template <class T>
+__device__ inline LC_GLOBAL T* gout(T* p) {
+  return (LC_GLOBAL T*)p;
+}
 constexpr int kCap = 12;  // candidate times per window kept in LDS while writing; more are redrawn
 
 __device__ inline int lane_id() { return __lane_id(); }
@@ -185,9 +198,9 @@ __device__ inline bool precedes(uint64_t t1, int64_t b1, uint64_t t2, int64_t b2
 // mask: each neighbouring bond's window bounds and kept times are read once
 // for all of them.
 constexpr int kChunk = 8;
-__device__ inline uint32_t antiparallel_mask(const ChainDesc& D, const uint8_t* __restrict__ s0,
-                                             const int64_t* __restrict__ kstart,
-                                             const uint64_t* __restrict__ ktime, int64_t b,
+__device__ inline uint32_t antiparallel_mask(const ChainDesc& D, const LC_GLOBAL uint8_t* __restrict__ s0,
+                                             const LC_GLOBAL int64_t* __restrict__ kstart,
+                                             const LC_GLOBAL uint64_t* __restrict__ ktime, int64_t b,
                                              uint64_t k, const uint64_t (&tc)[kChunk], int m) {
   const int64_t ends[2] = {bond_x(D, b), bond_y(D, b)};
   uint32_t base = static_cast<uint32_t>(s0[ends[0]] ^ s0[ends[1]]);
@@ -268,9 +281,9 @@ __global__ __launch_bounds__(kBlock) void k_gen(const ChainDesc* __restrict__ de
       const int c = chain_of(win_bases, nchain, i);
       if (!WRITE) part.at(c, stats, nchain, kIdx);
       const ChainDesc& D = descs[c];
-      const uint8_t* __restrict__ s0 = D.s0[D.cur];
-      const int64_t* __restrict__ kstart = D.kstart[D.cur];
-      const uint64_t* __restrict__ ktime = D.ktime[D.cur];
+      const LC_GLOBAL uint8_t* __restrict__ s0 = gin(D.s0[D.cur]);
+      const LC_GLOBAL int64_t* __restrict__ kstart = gin(D.kstart[D.cur]);
+      const LC_GLOBAL uint64_t* __restrict__ ktime = gin(D.ktime[D.cur]);
       const int64_t li = i - D.win_base;
       const int64_t b = li >> D.w;
       const uint64_t k = static_cast<uint64_t>(li & ((int64_t(1) << D.w) - 1));
@@ -654,6 +667,16 @@ struct TileLds {
 static_assert(sizeof(TileLists<2>) <= sizeof(int64_t) * 2 * TileCfg<2>::kSlots + 8 * TileCfg<2>::kSlots,
               "split-spin event lists fit the slots' LDS");
 
+// Time of flat operator e whose tile-local index is li (-1: not the tile's):
+// from LDS or from HBM.  The LDS read is an atomic load so that the two
+// reads stay loads of their own address spaces (a select between an LDS
+// and a global address would become one flat memory instruction).
+__device__ inline uint64_t op_time(const uint64_t* ltime, int li, const uint64_t* __restrict__ optime,
+                                   int64_t e) {
+  if (li >= 0) return __hip_atomic_load(ltime + li, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  return optime[e];
+}
+
 // Local operator index of flat operator e on bond bb, or -1 if the tile does
 // not own it.
 template <class Lds>
@@ -713,7 +736,7 @@ __device__ inline void tile_walk(TileLds<TS>& S, const ChainDesc& D, int64_t x, 
     before = before || opstart[i0] < h[s];
     const int64_t lb = bnd[s] - B0;
     hl[s] = (lb >= 0 && lb < nbt) ? static_cast<int>(S.tpre[lb] + (h[s] - S.tos[lb])) : -1;
-    th[s] = h[s] < e[s] ? (hl[s] >= 0 ? S.ltime[hl[s]] : optime[h[s]]) : 0;
+    th[s] = h[s] < e[s] ? op_time(S.ltime, hl[s], optime, h[s]) : 0;
     any = any || h[s] < e[s];
   }
   if (!any) {
@@ -756,7 +779,7 @@ __device__ inline void tile_walk(TileLds<TS>& S, const ChainDesc& D, int64_t x, 
     lprev = lcur;
     const int64_t nh = cur + 1;
     const int nl = lcur >= 0 ? lcur + 1 : -1;
-    const uint64_t nt = nh < em ? (nl >= 0 ? S.ltime[nl] : optime[nh]) : 0;
+    const uint64_t nt = nh < em ? op_time(S.ltime, nl, optime, nh) : 0;
 #pragma unroll
     for (int s = 0; s < NB; ++s) {
       if (s == sm) {
@@ -776,7 +799,7 @@ __device__ inline void tile_walk(TileLds<TS>& S, const ChainDesc& D, int64_t x, 
     const int64_t idx = e[s];
     if (idx < opstart[i0 + W]) {
       const int li = tile_local(S, B0, nbt, bnd[s], idx);
-      const uint64_t t = li >= 0 ? S.ltime[li] : optime[idx];
+      const uint64_t t = op_time(S.ltime, li, optime, idx);
       if (nxt < 0 || t < tn || (t == tn && bnd[s] < bn)) {
         nxt = idx;
         tn = t;
@@ -821,7 +844,7 @@ __device__ bool tile_walk_lists(TileLds<TS>& S, const ChainDesc& D, int64_t j0, 
     return q < TS ? (jl * TS + q) * TS + a : (j * TS + a) * TS + (q - TS);
   };
   auto run_time = [&](int r, int p) -> uint64_t {
-    return Lw.rloc[r] >= 0 ? S.ltime[Lw.rloc[r] + p] : optime[Lw.rstart[r] + p];
+    return op_time(S.ltime, Lw.rloc[r] >= 0 ? Lw.rloc[r] + p : -1, optime, Lw.rstart[r] + p);
   };
   // the run holding a walker's event `within`: the last run starting at or before it
   auto run_of = [&](int r0, int within) -> int {
@@ -855,7 +878,7 @@ __device__ bool tile_walk_lists(TileLds<TS>& S, const ChainDesc& D, int64_t j0, 
       m += e - h;
       if (e < bw) {
         const int li = tile_local(S, B0, nbt, bnd, e);
-        const uint64_t t = li >= 0 ? S.ltime[li] : optime[e];
+        const uint64_t t = op_time(S.ltime, li, optime, e);
         if (nxt < 0 || t < tn || (t == tn && bnd < bn)) {
           nxt = e;
           tn = t;
@@ -1808,8 +1831,8 @@ __global__ __launch_bounds__(kBlock) void k_compact(const ChainDesc* __restrict_
         w = wend;
         continue;
       }
-      int64_t* __restrict__ ks = D.kstart[D.cur ^ 1];
-      uint64_t* __restrict__ kt = D.ktime[D.cur ^ 1];
+      LC_GLOBAL int64_t* __restrict__ ks = gout(D.kstart[D.cur ^ 1]);
+      LC_GLOBAL uint64_t* __restrict__ kt = gout(D.ktime[D.cur ^ 1]);
       const int64_t i = w + tid;
       if (i < wend) {
         const int64_t li = i - D.win_base;
