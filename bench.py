@@ -243,7 +243,8 @@ def bench_batch(args, lc):
     note("small chains done")
 
     runner = batching.BatchRunner(chains, budget)
-    tune = runner.autotune((2048, 8192, 16384), 1)
+    tune = runner.autotune_tiles(lc.DEFAULT_TILE_SHAPES, (2048, 8192, 16384), 1)
+    note("tile shapes and grids tuned")
     runner.update(1, accumulate=False)
     el_b, ops_b = _timed_passes(lambda: runner.update(1), chains, args.steps)
     n_groups = len(runner.groups)
@@ -267,8 +268,11 @@ def bench_batch(args, lc):
                    "chains": len(chains), "scratch_budget_bytes": budget},
         "plain": {"value": ops_p / el_p, "ms_per_step": el_p / args.steps * 1e3,
                   "how": "512 sequential lc_update(1) calls per step, each chain's own graph"},
-        "batched": {"groups": n_groups, "grids": [g for g, _ in tune],
-                    "group_ms_per_sweep": [round(ms, 3) for _, ms in tune]},
+        "batched": {"groups": n_groups, "grids": [g for _, g, _ in tune],
+                    "tile_shapes": [list(sh) for sh, _, _ in tune],
+                    "group_ms_per_sweep": [round(ms, 3) for _, _, ms in tune],
+                    "how": "footprint-packed groups, each one captured sweep; (tile shape, grid) "
+                           "per group by lc_batch_autotune_tiles"},
         "speedup_vs_plain": (ops_b / el_b) / (ops_p / el_p),
         "small_chains": {"chains": len(small), "ops_per_step": ops_sp / args.steps,
                          "plain_value": ops_sp / el_sp, "batched_value": ops_sb / el_sb,

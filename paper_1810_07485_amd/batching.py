@@ -6,13 +6,14 @@ whose per-sweep scratch fits a budget (first fit, largest first); every group
 is one lc_batch, i.e. one captured launch sequence per sweep over all of its
 members.  All groups use the same stream, so they share one scratch arena in
 the library: device memory is the world lines of every chain plus the
-scratch of the largest group.  The grid size of each group is chosen by the
-library's autotuner.  Results of every chain equal its alone-run bit for bit
-(schedule and grouping never change the arithmetic).
+scratch of the largest group.  The grid size of each group, and with
+autotune_tiles its linking-tile shape, is chosen by the library's autotuner.
+Results of every chain equal its alone-run bit for bit (schedule, tile shape
+and grouping never change the arithmetic).
 """
 from __future__ import annotations
 
-from . import Batch, Chain, DEFAULT_GRIDS, lc_footprint_parts
+from . import Batch, Chain, DEFAULT_GRIDS, DEFAULT_TILE_SHAPES, lc_footprint_parts
 
 
 def pack(scratch: list, budget: int) -> list:
@@ -55,6 +56,18 @@ class BatchRunner:
             best, ms = b.autotune(grids, trial_sweeps)
             self.grids[k] = best
             out.append((best, ms))
+        return out
+
+    def autotune_tiles(self, shapes=DEFAULT_TILE_SHAPES, grids=DEFAULT_GRIDS,
+                       trial_sweeps: int = 1) -> list:
+        """Choose each group's (tile shape, grid) pair; every chain advances by
+        len(shapes) * len(grids) * (trial_sweeps + 1) unaccumulated sweeps.
+        Returns [(shape, grid, ms per sweep)] per group."""
+        out = []
+        for k, b in enumerate(self.batches):
+            shape, grid, ms = b.autotune_tiles(shapes, grids, trial_sweeps)
+            self.grids[k] = grid
+            out.append((shape, grid, ms))
         return out
 
     def update(self, n_sweeps: int = 1, accumulate: bool = True):

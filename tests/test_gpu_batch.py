@@ -145,6 +145,30 @@ def test_footprint_packed_runner_with_autotune_equals_alone(lc):
     r.close()
 
 
+def test_runner_tile_autotune_equals_alone(lc):
+    """The packed runner choosing a linking-tile shape and a grid per group:
+    every chain still ends where its alone-run does."""
+    from paper_1810_07485_amd import batching, workloads
+    inst = workloads.batch_instances(12, L_min=16, L_max=256)
+    specs = [(i.L, i.S, i.beta, i.seed) for i in inst]
+    chains = [lc.Chain(*s) for s in specs]
+    parts = [lc.lc_footprint_parts(*s[:3])[1] for s in specs]
+    r = batching.BatchRunner(chains, max(parts) + sum(parts) // 3)
+    shapes, grids = ((0, 0), (1, 300), (16, 1500)), (128, 512)
+    tune = r.autotune_tiles(shapes, grids, trial_sweeps=1)
+    assert len(tune) == len(r.batches)
+    assert all(sh in shapes and g in grids and ms > 0 for sh, g, ms in tune)
+    r.update(2)
+    n_sweeps = len(shapes) * len(grids) * 2 + 2
+    for s, c in zip(specs, chains):
+        ref = lc.Chain(*s)
+        ref.update(n_sweeps)
+        same_state(c.export_state(), ref.export_state())
+        assert c.last_sweep() == ref.last_sweep(), s
+        ref.close()
+    r.close()
+
+
 def test_chain_autotune_keeps_results(lc):
     a, b = lc.Chain(130, 0.5, 100.5, 3), lc.Chain(130, 0.5, 100.5, 3)
     best, ms = a.autotune((128, 512), trial_sweeps=2)
