@@ -166,8 +166,10 @@ struct Partial {
 // ---------------------------------------------------------------------------
 // Bonds touching a subspin x = (j, a): the 2S "left" bonds from (j-1, a') and
 // the 2S "right" bonds to (j+1, c).  For S=1/2 these are bonds j-1 and j.
+// (S = 1/2 takes a path without integer division.)
 __device__ inline int64_t bond_touching(const ChainDesc& D, int64_t x, int idx) {
   const int64_t ts = D.two_s;
+  if (ts == 1) return idx == 0 ? (x == 0 ? D.L - 1 : x - 1) : x;
   const int64_t j = x / ts, a = x - j * ts;
   if (idx < ts) {
     const int64_t jl = (j == 0) ? D.L - 1 : j - 1;
@@ -175,9 +177,12 @@ __device__ inline int64_t bond_touching(const ChainDesc& D, int64_t x, int idx) 
   }
   return (j * ts + a) * ts + (idx - ts);
 }
-__device__ inline int64_t bond_x(const ChainDesc& D, int64_t b) { return b / D.two_s; }
+__device__ inline int64_t bond_x(const ChainDesc& D, int64_t b) {
+  return D.two_s == 1 ? b : b / D.two_s;
+}
 __device__ inline int64_t bond_y(const ChainDesc& D, int64_t b) {
   const int64_t ts = D.two_s;
+  if (ts == 1) return b + 1 == D.L ? 0 : b + 1;
   const int64_t c = b % ts, x = b / ts, j = x / ts;
   const int64_t jn = (j + 1 == D.L) ? 0 : j + 1;
   return jn * ts + c;
@@ -252,6 +257,31 @@ __device__ inline uint64_t cand_time(const ChainDesc& D, int64_t b, uint64_t k, 
   return D.w == 0 ? v : ((k << (64 - D.w)) | (v >> D.w));
 }
 
+// Candidate times j0 .. j0 + m - 1 of window (b, k), j0 a multiple of
+// kChunk, 1 <= m <= kChunk (unused entries 0).  Even draw 2i is the upper
+// half of call i (call 0's is v0), odd draw 2i + 1 the lower half of call
+// i + 1: the chunk's first draw takes a call of its own when j0 > 0, and
+// then each call gives two consecutive draws.  Every entry of tc is written
+// once with a constant index, so the array stays in registers.
+static_assert(kChunk % 2 == 0, "chunks start at even draws");
+__device__ inline void chunk_times(const ChainDesc& D, int64_t b, uint64_t k, uint64_t v0, int j0,
+                                   int m, uint64_t (&tc)[kChunk]) {
+  const uint32_t c0 = static_cast<uint32_t>(j0 >> 1);
+  tc[0] = in_window(D, k, j0 == 0 ? v0 : hi64(cand_call(D, b, k, c0)));
+#pragma unroll
+  for (int p = 0; p < kChunk / 2; ++p) {
+    const int j = 2 * p + 1;  // draws j0 + j (lower half) and j0 + j + 1 (upper half)
+    uint64_t lo = 0, hi = 0;
+    if (j < m) {
+      const u32x4 r = cand_call(D, b, k, c0 + 1 + static_cast<uint32_t>(p));
+      lo = in_window(D, k, lo64(r));
+      hi = j + 1 < m ? in_window(D, k, hi64(r)) : 0;
+    }
+    tc[j] = lo;
+    if (j + 1 < kChunk) tc[j + 1] = hi;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Insertion of diagonal operators and removal of old ones (steps 2-6):
 // per (bond, window) the Poisson count from one 64-bit draw against the
@@ -267,7 +297,7 @@ __global__ __launch_bounds__(kBlock) void k_gen(const ChainDesc* __restrict__ de
                                                 uint64_t* __restrict__ optime,
                                                 uint8_t* __restrict__ optype, int64_t op_cap,
                                                 unsigned long long* __restrict__ stats,
-                                                uint32_t* __restrict__ flags) {
+                                                uint32_t* __restrict__ flags, int skip_split) {
   // only the writing pass keeps candidate times (LDS bounds its occupancy)
   __shared__ uint64_t slot[WRITE ? kCap * kBlock : 1];
   const int tid = threadIdx.x;
@@ -281,6 +311,7 @@ __global__ __launch_bounds__(kBlock) void k_gen(const ChainDesc* __restrict__ de
       const int c = chain_of(win_bases, nchain, i);
       if (!WRITE) part.at(c, stats, nchain, kIdx);
       const ChainDesc& D = descs[c];
+      if (!WRITE && skip_split && D.two_s > 1) continue;  // counted by k_gen_split
       const LC_GLOBAL uint8_t* __restrict__ s0 = gin(D.s0[D.cur]);
       const LC_GLOBAL int64_t* __restrict__ kstart = gin(D.kstart[D.cur]);
       const LC_GLOBAL uint64_t* __restrict__ ktime = gin(D.ktime[D.cur]);
@@ -309,24 +340,8 @@ __global__ __launch_bounds__(kBlock) void k_gen(const ChainDesc* __restrict__ de
         // n > kCap here whenever WRITE, so no candidate goes to LDS
         for (int j0 = 0; j0 < n; j0 += kChunk) {
           const int m = (n - j0 < kChunk) ? n - j0 : kChunk;
-          // one Philox call per pair of draws (2i-1, 2i); a chunk starts at an
-          // even draw, so only its first (draw j0 > 0) needs a call of its own
           uint64_t tc[kChunk];
-#pragma unroll
-          for (int j = 0; j < kChunk; ++j) {
-            const int jj = j0 + j;
-            if (j >= m) {
-              tc[j] = 0;
-            } else if (jj == 0) {
-              tc[j] = in_window(D, k, v0);
-            } else if (jj & 1) {
-              const u32x4 r = cand_call(D, b, k, static_cast<uint32_t>((jj + 1) >> 1));
-              tc[j] = in_window(D, k, lo64(r));
-              if (j + 1 < kChunk) tc[j + 1] = j + 1 < m ? in_window(D, k, hi64(r)) : 0;
-            } else if (j == 0) {
-              tc[j] = in_window(D, k, hi64(cand_call(D, b, k, static_cast<uint32_t>(jj >> 1))));
-            }
-          }
+          chunk_times(D, b, k, v0, j0, m, tc);
           accm |= static_cast<uint64_t>(antiparallel_mask(D, s0, kstart, ktime, b, k, tc, m)) << j0;
         }
       }
@@ -489,6 +504,242 @@ __device__ inline int64_t block_exclusive_scan(int64_t v, int64_t* sh, int64_t& 
   total = sh[kBlock / 64];
   __syncthreads();
   return r;
+}
+
+// Counting pass of split-spin chains, by tiles.  The antiparallel test of a
+// candidate on bond b = (x, y) needs the spins of subspins x and y at its
+// time, and a subspin's spin flips at every kept operator on the 2 (2S)
+// bonds touching it.  Per window, the kept operators on those bonds are
+// gathered once per subspin into an LDS list (time and bond of each), with
+// the subspin's spin at the window's start; every bond then tests its
+// candidates against the two lists of its ends instead of reading
+// 2 (2 (2S) - 1) bonds' windows from HBM.  Bond b's own operators are in
+// both lists and cancel, as they do in the XOR of the two spins.
+//
+// A tile is gj spins x gk windows of one chain, one thread per bond-window
+// (gj (2S)^2 gk <= 256).  Its lists are those of the subspins of spins
+// j0 .. j0 + gj (the last one holds right ends only), filled from the bonds
+// of spins j0 - 1 .. j0 + gj (modulo L).  A tile whose lists exceed the LDS
+// tests its windows one by one as k_gen does.  The result is the same
+// integers as k_gen's counting pass: counts, acceptance masks, statistics.
+constexpr int kGenLists = 256;   // subspin-window lists of a tile
+constexpr int kGenEnt = 2560;    // list entries (each kept operator in up to two lists)
+constexpr int kGenChains = 512;  // chains of one launch (tile bases in LDS)
+
+__host__ __device__ inline int gen_gk(int ts, int64_t W) {
+  int gk = 8;
+  while (gk > 1 && (gk > W || ts * ts * gk > kBlock)) gk >>= 1;
+  return gk;
+}
+__host__ __device__ inline int gen_gj(int ts, int gk) { return kBlock / (ts * ts * gk); }
+
+__global__ __launch_bounds__(kBlock) void k_gen_split(const ChainDesc* __restrict__ descs,
+                                                      const int* __restrict__ grp_chain, int ngrp,
+                                                      int nchain, int64_t* __restrict__ opstart,
+                                                      uint32_t* __restrict__ accmask,
+                                                      unsigned long long* __restrict__ stats) {
+  __shared__ int64_t gbase[kGenChains + 1];  // first tile of each chain of the launch
+  __shared__ int lcnt[kGenLists], loff[kGenLists], lcur[kGenLists];
+  __shared__ uint32_t lpar[kGenLists];       // spin of the list's subspin at its window's start
+  __shared__ uint64_t et[kGenEnt];           // list entries: time
+  __shared__ uint16_t eb[kGenEnt];           //               bond, as its index q / nk below
+  __shared__ int64_t scan[kWaves + 1];
+  const int tid = threadIdx.x;
+  constexpr int kIdx[2] = {ST_CAND, ST_ACC};
+  Partial<2> part;
+  if (ngrp > kGenChains) return;  // the host launches within the bound
+  {
+    int64_t total = 0;
+    for (int base = 0; base < ngrp; base += kBlock) {
+      int64_t cnt = 0;
+      if (base + tid < ngrp) {
+        const ChainDesc& D = descs[grp_chain[base + tid]];
+        const int64_t W = int64_t(1) << D.w;
+        const int gk = gen_gk(D.two_s, W), gj = gen_gj(D.two_s, gk);
+        cnt = ((D.L + gj - 1) / gj) * (W / gk);
+      }
+      int64_t t2;
+      const int64_t ex = block_exclusive_scan(cnt, scan, t2);
+      if (base + tid < ngrp) gbase[base + tid] = total + ex;
+      total += t2;
+    }
+    if (tid == 0) gbase[ngrp] = total;
+    __syncthreads();
+  }
+  const int64_t ntiles = gbase[ngrp];
+  for (int64_t t = xcd_block(); t < ntiles; t += gridDim.x) {
+    int lo = 0, hi = ngrp - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (gbase[mid] <= t)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const int c = grp_chain[lo];
+    part.at(c, stats, nchain, kIdx);
+    const ChainDesc& D = descs[c];
+    const LC_GLOBAL uint8_t* __restrict__ s0 = gin(D.s0[D.cur]);
+    const LC_GLOBAL int64_t* __restrict__ kstart = gin(D.kstart[D.cur]);
+    const LC_GLOBAL uint64_t* __restrict__ ktime = gin(D.ktime[D.cur]);
+    const int ts = static_cast<int>(D.two_s), ts2 = ts * ts;
+    const int64_t L = D.L, W = int64_t(1) << D.w;
+    const int gk = gen_gk(ts, W), gj = gen_gj(ts, gk);
+    const int64_t ntk = W / gk;  // tiles window-major: neighbours in time share cache lines
+    const int64_t lt = t - gbase[lo];
+    const int64_t j0 = (lt / ntk) * gj, k0 = (lt % ntk) * gk;
+    const int nj = static_cast<int>(min(static_cast<int64_t>(gj), L - j0));
+    const int nk = gk, lognk = __ffs(gk) - 1;  // gk is a power of two
+    // spin j0 + d modulo L for -1 <= d < 2 L (no 64-bit division in the loops)
+    auto spin_at = [&](int64_t d) -> int64_t {
+      int64_t j = j0 + d;
+      if (j < 0) j += L;
+      if (j >= L) j -= L;
+      return j;
+    };
+    const int nls = static_cast<int>(min(static_cast<int64_t>(nj + 1), L));  // spins with lists
+    const int nbs = static_cast<int>(min(static_cast<int64_t>(nj + 2), L));  // spins with bonds read
+    const int nlists = nls * ts * nk;  // <= kGenLists whenever gj (2S)^2 gk <= 256, 2S >= 2
+    const int nq = nbs * ts2 * nk;
+    const bool fit = nlists <= kGenLists;  // block-uniform
+    // list of subspin (spin j0 + v, a) in window k0 + kk: (v ts + a) nk + kk
+    for (int l = tid; fit && l < nlists; l += kBlock) {
+      const int va = l >> lognk, v = va / ts, a = va - v * ts;
+      lcnt[l] = 0;
+      lpar[l] = s0[spin_at(v) * ts + a];
+    }
+    __syncthreads();
+    // the bond-window q of the spins read: bond bl of spin j0 - 1 + u, window k0 + kk
+    // (spin index u, bond bl) of a list entry, kept as u ts2 + bl
+    auto ent_bond = [&](uint32_t id) -> int64_t {
+      const int u = static_cast<int>(id) / ts2;
+      return spin_at(u - 1) * ts2 + (static_cast<int>(id) - u * ts2);
+    };
+    auto bond_q = [&](int q, int64_t* bb, int* ll, int* lr, int* kk) {
+      const int ub = q >> lognk, u = ub / ts2, bl = ub - u * ts2;
+      *kk = q & (nk - 1);
+      *bb = spin_at(u - 1) * ts2 + bl;
+      // list slots of the bond's ends: spin j0 - 1 + u is slot u - 1 (mod L)
+      int vl = u - 1, vr = u;
+      if (vl < 0) vl += static_cast<int>(L);
+      if (vr == L) vr = 0;
+      const int a = bl / ts, c = bl - a * ts;
+      *ll = vl < nls ? ((vl * ts + a) << lognk) + *kk : -1;
+      *lr = vr < nls ? ((vr * ts + c) << lognk) + *kk : -1;
+    };
+    for (int q = tid; fit && q < nq; q += kBlock) {
+      int64_t bb;
+      int ll, lr, kk;
+      bond_q(q, &bb, &ll, &lr, &kk);
+      const int64_t i0 = bb * W;
+      const int64_t ka = kstart[i0 + k0 + kk], kb = kstart[i0 + k0 + kk + 1];
+      const int cnt = static_cast<int>(kb - ka);
+      const uint32_t par = static_cast<uint32_t>((ka - kstart[i0]) & 1);
+      if (ll >= 0) {
+        atomicAdd(lcnt + ll, cnt);
+        if (par) atomicXor(lpar + ll, 1u);
+      }
+      if (lr >= 0) {
+        atomicAdd(lcnt + lr, cnt);
+        if (par) atomicXor(lpar + lr, 1u);
+      }
+    }
+    __syncthreads();
+    int64_t nent;
+    {
+      const int64_t v = fit && tid < nlists ? lcnt[tid] : 0;
+      const int64_t ex = block_exclusive_scan(v, scan, nent);
+      if (fit && tid < nlists) loff[tid] = lcur[tid] = static_cast<int>(ex);
+    }
+    const bool lists = fit && nent <= kGenEnt;  // block-uniform
+    __syncthreads();
+    if (lists) {
+      for (int q = tid; q < nq; q += kBlock) {
+        int64_t bb;
+        int ll, lr, kk;
+        bond_q(q, &bb, &ll, &lr, &kk);
+        const int64_t i0 = bb * W;
+        const int64_t ka = kstart[i0 + k0 + kk], kb = kstart[i0 + k0 + kk + 1];
+        for (int64_t p = ka; p < kb; ++p) {
+          const uint64_t tp = ktime[p];
+          const uint16_t id = static_cast<uint16_t>(q >> lognk);
+          if (ll >= 0) {
+            const int e = atomicAdd(lcur + ll, 1);
+            et[e] = tp;
+            eb[e] = id;
+          }
+          if (lr >= 0) {
+            const int e = atomicAdd(lcur + lr, 1);
+            et[e] = tp;
+            eb[e] = id;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    uint32_t ncand = 0, nacc = 0;
+    if (tid < nj * ts2 * nk) {
+      const int lb = tid >> lognk, kk = tid & (nk - 1);
+      const int64_t b = j0 * ts2 + lb;
+      const uint64_t k = static_cast<uint64_t>(k0 + kk);
+      const int64_t li = b * W + static_cast<int64_t>(k);
+      const u32x4 r0 = philox10(D.seed, static_cast<uint32_t>(k), DOM_INS << 24,
+                                static_cast<uint32_t>(b), D.sweep);
+      const uint64_t u = lo64(r0), v0 = hi64(r0);
+      int n = 0;
+      while (n < D.K && u >= D.T[n]) ++n;
+      ncand = static_cast<uint32_t>(n);
+      // the lists of the two ends: x = (j0 + lb / ts2, a), y = (next spin, c)
+      const int vx = lb / ts2, ac = lb - vx * ts2, a = ac / ts, cy = ac - a * ts;
+      const int vy = vx + 1 == L ? 0 : vx + 1;
+      const int lx = ((vx * ts + a) << lognk) + kk, ly = ((vy * ts + cy) << lognk) + kk;
+      uint64_t accm = 0;
+      for (int c0 = 0; c0 < n; c0 += kChunk) {
+        const int m = (n - c0 < kChunk) ? n - c0 : kChunk;
+        uint64_t tc[kChunk];
+        chunk_times(D, b, k, v0, c0, m, tc);
+        uint32_t mask;
+        if (lists) {
+          uint32_t base = lpar[lx] ^ lpar[ly], flips = 0, ties = 0;
+#pragma unroll
+          for (int side = 0; side < 2; ++side) {
+            const int l = side ? ly : lx;
+            for (int e = loff[l]; e < loff[l] + lcnt[l]; ++e) {
+              const uint64_t tp = et[e];
+#pragma unroll
+              for (int j = 0; j < kChunk; ++j) {
+                flips ^= (tp < tc[j] ? 1u : 0u) << j;
+                ties |= (tp == tc[j] ? 1u : 0u) << j;
+              }
+            }
+          }
+          // a kept operator at exactly a candidate's time precedes it when
+          // its bond is the smaller one (never met in practice: 64-bit times)
+          if (ties & ((1u << m) - 1u)) {
+            for (int side = 0; side < 2; ++side) {
+              const int l = side ? ly : lx;
+              for (int e = loff[l]; e < loff[l] + lcnt[l]; ++e)
+                for (int j = 0; j < m; ++j)
+                  if (et[e] == tc[j] && ent_bond(eb[e]) < b) flips ^= 1u << j;
+            }
+          }
+          const uint32_t live = (1u << m) - 1u;
+          mask = ((base & 1u) ? ~flips : flips) & live;
+        } else {
+          mask = antiparallel_mask(D, s0, kstart, ktime, b, k, tc, m);
+        }
+        accm |= static_cast<uint64_t>(mask) << c0;
+      }
+      nacc = static_cast<uint32_t>(__popcll(accm));
+      const int64_t i = D.win_base + li;
+      opstart[i] = (kstart[li + 1] - kstart[li]) + nacc;
+      accmask[i] = static_cast<uint32_t>(accm);
+    }
+    part.v[0] += ncand;
+    part.v[1] += nacc;
+    __syncthreads();  // the LDS is reused by the next tile
+  }
+  part.flush(stats, nchain, kIdx);
 }
 
 // Boundary nodes start as their own roots (operator nodes get their parent
@@ -1005,7 +1256,8 @@ __global__ __launch_bounds__(kBlock) void k_link_tile(
     const ChainDyn dy = dyn[c];
     const int64_t lt = t - grp_tile_base[p];
     const int64_t W = int64_t(1) << D.w;
-    const int64_t tj = lt % D.ntj, tk = lt / D.ntj;
+    const int64_t ntk = (W + D.tile_k - 1) / D.tile_k;  // window-major tile order
+    const int64_t tk = lt % ntk, tj = lt / ntk;
     const int64_t j0 = tj * D.tile_j, k0 = tk * D.tile_k;
     const int nj = static_cast<int>(min(static_cast<int64_t>(D.tile_j), D.L - j0));
     const int nk = static_cast<int>(min(static_cast<int64_t>(D.tile_k), W - k0));
@@ -1689,7 +1941,8 @@ __global__ __launch_bounds__(kBlock) void k_flip_tiles(
     const ChainDyn dy = dyn[c];
     const int64_t lt = t - grp_tile_base[p];
     const int64_t W = int64_t(1) << D.w;
-    const int64_t tj = lt % D.ntj, tk = lt / D.ntj;
+    const int64_t ntk = (W + D.tile_k - 1) / D.tile_k;  // window-major tile order
+    const int64_t tk = lt % ntk, tj = lt / ntk;
     const int64_t j0 = tj * D.tile_j, k0 = tk * D.tile_k;
     const int nj = static_cast<int>(min(static_cast<int64_t>(D.tile_j), D.L - j0));
     const int nk = static_cast<int>(min(static_cast<int64_t>(D.tile_k), W - k0));
@@ -2162,9 +2415,19 @@ hipError_t lc_launch_sweep(const LcSweepArgs& A, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, A.dyncnt, 4, 0ull);
   // 1. count operators per window, 2. scan
   mark(LC_PH_GEN_COUNT);
+  // split-spin chains are counted by tiles when every group fits the LDS bases
+  bool split_tiles = A.any_split != 0;
+  for (int gi = 0; gi < A.ngroups; ++gi)
+    if (A.groups[gi].two_s > 1 && A.groups[gi].nchain > kGenChains) split_tiles = false;
   hipLaunchKernelGGL((k_gen<false>), dim3(grid_for(A.nwin, G)), dim3(kBlock), 0, s, A.descs,
                      A.win_bases, A.nchain, A.nwin, A.opstart, A.accmask, A.optime, A.optype,
-                     A.op_cap, st, A.flags);
+                     A.op_cap, st, A.flags, split_tiles ? 1 : 0);
+  for (int gi = 0; split_tiles && gi < A.ngroups; ++gi) {
+    const LcTileGroup& g = A.groups[gi];
+    if (g.two_s > 1)
+      hipLaunchKernelGGL(k_gen_split, dim3(G), dim3(kBlock), 0, s, A.descs, A.grp_chain + g.offset,
+                         g.nchain, A.nchain, A.opstart, A.accmask, st);
+  }
   mark(LC_PH_SCAN_OPS);
   (void)lc_launch_scan(A.opstart, A.nwin, A.scan_tmp, s);
   hipLaunchKernelGGL(k_chain_bases, dim3(grid_for(A.nchain, 64)), dim3(kBlock), 0, s, A.descs,
@@ -2174,7 +2437,7 @@ hipError_t lc_launch_sweep(const LcSweepArgs& A, hipStream_t s) {
   mark(LC_PH_GEN_WRITE);
   hipLaunchKernelGGL((k_gen<true>), dim3(grid_for(A.nwin, G)), dim3(kBlock), 0, s, A.descs,
                      A.win_bases, A.nchain, A.nwin, A.opstart, A.accmask, A.optime, A.optype,
-                     A.op_cap, st, A.flags);
+                     A.op_cap, st, A.flags, 0);
   // 4. loop graph and union-find: tiles, then the edges between them
   mark(LC_PH_LINK_TILES);
   hipLaunchKernelGGL(k_init_bnodes, dim3(grid_for(A.nbn, G)), dim3(kBlock), 0, s, A.bn_bases,
