@@ -1713,6 +1713,238 @@ __global__ __launch_bounds__(kBlock) void k_roots_items(
   part.flush(stats, nchain, kIdx);
 }
 
+// Per-loop records (before the flip) of the open loops, from their items:
+//   [0] nodes + (top nodes << 40)
+//   [1] sum of +-hi32(t), [2] sum of +-lo32(t)  over operator nodes: lower
+//       nodes count +t, upper nodes -t (two vertical segments end / start)
+//   [3] chain, bit 63: the loop's flip decision -- the bit of its label
+//       (set when the root is numbered), or the XOR of its nodes' votes
+// so the loop length is 2^64 tops + 2 (2^32 [1] + [2]) ticks.  A fragment
+// brings its node count and its sums; a boundary node one node (a top node
+// also 2^64 of length); every word takes plain additions (exact modulo 2^64,
+// the true values fit).  Bottom boundary nodes add 1 + (spin << 32) to bacc
+// of their loop's root subspin.
+//
+// A workgroup takes chunks of kAccHash items and sums them per loop in an
+// LDS hash table (open addressing on the loop index, LDS atomics), then
+// adds each distinct loop's sums to its record with one set of device
+// atomics (executed at the memory side: what this pass is bound by).
+// Fragments leave the linking tiles in tile order, and at S > 1/2 the loops
+// are long and tiles adjacent in time hold many pieces of the same loops, so
+// a chunk holds several items of most of its loops (at S = 4 this pass
+// takes a fifth of the time of the per-wave reduction below).  Taken when
+// any chain has S > 1/2.  A loop with items in nearly every
+// chunk (the largest loops at low temperature) would still take a set of
+// atomics on one record per chunk: the workgroup carries the sums of one
+// such loop -- a chunk's busiest, once it holds kAccHot items there -- from
+// chunk to chunk and adds them once, at the end or when the loop is absent
+// from a chunk and another busy one takes its place.
+constexpr int kAccHash = 1024;  // LDS slots = items per chunk: the table never fills
+constexpr int kAccPer = kAccHash / kBlock;
+constexpr unsigned long long kAccEmpty = ~0ull;
+static_assert(kAccHash == 1024, "the slot hash takes 10 bits");
+constexpr uint32_t kAccHot = 64;
+
+__device__ inline void acc_add(unsigned long long* acc, unsigned long long key, uint64_t v0,
+                               uint64_t v1, uint64_t v2, uint32_t x) {
+  unsigned long long* a = acc + kAccWords * static_cast<int64_t>(key);
+  atomicAdd(a + 0, static_cast<unsigned long long>(v0));
+  if (v1) atomicAdd(a + 1, static_cast<unsigned long long>(v1));
+  if (v2) atomicAdd(a + 2, static_cast<unsigned long long>(v2));
+  if (x & 1) atomicXor(a + 3, 1ull << 63);
+}
+
+__global__ __launch_bounds__(kBlock) void k_accum_hash(
+    const ChainDesc* __restrict__ descs, const int64_t* __restrict__ frag,
+    const unsigned long long* __restrict__ dyncnt, int64_t fcap, const int64_t* __restrict__ bn_bases,
+    int nchain, int64_t nbn, const ChainDyn* __restrict__ dyn, const int64_t* __restrict__ parent,
+    unsigned long long* __restrict__ acc, unsigned long long* __restrict__ bacc,
+    const int64_t* __restrict__ nloops, uint32_t* __restrict__ flags) {
+  __shared__ unsigned long long hkey[kAccHash];
+  __shared__ unsigned long long hv0[kAccHash], hv1[kAccHash], hv2[kAccHash];
+  __shared__ uint32_t hx[kAccHash];  // bit 0: XOR of votes; bits 16..: items
+  __shared__ unsigned long long ck, cv0, cv1, cv2;  // the carried loop and its sums
+  __shared__ uint32_t cx, cfound, wbest[kWaves];
+  __shared__ uint32_t fl;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    fl = *flags;
+    ck = kAccEmpty;
+    cv0 = cv1 = cv2 = 0;
+    cx = cfound = 0;
+  }
+  __syncthreads();
+  if (fl) return;
+  const int64_t nl = *nloops;
+  int64_t nf;
+  const int64_t n = items_count(dyncnt, fcap, nbn, &nf);
+  const int64_t nchunks = (n + kAccHash - 1) / kAccHash;
+  for (int64_t ch = xcd_block(); ch < nchunks; ch += gridDim.x) {
+    for (int h = tid; h < kAccHash; h += kBlock) {
+      hkey[h] = kAccEmpty;
+      hv0[h] = hv1[h] = hv2[h] = 0;
+      hx[h] = 0;
+    }
+    __syncthreads();
+    const int lane = lane_id();
+    // the items' dependent reads (node, its word, its rep's word) are issued
+    // for all of a thread's items before any is used
+    int64_t gq[kAccPer], pq[kAccPer], cq[kAccPer];
+    int chq[kAccPer];
+#pragma unroll
+    for (int q = 0; q < kAccPer; ++q) {
+      const int64_t i = ch * kAccHash + q * kBlock + tid;
+      chq[q] = 0;
+      gq[q] = i < n ? item_node(i, nf, frag, bn_bases, nchain, dyn, &chq[q]) : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < kAccPer; ++q) pq[q] = gq[q] >= 0 ? parent[gq[q]] : -1;
+#pragma unroll
+    for (int q = 0; q < kAccPer; ++q) cq[q] = (gq[q] >= 0 && pq[q] >= 0) ? parent[pq[q]] : pq[q];
+#pragma unroll
+    for (int q = 0; q < kAccPer; ++q) {
+      const int64_t i = ch * kAccHash + q * kBlock + tid;
+      int64_t r = -1;
+      uint64_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;  // w3: XOR of votes (bit 0)
+      if (i < n) {
+        const int c = chq[q];
+        const int64_t g = gq[q];
+        const int64_t p = pq[q];
+        const int64_t code = cq[q];
+        r = -1 - code;
+        if (code >= 0 || r >= nl) {  // not a numbered loop: inconsistent graph
+          atomicOr(flags, LC_FLAG_GRAPH);
+          r = -1;
+        } else if (i < nf) {
+          w0 = static_cast<uint64_t>(frag[4 * i + 1]) & 0x7FFFull;
+          w3 = (static_cast<uint64_t>(frag[4 * i + 1]) >> 15) & 1u;
+          w1 = static_cast<uint64_t>(frag[4 * i + 2]);
+          w2 = static_cast<uint64_t>(frag[4 * i + 3]);
+        } else {
+          const ChainDesc& D = descs[c];
+          const int64_t cb = dyn[c].node_base;
+          const int64_t v = g - cb;
+          const bool bottom = v < D.n_sites;
+          w0 = 1;
+          if (D.two_s == 1 || !bottom) w0 += 1ull << 40;  // a top node: + 2^64
+          if (D.flip_rule) w3 = vote_bit(D, v);
+          const int64_t root = (p >= 0 ? p : g) - cb;
+          if (bottom && root < D.n_sites)  // always true: the root is a bottom node
+            atomicAdd(bacc + D.site_base + root,
+                      1ull + (static_cast<uint64_t>(2 * static_cast<int64_t>(D.s0[D.cur][v]) - 1) << 32));
+        }
+      }
+      // Reduce by loop within the wave first (a large loop would otherwise
+      // queue many lanes on one LDS word): bitonic sort of one packed word
+      // per lane, (loop << 6) | lane (loop indices are below 2^40), so only
+      // the key moves through the 21 exchange stages; each lane fetches the
+      // sums of the item it ended up with, a segmented scan adds equal loops,
+      // and the last lane of each run adds them to the loop's slot.
+      uint64_t sk = r >= 0 ? ((static_cast<uint64_t>(r) << 6) | static_cast<uint64_t>(lane)) : ~0ull;
+#pragma unroll
+      for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+          const uint64_t pk = __shfl_xor(sk, j);
+          const bool ascending = (lane & k) == 0, lower = (lane & j) == 0;
+          const bool take = (lower == ascending) ? (pk < sk) : (pk > sk);
+          sk = take ? pk : sk;
+        }
+      }
+      const int src = static_cast<int>(sk & 63ull);
+      const int64_t key = sk == ~0ull ? -1 : static_cast<int64_t>(sk >> 6);
+      w0 = __shfl(w0, src);
+      w1 = __shfl(w1, src);
+      w2 = __shfl(w2, src);
+      w3 = __shfl(w3, src);
+      const int64_t pkey = __shfl_up(key, 1);
+      const unsigned long long heads = __ballot(lane == 0 || pkey != key);
+      const int seg = __popcll(heads & ((lane == 63) ? ~0ull : ((2ull << lane) - 1ull)));
+      uint32_t cnt = 1;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const int qs = __shfl_up(seg, d);
+        const uint64_t q0 = __shfl_up(w0, d), q1 = __shfl_up(w1, d), q2 = __shfl_up(w2, d);
+        const uint64_t q3 = __shfl_up(w3, d);
+        const uint32_t qc = __shfl_up(cnt, d);
+        if (lane >= d && qs == seg) {
+          w0 += q0;
+          w1 += q1;
+          w2 += q2;
+          w3 ^= q3;
+          cnt += qc;
+        }
+      }
+      const bool last = lane == 63 || ((heads >> (lane + 1)) & 1ull);
+      if (key < 0 || !last) continue;
+      // find or claim the loop's slot (at most kAccHash keys per chunk)
+      const unsigned long long uk = static_cast<unsigned long long>(key);
+      uint32_t h = static_cast<uint32_t>((uk * 0x9E3779B97F4A7C15ull) >> 54);  // 10 bits
+      for (;;) {
+        unsigned long long kk =
+            __hip_atomic_load(hkey + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (kk == kAccEmpty) {
+          kk = atomicCAS(hkey + h, kAccEmpty, uk);
+          if (kk == kAccEmpty) kk = uk;
+        }
+        if (kk == uk) break;
+        h = (h + 1) & (kAccHash - 1);
+      }
+      atomicAdd(hv0 + h, static_cast<unsigned long long>(w0));
+      if (w1) atomicAdd(hv1 + h, static_cast<unsigned long long>(w1));
+      if (w2) atomicAdd(hv2 + h, static_cast<unsigned long long>(w2));
+      atomicAdd(hx + h, (cnt << 16) | static_cast<uint32_t>(w3 & 1));
+    }
+    __syncthreads();
+    // the carried loop absorbs its slot; the busiest other loop is found
+    uint32_t best = 0;  // (items << 10) | slot
+    for (int h = tid; h < kAccHash; h += kBlock) {
+      const unsigned long long key = hkey[h];
+      if (key == kAccEmpty) continue;
+      if (key == ck) {  // one slot, one thread
+        cv0 += hv0[h];
+        cv1 += hv1[h];
+        cv2 += hv2[h];
+        cx ^= hx[h] & 1;
+        cfound = 1;
+        hkey[h] = kAccEmpty;
+      } else {
+        const uint32_t v = ((hx[h] >> 16) << 10) | static_cast<uint32_t>(h);
+        best = v > best ? v : best;
+      }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const uint32_t w = __shfl_xor(best, o);
+      best = w > best ? w : best;
+    }
+    if (lane_id() == 0) wbest[tid >> 6] = best;
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t b = 0;
+      for (int w = 0; w < kWaves; ++w) b = wbest[w] > b ? wbest[w] : b;
+      if (!cfound && (b >> 10) >= kAccHot) {
+        if (ck != kAccEmpty) acc_add(acc, ck, cv0, cv1, cv2, cx);
+        const int h = static_cast<int>(b & (kAccHash - 1));
+        ck = hkey[h];
+        cv0 = hv0[h];
+        cv1 = hv1[h];
+        cv2 = hv2[h];
+        cx = hx[h] & 1;
+        hkey[h] = kAccEmpty;
+      }
+      cfound = 0;
+    }
+    __syncthreads();
+    for (int h = tid; h < kAccHash; h += kBlock) {
+      const unsigned long long key = hkey[h];
+      if (key != kAccEmpty) acc_add(acc, key, hv0[h], hv1[h], hv2[h], hx[h]);
+    }
+    __syncthreads();  // the table is cleared for the next chunk
+  }
+  if (tid == 0 && ck != kAccEmpty) acc_add(acc, ck, cv0, cv1, cv2, cx);
+}
+
 __device__ inline uint32_t wave_max_u32(uint32_t v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
@@ -1731,17 +1963,11 @@ __device__ inline void flush_carry(unsigned long long* acc, int64_t key, uint64_
   if (v3 & 1) atomicXor(a + 3, 1ull << 63);
 }
 
-// Per-loop records (before the flip) of the open loops, from their items:
-//   [0] nodes + (top nodes << 40)
-//   [1] sum of +-hi32(t), [2] sum of +-lo32(t)  over operator nodes: lower
-//       nodes count +t, upper nodes -t (two vertical segments end / start)
-//   [3] chain, bit 63: the loop's flip decision -- the bit of its label
-//       (set when the root is numbered), or the XOR of its nodes' votes
-// so the loop length is 2^64 tops + 2 (2^32 [1] + [2]) ticks.  A fragment
-// brings its node count and its sums; a boundary node one node (a top node
-// also 2^64 of length); every word takes plain additions (exact modulo 2^64,
-// the true values fit).  Bottom boundary nodes add 1 + (spin << 32) to bacc
-// of their loop's root subspin.
+// The same records without an LDS table: each wave reduces its 64 items by
+// loop and issues one set of atomics per distinct loop, carrying the sums
+// of one hot loop across its steps.  Taken when every chain has S = 1/2:
+// there a 1,024-item chunk holds few more repeats of a loop than a wave
+// does, and this kernel, free of barriers and LDS, issues fewer atomics.
 __global__ __launch_bounds__(kBlock) void k_accum_items(
     const ChainDesc* __restrict__ descs, const int64_t* __restrict__ frag,
     const unsigned long long* __restrict__ dyncnt, int64_t fcap, const int64_t* __restrict__ bn_bases,
@@ -2478,9 +2704,9 @@ hipError_t lc_launch_sweep(const LcSweepArgs& A, hipStream_t s) {
                      A.bacc, A.root_cap, nchunks, A.rcnt, st, A.flags);
   // 6. estimators of the open loops, flips
   mark(LC_PH_ACCUM);
-  hipLaunchKernelGGL(k_accum_items, dim3(G), dim3(kBlock), 0, s, A.descs, A.frag, A.dyncnt, A.fcap,
-                     A.bn_bases, A.nchain, A.nbn, A.dyn, A.parent, A.acc, A.bacc, A.rcnt + nchunks,
-                     A.flags);
+  hipLaunchKernelGGL(A.any_split ? k_accum_hash : k_accum_items, dim3(G), dim3(kBlock), 0, s, A.descs,
+                     A.frag, A.dyncnt, A.fcap, A.bn_bases, A.nchain, A.nbn, A.dyn, A.parent, A.acc,
+                     A.bacc, A.rcnt + nchunks, A.flags);
   mark(LC_PH_CLUSTER_SUMS);
   // few resident threads: each flushes its partial sums with atomics
   hipLaunchKernelGGL(k_cluster_sums, dim3(G < 2048 ? G : 2048), dim3(kBlock), 0, s, A.nchain,
