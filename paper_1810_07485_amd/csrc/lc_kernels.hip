@@ -886,6 +886,11 @@ struct TileLists {
   uint16_t woff[kBlock + 1]; // first list entry of each walker
   int16_t wnl[kBlock];       // local index of wnxt, or -1
   uint8_t wflag[kBlock];     // bit 0: events before the window; bit 1: no event at all
+  uint64_t rnt[kRuns];       // time of the bond's first operator after the window (rflag bit 2)
+  uint16_t rtix[kRuns];      // the run's times: ltime[rtix + p] (staged when not owned)
+  uint8_t rflag[kRuns];      // bit 0: operators before the window; bit 1: none on the bond;
+                             // bit 2: an operator after the window
+  int xcur;                  // staging cursor in ltime, after the tile's own operators
 };
 
 template <int TS>
@@ -915,8 +920,7 @@ struct TileLds {
   int ncl;                           // closed components whose flip decision is drawn last
   uint32_t fl;
 };
-static_assert(sizeof(TileLists<2>) <= sizeof(int64_t) * 2 * TileCfg<2>::kSlots + 8 * TileCfg<2>::kSlots,
-              "split-spin event lists fit the slots' LDS");
+static_assert(sizeof(TileLds<8>) <= 80 * 1024, "two split-spin linking workgroups per CU");
 
 // Time of flat operator e whose tile-local index is li (-1: not the tile's):
 // from LDS or from HBM.  The LDS read is an atomic load so that the two
@@ -1079,7 +1083,7 @@ __device__ inline void tile_walk(TileLds<TS>& S, const ChainDesc& D, int64_t x, 
 // events than the lists hold (the caller flags the tile as too large).
 template <int TS>
 __device__ bool tile_walk_lists(TileLds<TS>& S, const ChainDesc& D, int64_t j0, int64_t k0, int nj,
-                                int nthr, int64_t nb0, int64_t node_base, int64_t B0, int nbt,
+                                int nthr, int64_t nb0, int64_t node_base, int64_t B0, int nbt, int nlo,
                                 const int64_t* __restrict__ opstart,
                                 const uint64_t* __restrict__ optime) {
   constexpr int NB = 2 * TS;
@@ -1104,44 +1108,60 @@ __device__ bool tile_walk_lists(TileLds<TS>& S, const ChainDesc& D, int64_t j0, 
       if (Lw.roff[r0 + q] <= within) s = q;
     return s;
   };
-  // 1. runs of every walker; the event after its window; the empty subspin
+  // 1. runs of every walker, one thread per run: its operators in the window,
+  // the bond's first operator after the window, whether the bond has
+  // operators before the window or none at all
+  const int nruns = nthr * NB;
+  if (nruns > WL::kRuns) return false;  // block-uniform
+  if (tid == 0) Lw.xcur = nlo;
+  for (int r = tid; r < nruns; r += kBlock) {
+    const int w = r / NB, q = r - w * NB;
+    const int64_t k = k0 + w / nx;
+    const int64_t bnd = bond_of(w, q);
+    const int64_t i0 = D.win_base + bnd * W;
+    const int64_t h = opstart[i0 + k], e = opstart[i0 + k + 1];
+    const int64_t b0 = opstart[i0], bw = opstart[i0 + W];
+    const int64_t lb = bnd - B0;
+    Lw.rstart[r] = h;
+    Lw.rlen[r] = static_cast<uint16_t>(min(e - h, int64_t(0xFFFF)));
+    Lw.rloc[r] = static_cast<int16_t>((lb >= 0 && lb < nbt) ? S.tpre[lb] + (h - S.tos[lb]) : -1);
+    uint32_t f = (b0 < h ? 1u : 0u) | (bw == b0 ? 2u : 0u);
+    if (e < bw) {
+      f |= 4u;
+      Lw.rnt[r] = op_time(S.ltime, tile_local(S, B0, nbt, bnd, e), optime, e);
+    }
+    Lw.rflag[r] = static_cast<uint8_t>(f);
+  }
+  __syncthreads();
+  // per walker: the offsets of its runs in its list, the event after its
+  // window (earliest in (time, bond) order), the empty subspin
   int64_t m = 0;
-  int fits = nthr * NB <= WL::kRuns ? 1 : 0;
-  if (tid < nthr && fits) {
-    const int kk = tid / nx;
-    const int64_t x = j0 * TS + tid % nx, k = k0 + kk;
+  int fits = 1;
+  if (tid < nthr) {
     bool before = false, empty = true;
     int64_t nxt = -1, bn = 0;
     uint64_t tn = 0;
     for (int q = 0; q < NB; ++q) {
-      const int64_t bnd = bond_of(tid, q);
-      const int64_t i0 = D.win_base + bnd * W;
-      const int64_t h = opstart[i0 + k], e = opstart[i0 + k + 1];
-      const int64_t b0 = opstart[i0], bw = opstart[i0 + W];
-      before = before || b0 < h;
-      empty = empty && bw == b0;
       const int r = tid * NB + q;
-      const int64_t lb = bnd - B0;
-      Lw.rstart[r] = h;
-      Lw.rlen[r] = static_cast<uint16_t>(e - h);
-      Lw.roff[r] = static_cast<uint16_t>(m);
-      Lw.rloc[r] = static_cast<int16_t>((lb >= 0 && lb < nbt) ? S.tpre[lb] + (h - S.tos[lb]) : -1);
-      m += e - h;
-      if (e < bw) {
-        const int li = tile_local(S, B0, nbt, bnd, e);
-        const uint64_t t = op_time(S.ltime, li, optime, e);
+      Lw.roff[r] = static_cast<uint16_t>(min(m, int64_t(0xFFFF)));
+      m += Lw.rlen[r];
+      const uint32_t f = Lw.rflag[r];
+      before = before || (f & 1u);
+      empty = empty && (f & 2u);
+      if (f & 4u) {
+        const int64_t bnd = bond_of(tid, q);
+        const uint64_t t = Lw.rnt[r];
         if (nxt < 0 || t < tn || (t == tn && bnd < bn)) {
-          nxt = e;
+          nxt = Lw.rstart[r] + Lw.rlen[r];
           tn = t;
           bn = bnd;
         }
       }
     }
-    fits = fits && m <= WL::kItems;
+    fits = m <= WL::kItems;
     Lw.wnxt[tid] = nxt;
     Lw.wnl[tid] = static_cast<int16_t>(nxt >= 0 ? tile_local(S, B0, nbt, bn, nxt) : -1);
     Lw.wflag[tid] = static_cast<uint8_t>((before ? 1 : 0) | (empty ? 2 : 0));
-    (void)x;
   }
   int64_t total;
   const int64_t ex = block_exclusive_scan(m, S.scan, total);
@@ -1155,7 +1175,23 @@ __device__ bool tile_walk_lists(TileLds<TS>& S, const ChainDesc& D, int64_t j0, 
     }
   }
   if (tid == 0) Lw.woff[nthr] = static_cast<uint16_t>(total);
+  // the times of runs on bonds the tile does not own go to ltime after the
+  // tile's own operators, so that every run's times are in LDS
+  for (int r = tid; r < nruns; r += kBlock) {
+    const int n = Lw.rlen[r];
+    if (Lw.rloc[r] >= 0) {
+      Lw.rtix[r] = static_cast<uint16_t>(Lw.rloc[r]);
+    } else if (n > 0) {
+      const int at = atomicAdd(&Lw.xcur, n);
+      Lw.rtix[r] = static_cast<uint16_t>(at < TileCfg<TS>::kOps ? at : 0);
+      if (at + n <= TileCfg<TS>::kOps)
+        for (int p = 0; p < n; ++p) S.ltime[at + p] = optime[Lw.rstart[r] + p];
+    } else {
+      Lw.rtix[r] = 0;
+    }
+  }
   __syncthreads();
+  const bool staged = Lw.xcur <= TileCfg<TS>::kOps;  // block-uniform
   const int nev = static_cast<int>(total);
   auto walker_of = [&](int g) -> int {
     int lo = 0, hi = nthr - 1;
@@ -1168,7 +1204,10 @@ __device__ bool tile_walk_lists(TileLds<TS>& S, const ChainDesc& D, int64_t j0, 
     }
     return lo;
   };
-  // 2. every event's place in its walker's list
+  // 2. every event's place in its walker's list: its position in its own
+  // run plus, for every other run, the number of the run's operators
+  // preceding it in (time, bond) order (a binary search, in the staged LDS
+  // times, or through run_time when they did not fit)
   for (int g = tid; g < nev; g += kBlock) {
     const int w = walker_of(g);
     const int within = g - Lw.woff[w];
@@ -1176,17 +1215,18 @@ __device__ bool tile_walk_lists(TileLds<TS>& S, const ChainDesc& D, int64_t j0, 
     const int s = run_of(r0, within);
     const int r = r0 + s, p = within - Lw.roff[r];
     const int64_t bnd = bond_of(w, s);
-    const uint64_t t = run_time(r, p);
+    const uint64_t t = staged ? S.ltime[Lw.rtix[r] + p] : run_time(r, p);
     int rank = p;
     for (int q = 0; q < NB; ++q) {
       const int rq = r0 + q;
       const int n = Lw.rlen[rq];
       if (q == s || n == 0) continue;
       const bool tie_before = bond_of(w, q) < bnd;  // equal times: smaller bond first
+      const int base = Lw.rtix[rq];
       int a = 0, b = n;
       while (a < b) {
         const int mid = (a + b) >> 1;
-        const uint64_t tm = run_time(rq, mid);
+        const uint64_t tm = staged ? S.ltime[base + mid] : run_time(rq, mid);
         if (tm < t || (tie_before && tm == t))
           a = mid + 1;
         else
@@ -1299,7 +1339,7 @@ __global__ __launch_bounds__(kBlock) void k_link_tile(
     // S = 1/2: a serial walker per (subspin, window) merges two bond runs;
     // split spins merge 2 (2S) runs through the per-subspin event lists
     if constexpr (TS > 1) {
-      if (!tile_walk_lists<TS>(S, D, j0, k0, nj, nthr, nb0, dy.node_base, B0, nbt, opstart, optime)) {
+      if (!tile_walk_lists<TS>(S, D, j0, k0, nj, nthr, nb0, dy.node_base, B0, nbt, nlo, opstart, optime)) {
         if (tid == 0) atomicOr(flags, LC_FLAG_TILE);  // block-uniform: the tile is too large
         break;
       }

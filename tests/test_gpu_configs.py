@@ -145,6 +145,9 @@ def test_largest_window_count(lc, orc):
     (64, 0.5, 64.0, 6, (8, 1500)),
     (8, 1.0, 16.5, 4, (2, 200)),         # split spins, two windows per tile
     (16, 4.0, 9.0, 5, (4, 1500)),        # S = 4: (2S)^2 x windows bounded by the lists
+    (8, 4.0, 64.0, 2, (2, 1400)),        # S = 4, two windows: the times of the bonds the tile
+                                         # does not own mostly overflow the LDS, so the walk
+                                         # places events by binary searches
 ])
 def test_tile_shapes_lockstep(lc, orc, L, S, beta, seed, shape):
     """The linking-tile shape is schedule only: every sweep equals the
