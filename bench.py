@@ -130,7 +130,7 @@ SURVEY_BYTES_PER_OP = 11.5 + 8 + 16 + 48 + 32 + 28
 
 
 PHASE_KERNELS = {
-    "gen_count": ["k_gen<false>", "k_gen_split"], "gen_write": ["k_gen<true>"],
+    "gen_count": ["k_gen<false>", "k_gen_split"], "gen_write": ["k_gen<true>", "k_gen_defer"],
     "link_tiles": ["k_init_bnodes", "k_link_tile<1>"], "link_cross": ["k_link_cross"],
     "compress": ["k_compress_items"], "roots": ["k_roots_items"], "accum": ["k_accum_items", "k_accum_hash"],
     "cluster_sums": ["k_cluster_sums"], "flip": ["k_flip_tiles", "k_flip_sites"],

@@ -297,7 +297,8 @@ __global__ __launch_bounds__(kBlock) void k_gen(const ChainDesc* __restrict__ de
                                                 uint64_t* __restrict__ optime,
                                                 uint8_t* __restrict__ optype, int64_t op_cap,
                                                 unsigned long long* __restrict__ stats,
-                                                uint32_t* __restrict__ flags, int skip_split) {
+                                                uint32_t* __restrict__ flags, int skip_split,
+                                                int64_t* __restrict__ defer) {
   // only the writing pass keeps candidate times (LDS bounds its occupancy)
   __shared__ uint64_t slot[WRITE ? kCap * kBlock : 1];
   const int tid = threadIdx.x;
@@ -326,6 +327,10 @@ __global__ __launch_bounds__(kBlock) void k_gen(const ChainDesc* __restrict__ de
       ncand = static_cast<uint32_t>(n);
       const bool inlds = WRITE && n <= kCap;
       const bool known = WRITE && n <= 32;
+      // windows with kCap < n <= 32 are written by k_gen_defer, a wave per
+      // window, so that no wave waits on one lane's redraws (0.1 % of the
+      // windows at the largest mean count, 4)
+      const bool deferred = known && !inlds;
       uint64_t accm = known ? accmask[i] : 0;
       if (known) {
         if (inlds) {
@@ -354,6 +359,10 @@ __global__ __launch_bounds__(kBlock) void k_gen(const ChainDesc* __restrict__ de
         const int64_t base = opstart[i];
         if (opstart[i + 1] > op_cap) {
           atomicOr(flags, 1u);
+        } else if (deferred) {
+          const unsigned long long at =
+              atomicAdd(reinterpret_cast<unsigned long long*>(defer + nwin), 1ull);
+          defer[at] = i;
         } else if (inlds) {
           // accepted candidates in draw order, then a stable insertion sort
           // (equal times keep draw order), then one merge with the kept
@@ -504,6 +513,69 @@ __device__ inline int64_t block_exclusive_scan(int64_t v, int64_t* sh, int64_t& 
   total = sh[kBlock / 64];
   __syncthreads();
   return r;
+}
+
+// The writing pass of the windows k_gen deferred (kCap < n <= 32
+// candidates): one wave per window, one lane per candidate.  Each lane draws
+// its candidate's time once; an accepted candidate's place is the number of
+// accepted ones before it (earlier time, or equal time and earlier draw)
+// plus the kept operators at or before its time; a kept operator's place is
+// its index plus the accepted candidates strictly before it -- the order
+// k_gen writes (a kept operator first at equal times).
+__global__ __launch_bounds__(kBlock) void k_gen_defer(const ChainDesc* __restrict__ descs,
+                                                      const int64_t* __restrict__ win_bases,
+                                                      int nchain, int64_t nwin,
+                                                      const int64_t* __restrict__ opstart,
+                                                      const uint32_t* __restrict__ accmask,
+                                                      uint64_t* __restrict__ optime,
+                                                      uint8_t* __restrict__ optype,
+                                                      const int64_t* __restrict__ defer) {
+  const int lane = lane_id();
+  const int64_t nd = defer[nwin];
+  const int64_t nwave = static_cast<int64_t>(gridDim.x) * kWaves;
+  for (int64_t d = xcd_block() * kWaves + (threadIdx.x >> 6); d < nd; d += nwave) {
+    const int64_t i = defer[d];
+    const int c = chain_of(win_bases, nchain, i);
+    const ChainDesc& D = descs[c];
+    const LC_GLOBAL int64_t* __restrict__ kstart = gin(D.kstart[D.cur]);
+    const LC_GLOBAL uint64_t* __restrict__ ktime = gin(D.ktime[D.cur]);
+    const int64_t li = i - D.win_base;
+    const int64_t b = li >> D.w;
+    const uint64_t k = static_cast<uint64_t>(li & ((int64_t(1) << D.w) - 1));
+    const u32x4 r0 = philox10(D.seed, static_cast<uint32_t>(k), DOM_INS << 24,
+                              static_cast<uint32_t>(b), D.sweep);
+    const uint64_t u = lo64(r0), v0 = hi64(r0);
+    int n = 0;
+    while (n < D.K && u >= D.T[n]) ++n;  // kCap < n <= 32: k_gen deferred it
+    const uint32_t accm = accmask[i];
+    const uint64_t t = lane < n ? cand_time(D, b, k, lane, v0) : 0;
+    const bool acc = lane < n && ((accm >> lane) & 1u);
+    const int64_t kb = kstart[li], ke = kstart[li + 1], base = opstart[i];
+    int64_t rank = 0;
+    for (int l = 0; l < n; ++l) {  // wave-uniform trip count
+      const uint64_t t2 = __shfl(t, l);
+      const bool a2 = (accm >> l) & 1u;
+      rank += (a2 && l != lane && (t2 < t || (t2 == t && l < lane))) ? 1 : 0;
+    }
+    if (acc) {
+      for (int64_t q = kb; q < ke; ++q) rank += ktime[q] <= t ? 1 : 0;
+      optime[base + rank] = t;
+      optype[base + rank] = 0;
+    }
+    for (int64_t q0 = kb; q0 < ke; q0 += 64) {  // kept operators, 64 at a time
+      const int64_t q = q0 + lane;
+      const uint64_t tk = q < ke ? ktime[q] : 0;
+      int64_t rk = q - kb;
+      for (int l = 0; l < n; ++l) {
+        const uint64_t t2 = __shfl(t, l);
+        rk += (((accm >> l) & 1u) && t2 < tk) ? 1 : 0;
+      }
+      if (q < ke) {
+        optime[base + rk] = tk;
+        optype[base + rk] = 3;
+      }
+    }
+  }
 }
 
 // Counting pass of split-spin chains, by tiles.  The antiparallel test of a
@@ -2687,7 +2759,7 @@ hipError_t lc_launch_sweep(const LcSweepArgs& A, hipStream_t s) {
     if (A.groups[gi].two_s > 1 && A.groups[gi].nchain > kGenChains) split_tiles = false;
   hipLaunchKernelGGL((k_gen<false>), dim3(grid_for(A.nwin, G)), dim3(kBlock), 0, s, A.descs,
                      A.win_bases, A.nchain, A.nwin, A.opstart, A.accmask, A.optime, A.optype,
-                     A.op_cap, st, A.flags, split_tiles ? 1 : 0);
+                     A.op_cap, st, A.flags, split_tiles ? 1 : 0, nullptr);
   for (int gi = 0; split_tiles && gi < A.ngroups; ++gi) {
     const LcTileGroup& g = A.groups[gi];
     if (g.two_s > 1)
@@ -2701,9 +2773,16 @@ hipError_t lc_launch_sweep(const LcSweepArgs& A, hipStream_t s) {
                      A.node_cap, st, A.flags);
   // 3. write operators
   mark(LC_PH_GEN_WRITE);
+  // the windows the writing pass defers are listed in kflat (unused until
+  // the flip), their count in kflat[nwin]
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s,
+                     reinterpret_cast<unsigned long long*>(A.kflat + A.nwin), 1, 0ull);
   hipLaunchKernelGGL((k_gen<true>), dim3(grid_for(A.nwin, G)), dim3(kBlock), 0, s, A.descs,
                      A.win_bases, A.nchain, A.nwin, A.opstart, A.accmask, A.optime, A.optype,
-                     A.op_cap, st, A.flags, 0);
+                     A.op_cap, st, A.flags, 0, A.kflat);
+  hipLaunchKernelGGL(k_gen_defer, dim3(G < 2048 ? G : 2048), dim3(kBlock), 0, s, A.descs,
+                     A.win_bases, A.nchain, A.nwin, A.opstart, A.accmask, A.optime, A.optype,
+                     A.kflat);
   // 4. loop graph and union-find: tiles, then the edges between them
   mark(LC_PH_LINK_TILES);
   hipLaunchKernelGGL(k_init_bnodes, dim3(grid_for(A.nbn, G)), dim3(kBlock), 0, s, A.bn_bases,
