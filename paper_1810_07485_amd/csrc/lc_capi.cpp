@@ -1435,15 +1435,20 @@ int lc_export_labels(const lc_chain* c, int64_t* labels, int64_t* n_nodes) {
   if (hipMemcpy(labels, c->last_engine->ar->parent.p + d.node_base, d.n_nodes * sizeof(int64_t),
                 hipMemcpyDeviceToHost) != hipSuccess)
     return LC_EDEVICE;
-  // parent words after a sweep: a node holding a negative word is the
-  // smallest node of its loop (a loop code, or a loop finished inside its
-  // linking tile); any other node's parent p is that smallest node or a
-  // node whose own word is it (non-negative) or a code (p is it).  Words
-  // are read from the copy before any is rewritten.
+  // parent words after a sweep: a node of a loop finished inside its
+  // linking tile holds a code naming the loop's smallest node; a node
+  // holding another negative word (a loop code) is the smallest node of its
+  // loop; any other node's parent p is that smallest node or a node whose
+  // own word is it (non-negative) or a code (p is it).  Words are read from
+  // the copy before any is rewritten.
   std::vector<int64_t> w(labels, labels + d.n_nodes);
   for (int64_t v = 0; v < d.n_nodes; ++v) {
     const int64_t p = w[v];
-    if (p < 0) {
+    if (lc::is_closed_word(p)) {
+      const int64_t r = lc::closed_rep(p) - d.node_base;
+      if (r < 0 || r >= d.n_nodes) return LC_EDEVICE;  // not a node of this chain
+      labels[v] = r;
+    } else if (p < 0) {
       labels[v] = v;
     } else {
       const int64_t pl = p - d.node_base;

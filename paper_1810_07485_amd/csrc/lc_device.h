@@ -13,6 +13,25 @@ enum : uint32_t { DOM_INIT = 0u, DOM_INS = 1u, DOM_FLIP = 2u, DOM_SYM = 3u, DOM_
 
 constexpr int kMaxTable = 64;  // longest Poisson threshold table
 
+// Parent word of every node of a loop finished inside its linking tile: a
+// code below all other words that holds the loop's smallest node (its
+// label) and the loop's flip decision, kClosedRoot + 2 rep + bit.  Other
+// loops' nodes hold a node id (>= 0) or, at their root, the loop code
+// -1 - index (>= -2^62).
+constexpr int64_t kClosedRoot = INT64_MIN;
+__host__ __device__ inline int64_t closed_word(int64_t rep, uint32_t bit) {
+  return static_cast<int64_t>((static_cast<uint64_t>(rep) << 1) + bit + (uint64_t(1) << 63));
+}
+__host__ __device__ inline bool is_closed_word(int64_t w) {
+  return w < kClosedRoot + (int64_t(1) << 62);
+}
+__host__ __device__ inline int64_t closed_rep(int64_t w) {
+  return static_cast<int64_t>((static_cast<uint64_t>(w) - (uint64_t(1) << 63)) >> 1);
+}
+__host__ __device__ inline uint32_t closed_bit(int64_t w) {
+  return static_cast<uint32_t>(static_cast<uint64_t>(w) & 1u);
+}
+
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds, each two
 // 32x32->64 products; the key advances by the Weyl increments between rounds.
 struct u32x4 {

@@ -17,8 +17,7 @@
 // at w = 2 pi / beta its e^{i w beta} = 1 cancels the bottom node's 1).
 // The bottom (tau = 0+) nodes give the equal-time P_c = sum e^{i d j}.
 //
-// Pass: (1) flag the loops' smallest nodes (a negative parent word) and
-// scan them into loop indices; (2) every node adds its terms to its loop's
+// Pass: (1) flag the loops' smallest nodes and scan them into loop indices; (2) every node adds its terms to its loop's
 // record (FP64 atomics); (3) squares summed per loop.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -42,17 +41,26 @@ __device__ inline int64_t loop_of(const FourierCtx& F, int64_t v) {
   const int64_t g = F.node_base + v;
   const int64_t p = F.parent[g];
   int64_t lab = g;
-  if (p >= 0) {
+  if (lc::is_closed_word(p)) {
+    lab = lc::closed_rep(p);
+  } else if (p >= 0) {
     const int64_t pp = F.parent[p];
     lab = pp >= 0 ? pp : p;
   }
   return F.loopidx[lab - F.node_base];
 }
 
+// a loop's smallest node: a loop code, or a finished loop's code naming it
 __global__ __launch_bounds__(kFB) void k_four_flag(LcFourierArgs A) {
   for (int64_t v = static_cast<int64_t>(blockIdx.x) * kFB + threadIdx.x; v <= A.n_nodes;
-       v += static_cast<int64_t>(gridDim.x) * kFB)
-    A.loopidx[v] = v < A.n_nodes && A.parent[A.node_base + v] < 0 ? 1 : 0;
+       v += static_cast<int64_t>(gridDim.x) * kFB) {
+    int64_t f = 0;
+    if (v < A.n_nodes) {
+      const int64_t g = A.node_base + v, p = A.parent[g];
+      f = p < 0 && (!lc::is_closed_word(p) || lc::closed_rep(p) == g) ? 1 : 0;
+    }
+    A.loopidx[v] = f;
+  }
 }
 
 __global__ __launch_bounds__(kFB) void k_four_ops(LcFourierArgs A) {

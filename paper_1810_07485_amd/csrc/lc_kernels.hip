@@ -906,15 +906,15 @@ struct LoopSums {
 // smallest node (rep), its size, and whether it is open (a node with fewer
 // than two local edges: the loop continues outside the tile).  A closed
 // component is a whole loop: the tile finishes it -- loop count, size^2,
-// length^2 into the chain statistics, its rep gets kClosedRoot plus the
-// loop's flip decision (the bit of its label, or the XOR of its nodes'
-// votes under the vote rule) -- without
+// length^2 into the chain statistics, and every node of it gets a code
+// naming its rep and the loop's flip decision (the bit of its label, or the
+// XOR of its nodes' votes under the vote rule) -- without
 // any global work (closed two-node loops directly from the two times, larger
 // ones through an LDS accumulator slot).  An open component is a fragment:
 // its rep, size and length sums go to the fragment list, which is all the
 // later phases see of it.  Every node's parent word is written once,
-// coalesced: its rep (a rep of an open component points to itself).
-constexpr int64_t kClosedRoot = INT64_MIN;  // below every loop code -1 - index
+// coalesced: its rep in an open component (the rep points to itself), the
+// finished loop's code in a closed one.
 constexpr int kTileBonds = LC_TILE_BONDS;
 static_assert(LC_TILE_THREADS == kBlock, "one (subspin, window) walker per thread");
 static_assert(kTileBonds <= 256, "owned bonds are numbered in one byte");
@@ -1556,19 +1556,19 @@ __global__ __launch_bounds__(kBlock) void k_link_tile(
       if (votes ? (vote_bit(D, v) ^ vote_bit(D, v + 1)) : flip_bit(D, v)) S.lpar[u] |= kRepFlip;
     }
     __syncthreads();  // flip decisions of closed components are read below
-    // parent words: the component's rep; a rep holds itself (open) or
-    // kClosedRoot (finished)
+    // parent words: an open component's nodes hold its rep (the rep itself);
+    // a finished loop's nodes hold its code, smallest node and flip decision
+    // (closed_word), so that the flip reads one word per node
     for (int lo = tid; lo < nlo; lo += kBlock) {
       const int64_t q = tile_op(S, static_cast<uint32_t>(lo));
 #pragma unroll
       for (int hh = 0; hh < 2; ++hh) {
         const uint32_t u = static_cast<uint32_t>(2 * lo + hh);
         const uint32_t r = rep_of(static_cast<int>(u));
+        const uint32_t rw = S.lpar[r];
         const int64_t g = nb0 + 2 * q + hh;
-        if (r == u)
-          parent[g] = (S.lpar[u] & kRepOpen) ? g : kClosedRoot + ((S.lpar[u] & kRepFlip) ? 1 : 0);
-        else
-          parent[g] = nb0 + 2 * tile_op(S, r >> 1) + (r & 1);
+        const int64_t gr = r == u ? g : nb0 + 2 * tile_op(S, r >> 1) + (r & 1);
+        parent[g] = (rw & kRepOpen) ? gr : closed_word(gr, (rw & kRepFlip) ? 1u : 0u);
       }
     }
     __syncthreads();  // the LDS is reused by the next tile
@@ -2226,31 +2226,33 @@ __global__ __launch_bounds__(kBlock) void k_cluster_sums(
   sums.flush(stats, nchain);
 }
 
-// Flip decision of the loop through node g, found through the loop's code
-// -- kClosedRoot + decision for a loop finished in its tile, else the
-// record's bit 63 -- from g's word, its rep's, or the root's.  The decision
+// Flip decision of the loop through node g: from g's own word for a loop
+// finished in its tile (closed_word), else the record's bit 63, found
+// through the loop code in g's word, its rep's, or the root's.  The decision
 // was taken once per loop (label rule: the bit of its smallest node; vote
 // rule: the XOR of its nodes' votes).
 __device__ inline uint32_t node_flip(const int64_t* __restrict__ parent,
                                      const unsigned long long* __restrict__ acc, int64_t g) {
   const int64_t p = parent[g];
+  if (is_closed_word(p)) return closed_bit(p);
   int64_t code = p;
   if (p >= 0) {
     const int64_t pp = parent[p];
     code = pp < 0 ? pp : parent[pp];
   }
-  if (code <= kClosedRoot + 1) return static_cast<uint32_t>(code - kClosedRoot);
   return static_cast<uint32_t>(acc[kAccWords * (-1 - code) + 3] >> 63);
 }
 
 // Cluster flip (step 7): the type of an operator changes when exactly one of
 // its two loops flips; kept (off-diagonal) operators are counted per window.
-// The operators are taken tile by tile (the linking tiles: bonds x windows),
-// one workgroup per tile and one thread per operator, so the reads of the
+// A node of a loop finished in its linking tile carries the decision in its
+// own word; other nodes reach their loop's record through the root.  The
+// operators are taken tile by tile (the linking tiles: bonds x windows), one
+// workgroup per tile and one thread per operator, so the reads of the
 // operators' words are coalesced along each bond's run and the lookups of
-// reps (always in the node's own tile) and of the roots of long loops
-// (shared by many nodes) hit lines the workgroup has just read.  Kept
-// operators are counted per window in LDS through an operator -> window map.
+// the roots of long loops (shared by many nodes) hit lines the workgroup has
+// just read.  Kept operators are counted per window in LDS through an
+// operator -> window map.
 constexpr int kFlipWin = LC_TILE_BONDS * LC_MAX_TS;  // windows of a tile: its bonds x windows <= 256 TS
 
 __global__ __launch_bounds__(kBlock) void k_flip_tiles(
