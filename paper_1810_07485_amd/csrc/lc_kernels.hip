@@ -2390,7 +2390,7 @@ __global__ __launch_bounds__(kBlock) void k_flip_sites(
 // They keep the operator array's own (window, operator) order, so this is a
 // stream compaction: a workgroup takes 256 windows, writes their starts, and
 // moves their kept operators with a block scan of the kept flags over the
-// windows' operator range (8 consecutive operators per thread), reading and
+// windows' operator range (8 operators per thread, 256 apart), reading and
 // writing contiguous memory.  Windows of different chains (a batch) are
 // taken chain by chain.
 constexpr int kCompactPer = 8;
@@ -2403,7 +2403,7 @@ __global__ __launch_bounds__(kBlock) void k_compact(const ChainDesc* __restrict_
                                                      const uint8_t* __restrict__ optype,
                                                      const int64_t* __restrict__ kflat,
                                                      uint32_t* __restrict__ flags) {
-  __shared__ int64_t sh[kWaves + 1];
+  __shared__ int wsum[kCompactPer][kWaves];
   __shared__ uint32_t fl;
   // a sweep with any overflow or error is discarded: kflat may be stale
   // (read once per block: blocks of this kernel may raise the kept flag)
@@ -2411,6 +2411,8 @@ __global__ __launch_bounds__(kBlock) void k_compact(const ChainDesc* __restrict_
   __syncthreads();
   if (fl) return;
   const int tid = threadIdx.x;
+  const int lane = lane_id(), wv = tid >> 6;
+  const unsigned long long below = (1ull << lane) - 1ull;
   for (int64_t c0 = xcd_block() * kBlock; c0 < nwin; c0 += static_cast<int64_t>(gridDim.x) * kBlock) {
     const int64_t cend = c0 + kBlock < nwin ? c0 + kBlock : nwin;
     for (int64_t w = c0; w < cend;) {  // block-uniform: the chains of the 256 windows
@@ -2434,24 +2436,35 @@ __global__ __launch_bounds__(kBlock) void k_compact(const ChainDesc* __restrict_
       }
       const int64_t qb = opstart[wend];
       int64_t out = kflat[w] - kb;
+      // operator base + m 256 + tid: every load and store of a wave is one
+      // contiguous run; a kept operator's place is the kept ones of earlier
+      // steps, of earlier waves in its step (LDS), and of lower lanes (ballot)
       for (int64_t base = opstart[w]; base < qb; base += kBlock * kCompactPer) {
-        const int64_t q0 = base + static_cast<int64_t>(tid) * kCompactPer;
-        uint32_t bits = 0;
-        int64_t cnt = 0;
+        unsigned long long bal[kCompactPer];
 #pragma unroll
         for (int m = 0; m < kCompactPer; ++m) {
-          const int64_t q = q0 + m;
-          if (q < qb && (optype[q] & 1)) {
-            bits |= 1u << m;
-            ++cnt;
-          }
+          const int64_t q = base + m * kBlock + tid;
+          bal[m] = __ballot(q < qb && (optype[q] & 1));
+          if (lane == 0) wsum[m][wv] = __popcll(bal[m]);
         }
-        int64_t tot;
-        int64_t o = out + block_exclusive_scan(cnt, sh, tot);
+        __syncthreads();
+        int64_t o = out;
 #pragma unroll
-        for (int m = 0; m < kCompactPer; ++m)
-          if ((bits >> m) & 1u) kt[o++] = optime[q0 + m];
-        out += tot;
+        for (int m = 0; m < kCompactPer; ++m) {
+          int before = 0, all = 0;
+#pragma unroll
+          for (int v = 0; v < kWaves; ++v) {
+            before += v < wv ? wsum[m][v] : 0;
+            all += wsum[m][v];
+          }
+          if ((bal[m] >> lane) & 1ull) {
+            const int64_t q = base + m * kBlock + tid;
+            kt[o + before + __popcll(bal[m] & below)] = optime[q];
+          }
+          o += all;
+        }
+        __syncthreads();  // wsum is rewritten by the next step
+        out = o;
       }
       w = wend;
     }
