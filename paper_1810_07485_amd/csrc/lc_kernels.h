@@ -13,7 +13,7 @@
 #define LC_MAX_TS 8          // 2S of the largest spin (S = 4)
 
 // Linking tiles (bond range x window range of one chain, one workgroup).
-#define LC_TILE_OPS 2048     // operators of an S = 1/2 tile held in LDS
+#define LC_TILE_OPS 1792     // operators of an S = 1/2 tile held in LDS (four workgroups per CU)
 #define LC_TILE_OPS_SPLIT 1536  // operators of a split-spin tile held in LDS
 #define LC_TILE_BONDS 256    // owned bonds of a tile
 #define LC_TILE_THREADS 256  // (subspin, window) walkers of a tile

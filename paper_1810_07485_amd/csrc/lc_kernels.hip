@@ -282,6 +282,34 @@ __device__ inline void chunk_times(const ChainDesc& D, int64_t b, uint64_t k, ui
   }
 }
 
+// Exclusive scan of one value per thread over the block (three barriers).
+__device__ inline int64_t block_exclusive_scan(int64_t v, int64_t* sh, int64_t& total) {
+  // wave inclusive scan
+  const int lane = lane_id(), wv = threadIdx.x >> 6;
+  int64_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sh[wv] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t s = 0;
+    for (int q = 0; q < kBlock / 64; ++q) {
+      const int64_t t = sh[q];
+      sh[q] = s;
+      s += t;
+    }
+    sh[kBlock / 64] = s;
+  }
+  __syncthreads();
+  const int64_t r = sh[wv] + x - v;
+  total = sh[kBlock / 64];
+  __syncthreads();
+  return r;
+}
+
 // ---------------------------------------------------------------------------
 // Insertion of diagonal operators and removal of old ones (steps 2-6):
 // per (bond, window) the Poisson count from one 64-bit draw against the
@@ -289,8 +317,18 @@ __device__ inline void chunk_times(const ChainDesc& D, int64_t b, uint64_t k, ui
 // the merge with the kept operators into the operator list.  The counting
 // pass leaves the acceptance mask of windows with at most 32 candidates in
 // accmask, so the writing pass redraws only the times.
+//
+// A workgroup takes 256 consecutive windows at a time.  In the writing
+// pass the candidate times of its windows with at most kCap candidates are
+// drawn first, block-wide: the Philox calls of all of them are numbered
+// through a block scan and dealt out to the threads in turn, so that every
+// lane draws about the mean number of times (a lane per window would make
+// its wave wait for the window with the most candidates); the times land in
+// LDS, draw j of window w at slot[j][w].  The counting pass draws each
+// window's times in its own lane, in chunks held in registers (measured
+// faster there: it needs no LDS and no barriers).
 template <bool WRITE>
-__global__ __launch_bounds__(kBlock) void k_gen(const ChainDesc* __restrict__ descs,
+__global__ __launch_bounds__(kBlock, WRITE ? 5 : 4) void k_gen(const ChainDesc* __restrict__ descs,
                                                 const int64_t* __restrict__ win_bases, int nchain,
                                                 int64_t nwin, int64_t* __restrict__ opstart,
                                                 uint32_t* __restrict__ accmask,
@@ -299,54 +337,95 @@ __global__ __launch_bounds__(kBlock) void k_gen(const ChainDesc* __restrict__ de
                                                 unsigned long long* __restrict__ stats,
                                                 uint32_t* __restrict__ flags, int skip_split,
                                                 int64_t* __restrict__ defer) {
-  // only the writing pass keeps candidate times (LDS bounds its occupancy)
-  __shared__ uint64_t slot[WRITE ? kCap * kBlock : 1];
+  constexpr int kW = WRITE ? kBlock : 1;
+  __shared__ uint64_t slot[kCap * kW];
+  __shared__ int cfirst[kW + 1];  // first call (block-wide numbering) of each window
+  __shared__ uint8_t ncnt[kW];    // candidates of each window
+  __shared__ int64_t scan[kWaves + 1];
   const int tid = threadIdx.x;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
-  const int64_t start = xcd_block() * kBlock + tid;
   constexpr int kIdx[2] = {ST_CAND, ST_ACC};
   Partial<2> part;
-  for (int64_t i = start; i < nwin; i += stride) {
+  // block-uniform: every thread takes part in the barriers of each step
+  for (int64_t i0 = xcd_block() * kBlock; i0 < nwin; i0 += stride) {
+    const int64_t i = i0 + tid;
     uint32_t ncand = 0, nacc = 0;
-    {
-      const int c = chain_of(win_bases, nchain, i);
+    bool live = i < nwin;
+    int c = 0, n = 0;
+    int64_t b = 0;
+    uint64_t k = 0, u = 0, v0 = 0;
+    if (live) {
+      c = chain_of(win_bases, nchain, i);
       if (!WRITE) part.at(c, stats, nchain, kIdx);
       const ChainDesc& D = descs[c];
-      if (!WRITE && skip_split && D.two_s > 1) continue;  // counted by k_gen_split
+      if (!WRITE && skip_split && D.two_s > 1) {
+        live = false;  // counted by k_gen_split
+      } else {
+        const int64_t li = i - D.win_base;
+        b = li >> D.w;
+        k = static_cast<uint64_t>(li & ((int64_t(1) << D.w) - 1));
+        const u32x4 r0 = philox10(D.seed, static_cast<uint32_t>(k), DOM_INS << 24,
+                                  static_cast<uint32_t>(b), D.sweep);
+        u = lo64(r0);
+        v0 = hi64(r0);
+        while (n < D.K && u >= D.T[n]) ++n;
+        if (WRITE && n > 0 && n <= kCap) slot[tid] = in_window(D, k, v0);
+      }
+    }
+    // the writing pass's candidate times of the windows with n <= kCap: draw
+    // 0 is v0, draws 2i-1 and 2i are the halves of call i (i = 1 .. n/2)
+    const bool inlds = WRITE && live && n <= kCap;
+    if constexpr (WRITE) {
+      int64_t ncall;
+      const int64_t cex = block_exclusive_scan(inlds ? (n >> 1) : 0, scan, ncall);
+      cfirst[tid] = static_cast<int>(cex);
+      ncnt[tid] = static_cast<uint8_t>(inlds ? n : 0);
+      if (tid == 0) cfirst[kBlock] = static_cast<int>(ncall);
+      __syncthreads();
+      for (int q = tid; q < static_cast<int>(ncall); q += kBlock) {
+        int lo = 0, hi = kBlock - 1;  // the last window whose first call is at or before q
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (cfirst[mid] <= q)
+            lo = mid;
+          else
+            hi = mid - 1;
+        }
+        const int64_t iw = i0 + lo;
+        const ChainDesc& D = descs[chain_of(win_bases, nchain, iw)];
+        const int64_t lw = iw - D.win_base;
+        const int64_t bw = lw >> D.w;
+        const uint64_t kw = static_cast<uint64_t>(lw & ((int64_t(1) << D.w) - 1));
+        const int call = q - cfirst[lo] + 1;
+        const u32x4 r = cand_call(D, bw, kw, static_cast<uint32_t>(call));
+        slot[(2 * call - 1) * kBlock + lo] = in_window(D, kw, lo64(r));
+        if (2 * call < ncnt[lo]) slot[2 * call * kBlock + lo] = in_window(D, kw, hi64(r));
+      }
+      __syncthreads();
+    }
+    if (live) {
+      const ChainDesc& D = descs[c];
       const LC_GLOBAL uint8_t* __restrict__ s0 = gin(D.s0[D.cur]);
       const LC_GLOBAL int64_t* __restrict__ kstart = gin(D.kstart[D.cur]);
       const LC_GLOBAL uint64_t* __restrict__ ktime = gin(D.ktime[D.cur]);
       const int64_t li = i - D.win_base;
-      const int64_t b = li >> D.w;
-      const uint64_t k = static_cast<uint64_t>(li & ((int64_t(1) << D.w) - 1));
-      const u32x4 r0 = philox10(D.seed, static_cast<uint32_t>(k), DOM_INS << 24,
-                                static_cast<uint32_t>(b), D.sweep);
-      const uint64_t u = lo64(r0), v0 = hi64(r0);
-      int n = 0;
-      while (n < D.K && u >= D.T[n]) ++n;
       ncand = static_cast<uint32_t>(n);
-      const bool inlds = WRITE && n <= kCap;
       const bool known = WRITE && n <= 32;
       // windows with kCap < n <= 32 are written by k_gen_defer, a wave per
       // window, so that no wave waits on one lane's redraws (0.1 % of the
       // windows at the largest mean count, 4)
       const bool deferred = known && !inlds;
       uint64_t accm = known ? accmask[i] : 0;
-      if (known) {
-        if (inlds) {
-          if (n > 0) slot[tid] = in_window(D, k, v0);
-          for (int j = 1; j < n; j += 2) {  // draws 2i-1, 2i from call i
-            const u32x4 r = cand_call(D, b, k, static_cast<uint32_t>((j + 1) >> 1));
-            slot[j * kBlock + tid] = in_window(D, k, lo64(r));
-            if (j + 1 < n) slot[(j + 1) * kBlock + tid] = in_window(D, k, hi64(r));
-          }
-        }
-      } else {
-        // n > kCap here whenever WRITE, so no candidate goes to LDS
+      if (!known) {
         for (int j0 = 0; j0 < n; j0 += kChunk) {
           const int m = (n - j0 < kChunk) ? n - j0 : kChunk;
           uint64_t tc[kChunk];
-          chunk_times(D, b, k, v0, j0, m, tc);
+          if (inlds) {
+#pragma unroll
+            for (int j = 0; j < kChunk; ++j) tc[j] = j < m ? slot[(j0 + j) * kBlock + tid] : 0;
+          } else {
+            chunk_times(D, b, k, v0, j0, m, tc);
+          }
           accm |= static_cast<uint64_t>(antiparallel_mask(D, s0, kstart, ktime, b, k, tc, m)) << j0;
         }
       }
@@ -397,17 +476,15 @@ __global__ __launch_bounds__(kBlock) void k_gen(const ChainDesc* __restrict__ de
             ++o;
           }
         } else {
-          auto tj = [&](int j) -> uint64_t {
-            return inlds ? slot[j * kBlock + tid] : cand_time(D, b, k, j, v0);
-          };
+          // more than 32 candidates: every time is redrawn where needed;
           // accepted candidates: rank among accepted + kept at or before
           for (int j = 0; j < n; ++j) {
             if (!((accm >> j) & 1)) continue;
-            const uint64_t t = tj(j);
+            const uint64_t t = cand_time(D, b, k, j, v0);
             int64_t rank = 0;
             for (int j2 = 0; j2 < n; ++j2) {
               if (!((accm >> j2) & 1) || j2 == j) continue;
-              const uint64_t t2 = tj(j2);
+              const uint64_t t2 = cand_time(D, b, k, j2, v0);
               rank += (t2 < t || (t2 == t && j2 < j)) ? 1 : 0;
             }
             for (int64_t q = kb; q < ke; ++q) rank += (ktime[q] <= t) ? 1 : 0;
@@ -419,7 +496,7 @@ __global__ __launch_bounds__(kBlock) void k_gen(const ChainDesc* __restrict__ de
             const uint64_t t = ktime[q];
             int64_t rank = q - kb;
             for (int j = 0; j < n; ++j)
-              if ((accm >> j) & 1) rank += (tj(j) < t) ? 1 : 0;
+              if ((accm >> j) & 1) rank += (cand_time(D, b, k, j, v0) < t) ? 1 : 0;
             optime[base + rank] = t;
             optype[base + rank] = 3;
           }
@@ -428,6 +505,7 @@ __global__ __launch_bounds__(kBlock) void k_gen(const ChainDesc* __restrict__ de
     }
     part.v[0] += ncand;
     part.v[1] += nacc;
+    if constexpr (WRITE) __syncthreads();  // slot and cfirst are rewritten by the next step
   }
   if (!WRITE) part.flush(stats, nchain, kIdx);
 }
@@ -488,32 +566,6 @@ __device__ inline uint32_t vote_bit(const ChainDesc& D, int64_t node) {
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kBlock * kScanItems;
 
-__device__ inline int64_t block_exclusive_scan(int64_t v, int64_t* sh, int64_t& total) {
-  // wave inclusive scan
-  const int lane = lane_id(), wv = threadIdx.x >> 6;
-  int64_t x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int64_t y = __shfl_up(x, o);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) sh[wv] = x;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int64_t s = 0;
-    for (int q = 0; q < kBlock / 64; ++q) {
-      const int64_t t = sh[q];
-      sh[q] = s;
-      s += t;
-    }
-    sh[kBlock / 64] = s;
-  }
-  __syncthreads();
-  const int64_t r = sh[wv] + x - v;
-  total = sh[kBlock / 64];
-  __syncthreads();
-  return r;
-}
 
 // The writing pass of the windows k_gen deferred (kCap < n <= 32
 // candidates): one wave per window, one lane per candidate.  Each lane draws
@@ -965,6 +1017,17 @@ struct TileLists {
   int xcur;                  // staging cursor in ltime, after the tile's own operators
 };
 
+// Edges leaving the tile, staged during the walk and written out right
+// after it.  S = 1/2 tiles keep them in the LDS of the accumulator slots,
+// which come into use only later: that keeps four of their workgroups on a
+// CU.  Split-spin tiles walk through lists held in those slots, so their
+// staged edges have LDS of their own.
+template <int TS>
+struct TileCross {
+  int64_t xsrc[TileCfg<TS>::kCross], xdst[TileCfg<TS>::kCross];
+};
+struct TileNone {};
+
 template <int TS>
 struct TileLds {
   using C = TileCfg<TS>;
@@ -982,16 +1045,27 @@ struct TileLds {
       uint32_t slot_vote[C::kSlots];  // XOR of the votes of a slotted component
     };
     TileLists<TS> wl;                 // the walk's event lists (split spins)
+    std::conditional_t<TS == 1, TileCross<TS>, TileNone> xin;  // staged edges (S = 1/2)
   };
+  std::conditional_t<TS == 1, TileNone, TileCross<TS>> xout;   // staged edges (split spins)
+  __device__ TileCross<TS>& cross() {
+    if constexpr (TS == 1)
+      return xin;
+    else
+      return xout;
+  }
   uint32_t tpre[kTileBonds + 1];     // first local operator of each owned bond
   int64_t tos[kTileBonds];           // first (flat) operator of each owned bond in the tile
-  int64_t xsrc[C::kCross], xdst[C::kCross];
   int64_t scan[kWaves + 1];
   int64_t base[2];                   // reserved positions: cross edges, fragments
   int cnt[4];                        // staged cross edges, slots, open slots, fragment cursor
   int ncl;                           // closed components whose flip decision is drawn last
   uint32_t fl;
+  int64_t sflat;                     // S = 1/2: first operator of the bond left of the tile in
+  int sn;                            // its windows, and how many follow it (times in ltime
+                                     // after the tile's own; 0 when owned or not staged)
 };
+static_assert(sizeof(TileLds<1>) <= 40 * 1024, "four S = 1/2 linking workgroups per CU");
 static_assert(sizeof(TileLds<8>) <= 80 * 1024, "two split-spin linking workgroups per CU");
 
 // Time of flat operator e whose tile-local index is li (-1: not the tile's):
@@ -1032,60 +1106,75 @@ __device__ inline void tile_edge(Lds& S, int64_t gu, int lu, int64_t gv, int lv)
   } else {
     const int s = atomicAdd(&S.cnt[0], 1);
     if (s < Lds::C::kCross) {
-      S.xsrc[s] = gu;
-      S.xdst[s] = gv;
+      S.cross().xsrc[s] = gu;
+      S.cross().xdst[s] = gv;
     }
   }
 }
 
-// The walker of subspin x in window k (see above).  nb0: node id of the
-// lower node of flat operator 0 of the chain's numbering (lower(e) = nb0 + 2e).
-// Times of the tile's own operators come from LDS, others from HBM.
-template <int TS>
-__device__ inline void tile_walk(TileLds<TS>& S, const ChainDesc& D, int64_t x, int64_t k,
-                                 int64_t nb0, int64_t node_base, int64_t B0, int nbt,
-                                 const int64_t* __restrict__ opstart,
-                                 const uint64_t* __restrict__ optime) {
-  constexpr int NB = 2 * TS;
+// The walker of spin x in window k of an S = 1/2 tile (see above): a merge
+// of the two time-ordered runs of bonds x - 1 and x in window k.  nb0: node
+// id of the lower node of flat operator 0 of the chain's numbering (lower(e)
+// = nb0 + 2e).  Every time it reads is in LDS -- the tile's own operators,
+// and those of the bond left of the tile in the tile's windows, staged
+// after them (S.sflat, S.sn) -- except the first operator after the window
+// when that lies beyond the tile.  Its global loads are issued in two
+// rounds before the walk, so that no wave waits on memory inside the loop.
+__device__ inline void tile_walk_half(TileLds<1>& S, const ChainDesc& D, int64_t x, int64_t k,
+                                      int64_t nb0, int64_t node_base, int64_t B0, int nbt, int nlo,
+                                      const int64_t* __restrict__ opstart,
+                                      const uint64_t* __restrict__ optime) {
   const int64_t W = int64_t(1) << D.w;
-  const int64_t j = x / TS, a = x - j * TS;
-  const int64_t jl = (j == 0) ? D.L - 1 : j - 1;
-  int64_t bnd[NB], h[NB], e[NB];
-  int hl[NB];  // local index of the head (owned bonds), or -1
-  uint64_t th[NB];
-  bool before = false, any = false;
+  const int64_t jl = (x == 0) ? D.L - 1 : x - 1;
+  const int64_t bnd[2] = {jl, x};
+  // LDS index of the time of flat operator idx on bond s, or -1
+  auto tix = [&](int s, int64_t idx) -> int {
+    const int64_t lb = bnd[s] - B0;
+    if (lb >= 0 && lb < nbt) {
+      const int64_t off = idx - S.tos[lb];
+      return (off >= 0 && off < static_cast<int64_t>(S.tpre[lb + 1] - S.tpre[lb]))
+                 ? static_cast<int>(S.tpre[lb] + off)
+                 : -1;
+    }
+    const int64_t off = idx - S.sflat;
+    return (off >= 0 && off < S.sn) ? nlo + static_cast<int>(off) : -1;
+  };
+  int64_t h[2], e[2], end[2];
+  int hl[2], ht[2];  // node-local index of the head (owned bonds, else -1); its time's LDS index
+  uint64_t th[2], tn[2];
+  bool before = false, any = false, has_next[2];
+  // round 1: the window's run, the bond's first and last operator
+  int64_t first[2];
 #pragma unroll
-  for (int s = 0; s < NB; ++s) {
-    bnd[s] = s < TS ? (jl * TS + s) * TS + a : (j * TS + a) * TS + (s - TS);
+  for (int s = 0; s < 2; ++s) {
     const int64_t i0 = D.win_base + bnd[s] * W;
     h[s] = opstart[i0 + k];
     e[s] = opstart[i0 + k + 1];
-    before = before || opstart[i0] < h[s];
+    first[s] = opstart[i0];
+    end[s] = opstart[i0 + W];
+  }
+  // round 2: the heads' times and the times of the first operators after
+  // the window
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    before = before || first[s] < h[s];
+    any = any || h[s] < e[s];
     const int64_t lb = bnd[s] - B0;
     hl[s] = (lb >= 0 && lb < nbt) ? static_cast<int>(S.tpre[lb] + (h[s] - S.tos[lb])) : -1;
-    th[s] = h[s] < e[s] ? op_time(S.ltime, hl[s], optime, h[s]) : 0;
-    any = any || h[s] < e[s];
+    ht[s] = h[s] < e[s] ? tix(s, h[s]) : -1;
+    th[s] = h[s] < e[s] ? op_time(S.ltime, ht[s], optime, h[s]) : 0;
+    has_next[s] = e[s] < end[s];
+    tn[s] = has_next[s] ? op_time(S.ltime, tix(s, e[s]), optime, e[s]) : 0;
   }
-  if (!any) {
-    if (TS > 1 && k == 0) {  // a subspin without events: bottom joins top
-      bool empty = true;
-#pragma unroll
-      for (int s = 0; s < NB; ++s) {
-        const int64_t i0 = D.win_base + bnd[s] * W;
-        empty = empty && opstart[i0 + W] == opstart[i0];
-      }
-      if (empty) tile_edge(S, node_base + x, -1, node_base + D.n_sites + x, -1);
-    }
-    return;
-  }
+  if (!any) return;
   int64_t prev = -1;
   int lprev = -1;
   for (;;) {
-    int sm = -1, lcur = -1;
+    int sm = -1, lcur = -1, tcur = -1;
     uint64_t tm = 0;
     int64_t bm = 0, cur = 0, em = 0;
 #pragma unroll
-    for (int s = 0; s < NB; ++s) {
+    for (int s = 0; s < 2; ++s) {
       if (h[s] < e[s] && (sm < 0 || th[s] < tm || (th[s] == tm && bnd[s] < bm))) {
         sm = s;
         tm = th[s];
@@ -1093,6 +1182,7 @@ __device__ inline void tile_walk(TileLds<TS>& S, const ChainDesc& D, int64_t x, 
         cur = h[s];
         em = e[s];
         lcur = hl[s];
+        tcur = ht[s];
       }
     }
     if (sm < 0) break;
@@ -1104,34 +1194,31 @@ __device__ inline void tile_walk(TileLds<TS>& S, const ChainDesc& D, int64_t x, 
     }
     prev = cur;
     lprev = lcur;
+    // the run's next operator is the next one in the LDS of its times
     const int64_t nh = cur + 1;
     const int nl = lcur >= 0 ? lcur + 1 : -1;
-    const uint64_t nt = nh < em ? op_time(S.ltime, nl, optime, nh) : 0;
+    const int nt = tcur >= 0 ? tcur + 1 : -1;
+    const uint64_t nth = nh < em ? op_time(S.ltime, nt, optime, nh) : 0;
 #pragma unroll
-    for (int s = 0; s < NB; ++s) {
+    for (int s = 0; s < 2; ++s) {
       if (s == sm) {
         h[s] = nh;
         hl[s] = nl;
-        th[s] = nt;
+        ht[s] = nt;
+        th[s] = nth;
       }
     }
   }
-  // the event after window k on this subspin: the first operator after the
-  // window on each touching bond, earliest in (time, bond) order
+  // the event after window k on this spin: the first operator after the
+  // window on either bond, earliest in (time, bond) order
   int64_t nxt = -1, bn = 0;
-  uint64_t tn = 0;
+  uint64_t tnx = 0;
 #pragma unroll
-  for (int s = 0; s < NB; ++s) {
-    const int64_t i0 = D.win_base + bnd[s] * W;
-    const int64_t idx = e[s];
-    if (idx < opstart[i0 + W]) {
-      const int li = tile_local(S, B0, nbt, bnd[s], idx);
-      const uint64_t t = op_time(S.ltime, li, optime, idx);
-      if (nxt < 0 || t < tn || (t == tn && bnd[s] < bn)) {
-        nxt = idx;
-        tn = t;
-        bn = bnd[s];
-      }
+  for (int s = 0; s < 2; ++s) {
+    if (has_next[s] && (nxt < 0 || tn[s] < tnx || (tn[s] == tnx && bnd[s] < bn))) {
+      nxt = e[s];
+      tnx = tn[s];
+      bn = bnd[s];
     }
   }
   const int64_t gu = nb0 + 2 * prev + 1;
@@ -1140,7 +1227,7 @@ __device__ inline void tile_walk(TileLds<TS>& S, const ChainDesc& D, int64_t x, 
     const int ln = tile_local(S, B0, nbt, bn, nxt);
     tile_edge(S, gu, lu, nb0 + 2 * nxt, ln >= 0 ? 2 * ln : -1);
   } else {
-    tile_edge(S, gu, lu, node_base + (TS == 1 ? x : D.n_sites + x), -1);
+    tile_edge(S, gu, lu, node_base + x, -1);
   }
 }
 
@@ -1385,6 +1472,17 @@ __global__ __launch_bounds__(kBlock) void k_link_tile(
       S.tos[tid] = s;
       cnt = opstart[i0 + nk] - s;
     }
+    // S = 1/2: the operators of the bond left of the tile in its windows,
+    // unless the tile owns that bond (a tile over the whole ring)
+    int64_t xs0 = 0, xs1 = 0;
+    if (TS == 1 && tid == kBlock - 1) {
+      const int64_t bl = (j0 == 0 ? D.L : j0) - 1;
+      if (bl - B0 < 0 || bl - B0 >= nbt) {
+        const int64_t i0 = D.win_base + bl * W + k0;
+        xs0 = opstart[i0];
+        xs1 = opstart[i0 + nk];
+      }
+    }
     int64_t total;
     const int64_t ex = block_exclusive_scan(cnt, S.scan, total);
     if (nbt > kTileBonds || nthr > kBlock || total > C::kOps) {  // block-uniform
@@ -1400,6 +1498,10 @@ __global__ __launch_bounds__(kBlock) void k_link_tile(
       S.cnt[0] = S.cnt[1] = S.cnt[2] = S.cnt[3] = 0;
       S.ncl = 0;
     }
+    if (TS == 1 && tid == kBlock - 1) {  // staged only when the times fit after the tile's own
+      S.sflat = xs0;
+      S.sn = total + (xs1 - xs0) <= C::kOps ? static_cast<int>(xs1 - xs0) : 0;
+    }
     const int nlo = static_cast<int>(total);
     const int nn = 2 * nlo;
     for (int u = tid; u < nn; u += kBlock) S.lpar[u] = static_cast<uint32_t>(u);
@@ -1407,6 +1509,8 @@ __global__ __launch_bounds__(kBlock) void k_link_tile(
     __syncthreads();
     // the tile's operator times, coalesced
     for (int lo = tid; lo < nlo; lo += kBlock) S.ltime[lo] = optime[tile_op(S, static_cast<uint32_t>(lo))];
+    if constexpr (TS == 1)
+      for (int q = tid; q < S.sn; q += kBlock) S.ltime[nlo + q] = optime[S.sflat + q];
     __syncthreads();
     // S = 1/2: a serial walker per (subspin, window) merges two bond runs;
     // split spins merge 2 (2S) runs through the per-subspin event lists
@@ -1418,9 +1522,18 @@ __global__ __launch_bounds__(kBlock) void k_link_tile(
     } else if (tid < nthr) {
       const int xs = tid % nj;
       const int kk = tid / nj;
-      tile_walk<TS>(S, D, j0 + xs, k0 + kk, nb0, dy.node_base, B0, nbt, opstart, optime);
+      tile_walk_half(S, D, j0 + xs, k0 + kk, nb0, dy.node_base, B0, nbt, nlo, opstart, optime);
     }
     __syncthreads();
+    if (S.cnt[0] > C::kCross) {  // block-uniform
+      if (tid == 0) atomicOr(flags, LC_FLAG_TILE);
+      break;
+    }
+    const int nx = S.cnt[0];
+    if (tid == 0) {  // places of the staged cross edges in the edge list
+      S.base[0] = nx ? static_cast<int64_t>(atomicAdd(dyncnt + 0, static_cast<unsigned long long>(nx))) : 0;
+      if (S.base[0] + nx > xcap) atomicOr(flags, LC_FLAG_XEDGE);
+    }
     // full compression in two steps: every root is found by read-only walks
     // first (a halving write landing after another thread's final write
     // would leave a node below a non-root), then written; a rep's word
@@ -1435,6 +1548,15 @@ __global__ __launch_bounds__(kBlock) void k_link_tile(
       roots[i] = r;
     }
     __syncthreads();
+    // the staged cross edges go out before the slots (which may share
+    // their LDS) come into use
+    for (int i = tid; i < nx; i += kBlock) {
+      const int64_t g = S.base[0] + i;
+      if (g < xcap) {
+        xedge[2 * g] = S.cross().xsrc[i];
+        xedge[2 * g + 1] = S.cross().xdst[i];
+      }
+    }
 #pragma unroll
     for (int i = 0; i < (kNodes + kBlock - 1) / kBlock; ++i) {
       const int u = tid + i * kBlock;
@@ -1476,7 +1598,7 @@ __global__ __launch_bounds__(kBlock) void k_link_tile(
       }
     }
     __syncthreads();
-    if (S.cnt[0] > C::kCross || S.cnt[1] > C::kSlots) {  // block-uniform
+    if (S.cnt[1] > C::kSlots) {  // block-uniform
       if (tid == 0) atomicOr(flags, LC_FLAG_TILE);
       break;
     }
@@ -1500,21 +1622,11 @@ __global__ __launch_bounds__(kBlock) void k_link_tile(
       }
     }
     if (tid == 0) {
-      const int nx = S.cnt[0], nf = S.cnt[2];
-      S.base[0] = nx ? static_cast<int64_t>(atomicAdd(dyncnt + 0, static_cast<unsigned long long>(nx))) : 0;
+      const int nf = S.cnt[2];
       S.base[1] = nf ? static_cast<int64_t>(atomicAdd(dyncnt + 1, static_cast<unsigned long long>(nf))) : 0;
-      if (S.base[0] + nx > xcap) atomicOr(flags, LC_FLAG_XEDGE);
       if (S.base[1] + nf > fcap) atomicOr(flags, LC_FLAG_FRAG);
     }
     __syncthreads();
-    const int nx = S.cnt[0];
-    for (int i = tid; i < nx; i += kBlock) {
-      const int64_t g = S.base[0] + i;
-      if (g < xcap) {
-        xedge[2 * g] = S.xsrc[i];
-        xedge[2 * g + 1] = S.xdst[i];
-      }
-    }
     // closed components are finished here; open ones become fragments
     const int ns = S.cnt[1];
     for (int s = tid; s < ns; s += kBlock) {

@@ -140,7 +140,7 @@ def test_largest_window_count(lc, orc):
 
 @pytest.mark.parametrize("L,S,beta,seed,shape", [
     (1024, 0.5, 256.0, 3, (1, 300)),     # one window per tile, small tiles
-    (1024, 0.5, 256.0, 3, (16, 2000)),   # sixteen windows per tile
+    (1024, 0.5, 256.0, 3, (16, 1700)),   # sixteen windows per tile
     (1024, 0.5, 256.0, 3, (2, 64)),      # the smallest target
     (64, 0.5, 64.0, 6, (8, 1500)),
     (8, 1.0, 16.5, 4, (2, 200)),         # split spins, two windows per tile
