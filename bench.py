@@ -133,7 +133,7 @@ PHASE_KERNELS = {
     "gen_count": ["k_gen<false>", "k_gen_split"], "gen_write": ["k_gen<true>", "k_gen_defer"],
     "link_tiles": ["k_init_bnodes", "k_link_tile<1>"], "link_cross": ["k_link_cross"],
     "compress": ["k_compress_items"], "roots": ["k_roots_items"], "accum": ["k_accum_items", "k_accum_hash"],
-    "cluster_sums": ["k_cluster_sums"], "flip": ["k_flip_tiles", "k_flip_sites"],
+    "cluster_sums": ["k_cluster_sums"], "flip": ["k_flip_tiles<256>", "k_flip_sites"],
     "compact": ["k_compact"],
 }
 TRAFFIC_FILES = {"medium": os.path.join(ROOT, "profiles", "hbm_traffic_L65536_beta4096.txt"),

@@ -2367,14 +2367,18 @@ __device__ inline uint32_t node_flip(const int64_t* __restrict__ parent,
 // operator -> window map.
 constexpr int kFlipWin = LC_TILE_BONDS * LC_MAX_TS;  // windows of a tile: its bonds x windows <= 256 TS
 
+// NWIN: windows a tile may hold -- kBlock for S = 1/2 (one walker per
+// window), kFlipWin for split spins; the smaller LDS keeps more
+// workgroups of the S = 1/2 flip on a CU.
+template <int NWIN>
 __global__ __launch_bounds__(kBlock) void k_flip_tiles(
     const ChainDesc* __restrict__ descs, const ChainDyn* __restrict__ dyn, int nchain,
     const int* __restrict__ grp_chain, const int64_t* __restrict__ grp_tile_base, int ngrp,
     int64_t ntiles, const int64_t* __restrict__ opstart, const int64_t* __restrict__ parent,
     const unsigned long long* __restrict__ acc, uint8_t* __restrict__ optype,
     int64_t* __restrict__ kcnt, unsigned long long* __restrict__ stats, uint32_t* __restrict__ flags) {
-  __shared__ uint32_t wstart[kFlipWin + 1];   // first local operator of each window
-  __shared__ uint32_t wkept[kFlipWin];
+  __shared__ uint32_t wstart[NWIN + 1];   // first local operator of each window
+  __shared__ uint32_t wkept[NWIN];
   __shared__ uint16_t wop[LC_TILE_OPS];       // window of each local operator
   __shared__ int64_t bfirst[kTileBonds];      // first flat operator of each bond's run
   __shared__ int64_t scan[kWaves + 1];
@@ -2403,7 +2407,7 @@ __global__ __launch_bounds__(kBlock) void k_flip_tiles(
     const int nwt = nbt * nk;
     const int64_t nb0 = dy.node_base + D.nbn - 2 * dy.op_base;
     // the linking of these tiles succeeded, so they fit; checked all the same
-    if (nbt > kTileBonds || nwt > kFlipWin) {  // block-uniform
+    if (nbt > kTileBonds || nwt > NWIN) {  // block-uniform
       if (tid == 0) atomicOr(flags, LC_FLAG_TILE);
       break;
     }
@@ -2961,7 +2965,8 @@ hipError_t lc_launch_sweep(const LcSweepArgs& A, hipStream_t s) {
   for (int gi = 0; gi < A.ngroups; ++gi) {
     const LcTileGroup& g = A.groups[gi];
     const int grid = static_cast<int>(g.ntiles < G ? (g.ntiles > 0 ? g.ntiles : 1) : G);
-    hipLaunchKernelGGL(k_flip_tiles, dim3(grid), dim3(kBlock), 0, s, A.descs, A.dyn, A.nchain,
+    hipLaunchKernelGGL(g.two_s == 1 ? k_flip_tiles<kBlock> : k_flip_tiles<kFlipWin>, dim3(grid),
+                       dim3(kBlock), 0, s, A.descs, A.dyn, A.nchain,
                        A.grp_chain + g.offset, A.grp_tile_base + g.offset, g.nchain, g.ntiles,
                        A.opstart, A.parent, A.acc, A.optype, A.kflat, st, A.flags);
   }
