@@ -1035,7 +1035,11 @@ struct TileLds {
   static_assert(C::kSlots < static_cast<int>(kRepSlotMask), "slot field");
   static_assert(C::kNodes / 2 <= 2 * C::kOps, "closed-component list fits the times' LDS");
   uint32_t lpar[C::kNodes];          // local forest, then reps and their fields
-  uint32_t deg[C::kNodes / 16];      // 2-bit counts of the edges of each node inside the tile
+  // split spins: 2-bit counts of the edges of each node inside the tile;
+  // S = 1/2: one bit per node, set when the node has an edge leaving the
+  // tile (open_mark)
+  static constexpr bool kOpenBits = TS == 1;
+  uint32_t deg[C::kNodes / 16];
   uint64_t ltime[C::kOps];           // times of the tile's operators
   uint8_t lbond[C::kOps];            // owned bond (local index) of each tile operator
   union {
@@ -1097,13 +1101,25 @@ __device__ inline int64_t tile_op(const Lds& S, uint32_t lo) {
 }
 
 // An edge between nodes (gu, gv); lu, lv their local indices or -1.
+// S = 1/2 tiles: local node u has an edge that leaves the tile.
+template <class Lds>
+__device__ inline void open_mark(Lds& S, int u) {
+  atomicOr(S.deg + (u >> 5), 1u << (u & 31));
+}
+
 template <class Lds>
 __device__ inline void tile_edge(Lds& S, int64_t gu, int lu, int64_t gv, int lv) {
   if (lu >= 0 && lv >= 0) {
-    atomicAdd(S.deg + (lu >> 4), 1u << ((lu & 15) * 2));
-    atomicAdd(S.deg + (lv >> 4), 1u << ((lv & 15) * 2));
+    if constexpr (!Lds::kOpenBits) {
+      atomicAdd(S.deg + (lu >> 4), 1u << ((lu & 15) * 2));
+      atomicAdd(S.deg + (lv >> 4), 1u << ((lv & 15) * 2));
+    }
     lunion(S.lpar, static_cast<uint32_t>(lu), static_cast<uint32_t>(lv));
   } else {
+    if constexpr (Lds::kOpenBits) {
+      if (lu >= 0) open_mark(S, lu);
+      if (lv >= 0) open_mark(S, lv);
+    }
     const int s = atomicAdd(&S.cnt[0], 1);
     if (s < Lds::C::kCross) {
       S.cross().xsrc[s] = gu;
@@ -1167,6 +1183,15 @@ __device__ inline void tile_walk_half(TileLds<1>& S, const ChainDesc& D, int64_t
     tn[s] = has_next[s] ? op_time(S.ltime, tix(s, e[s]), optime, e[s]) : 0;
   }
   if (!any) return;
+  // the first event's predecessor lies before the tile's first window when
+  // neither bond has an operator in the tile's windows before this one: its
+  // edge is another tile's, and the first event's lower node is open
+  bool ext = before;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const int64_t lb = bnd[s] - B0;
+    ext = ext && h[s] == ((lb >= 0 && lb < nbt) ? S.tos[lb] : S.sflat);
+  }
   int64_t prev = -1;
   int lprev = -1;
   for (;;) {
@@ -1188,7 +1213,10 @@ __device__ inline void tile_walk_half(TileLds<1>& S, const ChainDesc& D, int64_t
     if (sm < 0) break;
     const int64_t gl = nb0 + 2 * cur;
     if (prev < 0) {
-      if (!before) tile_edge(S, node_base + x, -1, gl, lcur >= 0 ? 2 * lcur : -1);
+      if (!before)
+        tile_edge(S, node_base + x, -1, gl, lcur >= 0 ? 2 * lcur : -1);
+      else if (ext && lcur >= 0)
+        open_mark(S, 2 * lcur);
     } else {
       tile_edge(S, nb0 + 2 * prev + 1, lprev >= 0 ? 2 * lprev + 1 : -1, gl, lcur >= 0 ? 2 * lcur : -1);
     }
@@ -1519,10 +1547,18 @@ __global__ __launch_bounds__(kBlock) void k_link_tile(
         if (tid == 0) atomicOr(flags, LC_FLAG_TILE);  // block-uniform: the tile is too large
         break;
       }
-    } else if (tid < nthr) {
-      const int xs = tid % nj;
-      const int kk = tid / nj;
-      tile_walk_half(S, D, j0 + xs, k0 + kk, nb0, dy.node_base, B0, nbt, nlo, opstart, optime);
+    } else {
+      // the nodes of the last bond's operators have their edges at the spin
+      // right of the tile, which another tile walks: they are open (unless
+      // the tile spans the ring)
+      if (nj < D.L)
+        for (int lo = static_cast<int>(S.tpre[nbt - 1]) + tid; lo < nlo; lo += kBlock)
+          atomicOr(S.deg + ((2 * lo) >> 5), 3u << ((2 * lo) & 31));
+      if (tid < nthr) {
+        const int xs = tid % nj;
+        const int kk = tid / nj;
+        tile_walk_half(S, D, j0 + xs, k0 + kk, nb0, dy.node_base, B0, nbt, nlo, opstart, optime);
+      }
     }
     __syncthreads();
     if (S.cnt[0] > C::kCross) {  // block-uniform
@@ -1570,9 +1606,10 @@ __global__ __launch_bounds__(kBlock) void k_link_tile(
     // component sizes; components with a node lacking a local edge are open
     for (int u = tid; u < nn; u += kBlock) {
       const uint32_t r = rep_of(u);
-      const uint32_t deg = (S.deg[u >> 4] >> ((u & 15) * 2)) & 3u;
+      const bool open = TileLds<TS>::kOpenBits ? ((S.deg[u >> 5] >> (u & 31)) & 1u) != 0
+                                                : ((S.deg[u >> 4] >> ((u & 15) * 2)) & 3u) < 2;
       atomicAdd(S.lpar + r, 1u);
-      if (deg < 2) atomicOr(S.lpar + r, kRepOpen);
+      if (open) atomicOr(S.lpar + r, kRepOpen);
     }
     __syncthreads();
     // closed two-node loops are finished from their two times; every other
