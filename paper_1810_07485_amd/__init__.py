@@ -99,6 +99,11 @@ def load():
     if not os.path.exists(SO):
         raise RuntimeError(f"{SO} is missing: run paper_1810_07485_amd/build.py (or "
                            "__graft_entry__.build()) first; there is no fallback path")
+    # torch first: its bundled HIP runtime is then the one the library binds
+    # to.  Loaded the other way round, the process would hold two HIP
+    # runtimes, and torch's device memory and streams would be foreign to
+    # the library's (every call fails with LC_EDEVICE).
+    import torch  # noqa: F401
     L = C.CDLL(SO)
     p64, pu64, pu8, pi = (C.POINTER(C.c_int64), C.POINTER(C.c_uint64), C.POINTER(C.c_uint8),
                           C.POINTER(C.c_int))

@@ -2229,7 +2229,7 @@ __device__ inline void flush_carry(unsigned long long* acc, int64_t key, uint64_
 // of one hot loop across its steps.  Taken when every chain has S = 1/2:
 // there a 1,024-item chunk holds few more repeats of a loop than a wave
 // does, and this kernel, free of barriers and LDS, issues fewer atomics.
-__global__ __launch_bounds__(kBlock) void k_accum_items(
+__global__ __launch_bounds__(kBlock, 6) void k_accum_items(
     const ChainDesc* __restrict__ descs, const int64_t* __restrict__ frag,
     const unsigned long long* __restrict__ dyncnt, int64_t fcap, const int64_t* __restrict__ bn_bases,
     int nchain, int64_t nbn, const ChainDyn* __restrict__ dyn, const int64_t* __restrict__ parent,
