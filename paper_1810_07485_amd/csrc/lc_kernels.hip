@@ -2392,6 +2392,34 @@ __device__ inline uint32_t node_flip(const int64_t* __restrict__ parent,
   return static_cast<uint32_t>(acc[kAccWords * (-1 - code) + 3] >> 63);
 }
 
+// The XOR of the flip decisions of an operator's two nodes, g (lower, even)
+// and g + 1: node_flip for both, each step's reads of the two nodes issued
+// together (one 16-byte read of the two words, then the reps' words, the
+// roots' words, the loop records), so that a wave waits on one chain of
+// dependent reads per operator instead of two.
+__device__ inline uint32_t pair_flip(const int64_t* __restrict__ parent,
+                                     const unsigned long long* __restrict__ acc, int64_t g) {
+  const longlong2 w = *reinterpret_cast<const longlong2*>(parent + g);
+  const int64_t x0 = w.x, x1 = w.y;
+  const bool c0 = is_closed_word(x0), c1 = is_closed_word(x1);
+  // an open node's word is its rep (>= 0) or, for a root, its loop code (< 0)
+  int64_t y0 = x0, y1 = x1;
+  if (!c0 && x0 >= 0) y0 = parent[x0];
+  if (!c1 && x1 >= 0) y1 = parent[x1];
+  // the rep's word: its root (>= 0) or its loop code
+  int64_t z0 = y0, z1 = y1;
+  if (!c0 && y0 >= 0) z0 = parent[y0];
+  if (!c1 && y1 >= 0) z1 = parent[y1];
+  // the loop records' flip bits (bit 63 of word 3), both read at once: a
+  // closed node reads record 0 instead (the records always outnumber the
+  // boundary nodes, so there is one) and ignores it
+  const int64_t k0 = c0 ? 0 : -1 - z0, k1 = c1 ? 0 : -1 - z1;
+  const unsigned long long r0 = acc[kAccWords * k0 + 3], r1 = acc[kAccWords * k1 + 3];
+  const uint32_t f0 = c0 ? closed_bit(x0) : static_cast<uint32_t>(r0 >> 63);
+  const uint32_t f1 = c1 ? closed_bit(x1) : static_cast<uint32_t>(r1 >> 63);
+  return f0 ^ f1;
+}
+
 // Cluster flip (step 7): the type of an operator changes when exactly one of
 // its two loops flips; kept (off-diagonal) operators are counted per window.
 // A node of a loop finished in its linking tile carries the decision in its
@@ -2490,7 +2518,7 @@ __global__ __launch_bounds__(kBlock) void k_flip_tiles(
       const int64_t q = bfirst[lb] + (lo - static_cast<int64_t>(wstart[lb * nk]));
       const int64_t g = nb0 + 2 * q;
       const uint8_t v = optype[q];
-      const uint8_t ty = static_cast<uint8_t>((v & 1) ^ node_flip(parent, acc, g) ^ node_flip(parent, acc, g + 1));
+      const uint8_t ty = static_cast<uint8_t>((v & 1) ^ pair_flip(parent, acc, g));
       optype[q] = static_cast<uint8_t>(ty | (v & 2));
       if (ty) atomicAdd(wkept + wi, 1u);
     }
