@@ -1135,7 +1135,7 @@ __device__ inline void tile_edge(Lds& S, int64_t gu, int lu, int64_t gv, int lv)
 // and those of the bond left of the tile in the tile's windows, staged
 // after them (S.sflat, S.sn) -- except the first operator after the window
 // when that lies beyond the tile.  Its global loads are issued in two
-// rounds before the walk, so that no wave waits on memory inside the loop.
+// batches before the walk, so that no wave waits on memory inside the loop.
 __device__ inline void tile_walk_half(TileLds<1>& S, const ChainDesc& D, int64_t x, int64_t k,
                                       int64_t nb0, int64_t node_base, int64_t B0, int nbt, int nlo,
                                       const int64_t* __restrict__ opstart,
@@ -1159,7 +1159,7 @@ __device__ inline void tile_walk_half(TileLds<1>& S, const ChainDesc& D, int64_t
   int hl[2], ht[2];  // node-local index of the head (owned bonds, else -1); its time's LDS index
   uint64_t th[2], tn[2];
   bool before = false, any = false, has_next[2];
-  // round 1: the window's run, the bond's first and last operator
+  // first batch: the window's run, the bond's first and last operator
   int64_t first[2];
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
@@ -1169,7 +1169,7 @@ __device__ inline void tile_walk_half(TileLds<1>& S, const ChainDesc& D, int64_t
     first[s] = opstart[i0];
     end[s] = opstart[i0 + W];
   }
-  // round 2: the heads' times and the times of the first operators after
+  // second batch: the heads' times and the times of the first operators after
   // the window
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
