@@ -35,9 +35,43 @@ __device__ inline int64_t uf_find(int64_t* parent, int64_t x, int64_t n) {
   return x;
 }
 
+// uf_find of a and of b at once: the two walks advance one step at a time
+// together, so that their reads of parent words are in flight at the same
+// time (a union waits on the longer walk, not on the sum of the two).
+__device__ inline void uf_find2(int64_t* parent, int64_t& a, int64_t& b, int64_t n) {
+  const bool oka = a >= 0 && a < n, okb = b >= 0 && b < n;
+  int64_t pa = oka ? parent[a] : -1, pb = okb ? parent[b] : -1;
+  if (!oka) a = -1;
+  if (!okb) b = -1;
+  bool da = !oka || pa == a, db = !okb || pb == b;
+  while (!da || !db) {
+    if (!da && (pa < 0 || pa >= n)) {
+      a = -1;
+      da = true;
+    }
+    if (!db && (pb < 0 || pb >= n)) {
+      b = -1;
+      db = true;
+    }
+    const int64_t ga = da ? pa : parent[pa];
+    const int64_t gb = db ? pb : parent[pb];
+    if (!da) {
+      if (ga != pa && ga >= 0 && ga < n) parent[a] = ga;  // path halving
+      a = pa;
+      pa = ga;
+      da = pa == a;
+    }
+    if (!db) {
+      if (gb != pb && gb >= 0 && gb < n) parent[b] = gb;
+      b = pb;
+      pb = gb;
+      db = pb == b;
+    }
+  }
+}
+
 __device__ inline void uf_union(int64_t* parent, int64_t a, int64_t b, int64_t n, uint32_t* flags) {
-  a = uf_find(parent, a, n);
-  b = uf_find(parent, b, n);
+  uf_find2(parent, a, b, n);
   while (a != b) {
     if (a < 0 || b < 0) {
       atomicOr(flags, LC_FLAG_GRAPH);
@@ -53,8 +87,8 @@ __device__ inline void uf_union(int64_t* parent, int64_t a, int64_t b, int64_t n
         atomicCAS(reinterpret_cast<unsigned long long*>(parent + a), static_cast<unsigned long long>(a),
                   static_cast<unsigned long long>(b));
     if (static_cast<int64_t>(old) == a) return;
-    a = uf_find(parent, static_cast<int64_t>(old), n);
-    b = uf_find(parent, b, n);
+    a = static_cast<int64_t>(old);
+    uf_find2(parent, a, b, n);
   }
 }
 
