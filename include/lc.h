@@ -320,7 +320,7 @@ int lc_autotune(lc_chain *c, const int *grids, int n_grids, int trial_sweeps, in
  * loop graph is linked and union-found in tiles of spins x windows, local
  * first, then globally (Secs. 3.1-3.2); a tile takes at most max_windows
  * windows per bond (a power of two up to 16; 0: 8 for S = 1/2, 1 for split
- * spins) and about target_ops operators (64..2,048; 0: 1,500 for
+ * spins) and about target_ops operators (64..1,792; 0: 1,500 for
  * S = 1/2, 1,400 for split spins), within the LDS capacities.  LC_EINVAL
  * otherwise.  lc_autotune_tiles / lc_batch_autotune_tiles time every shape
  * i (windows[i], targets[i]) with every grid as lc_autotune does (the
