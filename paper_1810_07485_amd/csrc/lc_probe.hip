@@ -1,5 +1,5 @@
 // lc_probe.hip -- measurement probes that set the ceilings the loop-cluster
-// kernels are judged against on this device: a device-to-device streaming
+// kernels are measured against on this device: a device-to-device streaming
 // copy (HBM bandwidth) and random 8-byte compare-and-swap on a word array
 // (the access pattern of a lock-free union-find hook, Sec. 3.2), once on an
 // array far larger than the caches and once on one that stays in L2.
