@@ -3014,7 +3014,9 @@ hipError_t lc_launch_sweep(const LcSweepArgs& A, hipStream_t s) {
                      reinterpret_cast<unsigned long long*>(A.rcnt), A.flags);
   mark(LC_PH_ROOTS);
   (void)lc_launch_scan(A.rcnt, nchunks, A.scan_tmp, s);
-  hipLaunchKernelGGL(k_roots_items, dim3(grid_for(nchunks, G)), dim3(kBlock), 0, s, A.descs,
+  // a workgroup numbers one chunk of kRootChunk items at a time
+  const int groots = static_cast<int>(nchunks < G ? (nchunks > 0 ? nchunks : 1) : G);
+  hipLaunchKernelGGL(k_roots_items, dim3(groots), dim3(kBlock), 0, s, A.descs,
                      A.frag, A.dyncnt, A.fcap, A.bn_bases, A.nchain, A.nbn, A.dyn, A.parent, A.acc,
                      A.bacc, A.root_cap, nchunks, A.rcnt, st, A.flags);
   // 6. estimators of the open loops, flips
