@@ -50,6 +50,22 @@ def test_python_binding_loads(lib):
     assert lib.lc_strerror(-1) == "invalid argument"
 
 
+def test_binding_shares_torchs_hip_runtime():
+    """The binding loads torch before the library, so the process maps one
+    HIP runtime (torch's), even when the library is loaded before the user
+    imports torch.  Two runtimes would make torch's device memory and streams
+    foreign to the library.  Checked in a fresh process from its memory map."""
+    import subprocess
+    import sys
+    code = ("import paper_1810_07485_amd as lc; lc.load(); import torch; "
+            "m = [l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l]; "
+            "print(len(set(m)))")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                       timeout=600)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert r.stdout.strip().splitlines()[-1] == "1", r.stdout
+
+
 KAT = [
     ((0, 0, 0, 0), 0, (0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8)),
     ((0xFFFFFFFF,) * 4, 0xFFFFFFFFFFFFFFFF, (0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD)),
