@@ -216,7 +216,7 @@ def bench_batch(args, lc):
 
     inst = workloads.batch_instances()
     chains = [lc.Chain(i.L, i.S, i.beta, i.seed) for i in inst]
-    budget = 48 << 30
+    budget = int(args.batch_budget_gib) << 30
 
     def plain_pass(cs=chains):
         for c in cs:
@@ -469,6 +469,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 2 GiB device to device three times (reference kernel for "
                          "the HBM byte counters) and exit")
+    ap.add_argument("--batch-budget-gib", type=int, default=128,
+                    help="--workload batch: per-sweep scratch budget of a footprint-packed group")
     ap.add_argument("--serve-jobs", type=int, default=24)
     ap.add_argument("--serve-sweep-scale", type=float, default=0.1)
     args = ap.parse_args()
